@@ -1,0 +1,239 @@
+/*
+ * chfsi.h -- C ABI of libchfsi: Chebyshev-filtered subspace iteration on the
+ * spectral finite-element Kohn-Sham Hamiltonian, on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method is the eigensolver of DFT-FE 1.0 (Das, Motamarri, Subramanian,
+ * Rogers, Gavini, arXiv 2203.07820): the Chebyshev filter of Section 3.1
+ * (Eq. chebyfilter), whose every step is the cell-wise product H~.X of
+ * Section 4.3 (Eq. celldgemm, Algorithm 4 for the nonlocal part), followed by
+ * the Cholesky-Gram-Schmidt orthonormalisation and Rayleigh-Ritz steps of
+ * Algorithm 2.  H~ = M^-1/2 H M^-1/2 is the Loewdin-transformed discrete
+ * Hamiltonian of Section 2.3 (discrete H^loc and H^nl equations, GLL-lumped
+ * overlap M).
+ *
+ * Conventions
+ * -----------
+ * - Every function returns an int status: 0 on success, a negative error
+ *   code, or a positive warning.  The text of the last error is available
+ *   from chfsi_last_error().  No C++ exception crosses this boundary.
+ * - Arrays documented "device" are device pointers on the context's GPU
+ *   (for instance torch.Tensor.data_ptr() of a CUDA tensor); all other
+ *   array arguments are host pointers.
+ * - Blocks of vectors are row-major M x ld arrays: row j holds the values of
+ *   node j for all columns (all B values of one node are contiguous, the
+ *   node-major layout of Section 4.3), ld >= ncols.  Complex data
+ *   (CHFSI_C128 / CHFSI_C64) is interleaved (re, im) and ld counts complex
+ *   entries.
+ * - Ownership: the caller owns every array it passes.  The library never
+ *   frees a caller pointer and does not keep it after the call returns,
+ *   except while work it enqueued on the context's stream is in flight.
+ *   Operators own their device tables until chfsi_op_destroy().  The context
+ *   owns its scratch memory, which only grows, until chfsi_ctx_destroy().
+ * - Work is enqueued on the stream given to chfsi_ctx_create().  Functions
+ *   documented "synchronous" wait for that stream before returning.
+ * - A context and its operators are not thread-safe: use one thread per
+ *   context.
+ * - Invalid arguments (null required pointers, ld < ncols, ncols > M, an
+ *   order outside [2, 7], a precision that does not match the operator,
+ *   a > b or aL >= a for the filter) return CHFSI_EINVAL before any work is
+ *   enqueued.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CHFSI_OK         0
+#define CHFSI_NOTCONV    1   /* warning: tolerance not met; results valid   */
+#define CHFSI_EINVAL    (-1) /* invalid argument                            */
+#define CHFSI_ENOMEM    (-2) /* device allocation failed                    */
+#define CHFSI_EHIP      (-3) /* HIP runtime or library error                */
+#define CHFSI_ECHOL     (-4) /* overlap matrix not positive definite        */
+#define CHFSI_EDIVERGE  (-5) /* non-finite values (e.g. b below lambda_max) */
+
+/* ---- arithmetic / storage precision ------------------------------------ */
+typedef enum {
+  CHFSI_F64  = 0, /* real double                                           */
+  CHFSI_F32  = 1, /* real float                                            */
+  CHFSI_BF16 = 2, /* real: float storage, cell products on bf16-rounded
+                     inputs (round to nearest even) with float accumulation */
+  CHFSI_C128 = 3, /* complex double (Bloch k != 0)                          */
+  CHFSI_C64  = 4  /* complex float                                         */
+} chfsi_prec;
+
+typedef struct chfsi_ctx chfsi_ctx;
+typedef struct chfsi_op chfsi_op;
+
+/* A periodic cube [0, L)^3 of ncell^3 hexahedral cells of order p, with
+ * Gaussian atoms (Section 2.3 discretisation; synthetic stand-ins for the
+ * pseudopotential atoms of Section 5).
+ *   V(x)   = sum_a sum_images -Z_a exp(-|x - R_a - nL|^2 / (2 s_a^2)),
+ *            image terms within 10 s_a;
+ *   chi_s  = n_s exp(-r^2/(2 w^2)), chi_p,alpha = n_p r_alpha exp(...),
+ *            unit L2 norm, zero beyond r = 6 w, couplings h_s and h_p
+ *            (separable form of Eq. nlps / nonlocalHamDiscrete);
+ *   k      = Bloch vector (Eq. contEigenBZ); k = 0 gives a real operator.
+ * pos has 3*natoms entries (x, y, z per atom).  w, h_s, h_p are read only
+ * when has_proj != 0.  All arrays are host arrays copied by the call. */
+typedef struct {
+  double L;
+  int32_t ncell;
+  int32_t p;
+  int32_t natoms;
+  int32_t has_proj;
+  const double* pos;
+  const double* Z;
+  const double* s;
+  const double* w;
+  const double* h_s;
+  const double* h_p;
+  double k[3];
+} chfsi_system;
+
+/* Parameters of chfsi_solve().
+ *   nwanted        N: number of wanted eigenpairs;
+ *   n_buf          extra buffer columns filtered with the wanted ones
+ *                  (X has N + n_buf columns);
+ *   m              Chebyshev degree;
+ *   block          column block B filtered at a time (Section 4.3 blocked
+ *                  H~.X);
+ *   fixed_passes   > 0: run exactly this many passes; else iterate until
+ *                  max_{i<N} r_i <= tol or max_passes;
+ *   filter_prec    arithmetic of the filter: F64, F32 or BF16 for a real
+ *                  operator, C128 or C64 for a complex one.  Orthonormalis-
+ *                  ation, Rayleigh-Ritz and residuals are always FP64;
+ *   lanczos_steps  steps of the Lanczos run that gives the upper bound b;
+ *   b_upper        > 0: use this bound instead of running Lanczos;
+ *   lanczos_v0     optional host vector (M real or 2M interleaved complex
+ *                  values) that starts Lanczos; NULL draws one from seed;
+ *   seed           seed of the library's own generator (splitmix64 +
+ *                  Box-Muller) when lanczos_v0 is NULL. */
+typedef struct {
+  int32_t nwanted;
+  int32_t n_buf;
+  int32_t m;
+  int32_t block;
+  int32_t fixed_passes;
+  int32_t max_passes;
+  double tol;
+  int32_t filter_prec;
+  int32_t lanczos_steps;
+  double b_upper;
+  const double* lanczos_v0;
+  uint64_t seed;
+} chfsi_params;
+
+/* Timings (milliseconds, from HIP events on the context stream) and counts
+ * filled by chfsi_solve(). */
+typedef struct {
+  double t_bounds;
+  double t_filter;
+  double t_cholgs;
+  double t_rr;
+  double t_total;
+  int32_t passes;
+  int64_t hx_columns;       /* number of single-column H~ applications    */
+  double hx_flops;          /* algorithmic cell-product flops (padding excluded) */
+  double b_upper;           /* bound used                                 */
+  double a_last, aL_last;   /* filter interval of the last pass           */
+  double max_resid;         /* max_{i<N} r_i after the last pass          */
+} chfsi_stats;
+
+/* ---- context ------------------------------------------------------------ */
+/* Create a context on HIP device `device`; all work goes to `hip_stream`
+ * (a hipStream_t; NULL means the legacy default stream). */
+int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream);
+int chfsi_ctx_destroy(chfsi_ctx* ctx);
+/* Text of the last error of this context ("" if none).  Valid until the next
+ * call on the context.  ctx may be NULL (errors of chfsi_ctx_create). */
+const char* chfsi_last_error(const chfsi_ctx* ctx);
+/* Wait for all work enqueued on the context stream. */
+int chfsi_sync(chfsi_ctx* ctx);
+/* Library version string. */
+const char* chfsi_version(void);
+
+/* ---- operator build (Section 2.3; cell-level matrices of Section 4.2) ---
+ * Builds on the host, in FP64: GLL nodes and weights, the (p+1)-point Gauss
+ * rule, the 1D stiffness, consistent mass and derivative matrices, the
+ * reference cell matrix A_k = D_c (K^c/2 - i skew(k.G^c)/2) D_c with
+ * D = M^-1/2 of the GLL-lumped overlap, the nodal potential V + |k|^2/2 and
+ * the projector tables (per atom node lists and per (cell, atom) cell
+ * matrices split by node multiplicity).  Then uploads them.  The operator
+ * keeps a pointer to ctx, which must outlive it.  Synchronous. */
+int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
+int chfsi_op_destroy(chfsi_op* op);
+/* M nodes, E cells, mcell = (p+1)^3 nodes per cell, nproj = 4 * natoms (0
+ * without projectors), npairs = number of (cell, atom) pairs, is_complex. */
+int chfsi_op_info(const chfsi_op* op, int64_t* M, int64_t* E, int32_t* mcell,
+                  int32_t* nproj, int64_t* npairs, int32_t* is_complex);
+/* Host copies of the built tables, for checking: node coordinates (M x 3),
+ * the reference cell matrix (mcell x mcell row-major; complex operators
+ * write real and imaginary parts to cell_re / cell_im, cell_im may be NULL
+ * otherwise), the nodal diagonal V + |k|^2/2 (M) and D = M^-1/2 (M).  Any
+ * output pointer may be NULL.  Synchronous. */
+int chfsi_op_tables(const chfsi_op* op, double* xyz, double* cell_re, double* cell_im,
+                    double* vdiag, double* dscale);
+
+/* ---- H~.X (Eq. celldgemm + Algorithm 4) ---------------------------------
+ * Y = H~ X for ncols columns.  X and Y are device arrays with the storage
+ * type of `prec` (F64: double; F32 and BF16: float; C128: complex double;
+ * C64: complex float), row-major M x ld.  X and Y must not overlap.
+ * Asynchronous. */
+int chfsi_apply(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld, int32_t prec);
+
+/* ---- upper bound of the spectrum ----------------------------------------
+ * `steps`-step Lanczos run without reorthogonalisation from v0 (device, M
+ * real or M complex values; NULL draws one from `seed`):
+ * b_upper = theta_max(T) + ||f||, lmin_est = theta_min(T).  FP64.
+ * Synchronous. */
+int chfsi_bounds(chfsi_op* op, int32_t steps, const void* v0, uint64_t seed,
+                 double* b_upper, double* lmin_est);
+
+/* ---- Chebyshev filter (Eq. chebyfilter, scaled three-term recurrence) ---
+ * In place on the device block X (double, or complex double for a complex
+ * operator; M x ld, ncols columns): X <- T_m(Hbar) X / T_m((aL - c)/e) with
+ * Hbar = (H~ - c)/e, e = (b - a)/2, c = (b + a)/2.  Requires aL < a < b.
+ * `prec` is the arithmetic of the recurrence (F64/F32/BF16 real, C128/C64
+ * complex); the block is converted to it and back.  Columns are processed in
+ * blocks of `block` (<= 0: all at once).  Asynchronous. */
+int chfsi_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int32_t m,
+                 double a, double b, double aL, int32_t prec, int32_t block);
+
+/* ---- Cholesky-Gram-Schmidt (Algorithm 2, RRGEP-O and Cholesky of S) ----
+ * In place on the device block X (double / complex double): S = X^H X
+ * (FP64, lower triangle, deterministic), S = L L^H, X <- X L^-H.
+ * L_host (nullable, ncols x ncols row-major, complex interleaved for a
+ * complex operator) receives L.  Returns CHFSI_ECHOL, leaving X unchanged,
+ * if S is not positive definite.  Synchronous. */
+int chfsi_orthonormalize(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double* L_host);
+
+/* ---- Rayleigh-Ritz (Algorithm 2, RRGEP-P, RRGEP-D, RRGEP-ST) ------------
+ * X (device, orthonormal columns) is replaced by the Ritz vectors, ordered by
+ * ascending Ritz value: W = H~ X, H^ = X^H W (lower triangle, mirrored),
+ * H^ = Q' Theta Q'^H, X <- X Q'.  theta (host, ncols) receives the Ritz
+ * values; resid (host, nullable) receives r_i = ||H~ psi_i - theta_i psi_i||.
+ * FP64 throughout.  Synchronous. */
+int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double* theta,
+                        double* resid);
+
+/* ---- full solve -----------------------------------------------------------
+ * X (device, double or complex double, M x ld with N + n_buf columns) holds
+ * the start block on entry and the Ritz vectors on exit.  Steps: bound b;
+ * CholGS + RR on X giving a = theta_{N+n_buf}, aL = theta_1; then passes of
+ * (filter every block, CholGS, RR, update a and aL).  theta and resid (host,
+ * N + n_buf each, resid nullable) receive the final Ritz values and residual
+ * norms; stats (nullable) the timings.  Returns CHFSI_NOTCONV if a tolerance
+ * was requested and not met.  Synchronous. */
+int chfsi_solve(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double* theta,
+                double* resid, chfsi_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFSI_H */

@@ -1,0 +1,229 @@
+"""MI355X-native Chebyshev-filtered subspace iteration (ChFSI) on the
+spectral finite-element Kohn-Sham Hamiltonian of DFT-FE 1.0
+(arXiv 2203.07820).
+
+This module is a thin binding of ``libchfsi.so`` (C ABI in
+``include/chfsi.h``): it marshals torch tensors (device memory, streams)
+and host arrays into the library's calls.  Every step of the method runs in
+the library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16, C64, C128, F32, F64  # noqa: F401
+
+__all__ = ["ChfsiError", "Context", "Operator", "F64", "F32", "BF16", "C128", "C64", "load"]
+
+
+class ChfsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chfsi error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    return _lib.load()
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _ld_cols(t):
+    """(ncols, ld) in logical entries of a row-major block tensor."""
+    if t.dim() == 1:
+        return 1, 1
+    if t.dim() != 2:
+        raise ValueError("block tensors are 2-D (M x ld)")
+    return t.shape[1], t.stride(0)
+
+
+class Context:
+    """A library context bound to one device and one HIP stream (torch's
+    current stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = _lib.load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = self.lib.chfsi_ctx_create(C.byref(h), int(device), C.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise ChfsiError(rc, self.lib.chfsi_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def check(self, rc: int, allow=(0,)):
+        if rc not in allow:
+            raise ChfsiError(rc, self.lib.chfsi_last_error(self.h).decode())
+        return rc
+
+    def sync(self):
+        self.check(self.lib.chfsi_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chfsi_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """The operator H~(k) of one system (``workloads.System`` or any object
+    with the same fields)."""
+
+    def __init__(self, ctx: Context, sys):
+        self.ctx = ctx
+        lib = ctx.lib
+        na = int(sys.pos.shape[0])
+        self._keep = []
+
+        def arr(x, n):
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
+            self._keep.append(a)
+            return _dptr(a)
+
+        s = _lib.System()
+        s.L = float(sys.L)
+        s.ncell = int(sys.ncell)
+        s.p = int(sys.p)
+        s.natoms = na
+        s.has_proj = 1 if sys.has_proj else 0
+        if na:
+            s.pos = arr(sys.pos, 3 * na)
+            s.Z = arr(sys.Z, na)
+            s.s = arr(sys.s, na)
+            if sys.has_proj:
+                s.w = arr(sys.w, na)
+                s.h_s = arr(sys.h_s, na)
+                s.h_p = arr(sys.h_p, na)
+        k = np.asarray(sys.k, dtype=np.float64)
+        for i in range(3):
+            s.k[i] = float(k[i])
+        h = C.c_void_p()
+        ctx.check(lib.chfsi_op_build(ctx.h, C.byref(s), C.byref(h)))
+        self.h = h
+        self._keep.clear()
+        M, E, npairs = C.c_int64(), C.c_int64(), C.c_int64()
+        mc, npj, cp = C.c_int32(), C.c_int32(), C.c_int32()
+        ctx.check(lib.chfsi_op_info(h, C.byref(M), C.byref(E), C.byref(mc), C.byref(npj), C.byref(npairs),
+                                    C.byref(cp)))
+        self.M, self.E, self.mcell = M.value, E.value, mc.value
+        self.nproj, self.npairs, self.is_complex = npj.value, npairs.value, bool(cp.value)
+        self.p = int(sys.p)
+        self.ncell = int(sys.ncell)
+
+    # -- tables -------------------------------------------------------------
+    def tables(self):
+        mc, M = self.mcell, self.M
+        xyz = np.zeros((M, 3))
+        cre = np.zeros((mc, mc))
+        cim = np.zeros((mc, mc))
+        vd = np.zeros(M)
+        ds = np.zeros(M)
+        self.ctx.check(self.ctx.lib.chfsi_op_tables(self.h, _dptr(xyz), _dptr(cre), _dptr(cim), _dptr(vd), _dptr(ds)))
+        return {"xyz": xyz, "cell": cre + 1j * cim if self.is_complex else cre, "vdiag": vd, "dscale": ds}
+
+    # -- steps of the method -----------------------------------------------
+    def apply(self, X, Y, prec: Optional[int] = None):
+        """Y = H~ X (device tensors, same storage type, same ld)."""
+        if prec is None:
+            prec = C128 if self.is_complex else F64
+        ncols, ld = _ld_cols(X)
+        ncols_y, ld_y = _ld_cols(Y)
+        if ld_y != ld or ncols_y != ncols:
+            raise ValueError("X and Y must have the same shape and ld")
+        self.ctx.check(self.ctx.lib.chfsi_apply(self.h, _tptr(X), _tptr(Y), ncols, ld, int(prec)))
+
+    def bounds(self, steps: int = 20, v0=None, seed: int = 0):
+        b, lmin = C.c_double(), C.c_double()
+        self.ctx.check(self.ctx.lib.chfsi_bounds(self.h, int(steps), _tptr(v0), C.c_uint64(seed), C.byref(b),
+                                                 C.byref(lmin)))
+        return b.value, lmin.value
+
+    def filter(self, X, m: int, a: float, b: float, aL: float, prec: Optional[int] = None, block: int = 0):
+        if prec is None:
+            prec = C128 if self.is_complex else F64
+        ncols, ld = _ld_cols(X)
+        self.ctx.check(self.ctx.lib.chfsi_filter(self.h, _tptr(X), ncols, ld, int(m), float(a), float(b),
+                                                 float(aL), int(prec), int(block)))
+
+    def orthonormalize(self, X, want_L: bool = False):
+        ncols, ld = _ld_cols(X)
+        L = None
+        ptr = C.POINTER(C.c_double)()
+        if want_L:
+            L = np.zeros((ncols, ncols), dtype=np.complex128 if self.is_complex else np.float64)
+            ptr = L.ctypes.data_as(C.POINTER(C.c_double))
+        self.ctx.check(self.ctx.lib.chfsi_orthonormalize(self.h, _tptr(X), ncols, ld, ptr))
+        return L
+
+    def rayleigh_ritz(self, X, want_resid: bool = True):
+        ncols, ld = _ld_cols(X)
+        th = np.zeros(ncols)
+        r = np.zeros(ncols) if want_resid else None
+        self.ctx.check(self.ctx.lib.chfsi_rayleigh_ritz(self.h, _tptr(X), ncols, ld, _dptr(th),
+                                                        _dptr(r) if r is not None else C.POINTER(C.c_double)()))
+        return th, r
+
+    def solve(self, X, nwanted: int, m: int, block: int, n_buf: int = 0, fixed_passes: int = 0,
+              tol: float = 0.0, max_passes: int = 100, filter_prec: Optional[int] = None,
+              lanczos_steps: int = 20, b_upper: float = 0.0, lanczos_v0=None, seed: int = 0):
+        if filter_prec is None:
+            filter_prec = C128 if self.is_complex else F64
+        ncols, ld = _ld_cols(X)
+        if ncols != nwanted + n_buf:
+            raise ValueError("X must have nwanted + n_buf columns")
+        p = _lib.Params()
+        p.nwanted, p.n_buf, p.m, p.block = nwanted, n_buf, m, block
+        p.fixed_passes, p.max_passes, p.tol = fixed_passes, max_passes, tol
+        p.filter_prec, p.lanczos_steps, p.b_upper = int(filter_prec), lanczos_steps, b_upper
+        v0 = None
+        if lanczos_v0 is not None:
+            v0 = np.ascontiguousarray(lanczos_v0)
+            if np.iscomplexobj(v0):
+                v0 = v0.view(np.float64)
+            v0 = np.ascontiguousarray(v0, dtype=np.float64)
+            p.lanczos_v0 = _dptr(v0)
+        p.seed = seed
+        th = np.zeros(ncols)
+        r = np.zeros(ncols)
+        st = _lib.Stats()
+        rc = self.ctx.lib.chfsi_solve(self.h, C.byref(p), _tptr(X), ld, _dptr(th), _dptr(r), C.byref(st))
+        self.ctx.check(rc, allow=(0, 1))
+        stats = {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
+        stats["converged"] = rc == 0
+        return th, r, stats
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.chfsi_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,916 @@
+// Host driver of libchfsi: the C ABI of include/chfsi.h.
+//
+// The eigensolver is DFT-FE 1.0's Chebyshev filtered eigensolver (Section
+// 3.1 and Algorithm 2) at a fixed potential:
+//   bound b (Lanczos), then per pass: Chebyshev filter of every column block
+//   (cell-wise H~.X of Section 4.3), RRGEP-O / Cholesky / RRGEP-ST-O
+//   (X <- X L^-H), RRGEP-P (H^ = X^H H~ X), RRGEP-D (dense eigensolve of the
+//   N x N projected matrix) and RRGEP-ST (X <- X Q').
+// The O(MN) and O(MN^2) work runs in the kernels of kernels_hx.hip and
+// kernels_dense.hip.  The O(N^3) dense factorisations of the N x N matrices
+// (Cholesky, triangular inverse, symmetric eigensolve) call rocSOLVER on the
+// device, as the paper calls ScaLAPACK/ELPA for RRGEP-D.
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace chfsi;
+
+namespace {
+
+enum Slot {
+  WS_R0, WS_R1, WS_R2, WS_R3,      // filter buffers
+  WS_NLPART, WS_HP,                // projector partials / scaled coefficients
+  WS_GPART, WS_G, WS_S, WS_Z, WS_Z2,
+  WS_W, WS_X2, WS_HPSI,            // M x N work blocks
+  WS_RPART, WS_VEC, WS_SMALL, WS_EIG, WS_INFO,
+  WS_COUNT
+};
+
+}  // namespace
+
+struct chfsi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  std::string err;
+  void* ws[WS_COUNT] = {};
+  size_t ws_size[WS_COUNT] = {};
+};
+
+struct chfsi_op {
+  chfsi_ctx* ctx = nullptr;
+  HostTables t;                      // host copies (large projector arrays dropped)
+  int64_t npairs = 0;
+  // device tables
+  void* A64 = nullptr;  void* Ai64 = nullptr;   // swizzled cell matrix, double
+  void* A32 = nullptr;  void* Ai32 = nullptr;   // float
+  double* vdiag = nullptr;
+  int64_t* atom_ptr = nullptr;
+  int32_t* atom_node = nullptr;
+  double* atom_val = nullptr;
+  int32_t* chunk_atom = nullptr;
+  int64_t* chunk_begin = nullptr;
+  int32_t* atom_chunk_ptr = nullptr;
+  int nchunks = 0;
+  double* hcoef = nullptr;
+  int32_t* pair_ptr = nullptr;
+  int32_t* pair_atom = nullptr;
+  void* pair_re64 = nullptr; void* pair_im64 = nullptr;
+  void* pair_re32 = nullptr; void* pair_im32 = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(chfsi_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, CHFSI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define RB_TRY(ctx, expr)                                                                 \
+  do {                                                                                    \
+    rocblas_status s_ = (expr);                                                           \
+    if (s_ != rocblas_status_success)                                                     \
+      return fail(ctx, CHFSI_EHIP, std::string(#expr) + ": rocblas status " +             \
+                                       std::to_string(static_cast<int>(s_)));             \
+  } while (0)
+
+#define CHECK(expr)            \
+  do {                         \
+    int r_ = (expr);           \
+    if (r_ < 0) return r_;     \
+  } while (0)
+
+// Grow-only scratch slot.
+int ws_get(chfsi_ctx* c, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  if (c->ws_size[slot] < bytes) {
+    if (c->ws[slot]) {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipFree(c->ws[slot]));
+      c->ws[slot] = nullptr;
+      c->ws_size[slot] = 0;
+    }
+    const size_t b = (bytes + 4095) / 4096 * 4096;
+    hipError_t e = hipMalloc(&c->ws[slot], b);
+    if (e != hipSuccess) {
+      c->ws[slot] = nullptr;
+      return fail(c, CHFSI_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    c->ws_size[slot] = b;
+  }
+  *out = c->ws[slot];
+  return 0;
+}
+
+template <typename T>
+int upload(chfsi_op* op, const std::vector<T>& v, T** out) {
+  *out = nullptr;
+  if (v.empty()) return 0;
+  void* p = nullptr;
+  if (hipMalloc(&p, v.size() * sizeof(T)) != hipSuccess)
+    return fail(op->ctx, CHFSI_ENOMEM, "hipMalloc of operator table failed");
+  op->allocs.push_back(p);
+  HIP_TRY(op->ctx, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<T*>(p);
+  return 0;
+}
+
+int upload_f32(chfsi_op* op, const std::vector<double>& v, void** out) {
+  std::vector<float> f(v.size());
+  for (size_t i = 0; i < v.size(); ++i) f[i] = static_cast<float>(v[i]);
+  float* p = nullptr;
+  CHECK(upload(op, f, &p));
+  *out = p;
+  return 0;
+}
+
+bool prec_valid_for(const chfsi_op* op, int prec) {
+  if (op->t.cplx) return prec == CHFSI_C128 || prec == CHFSI_C64;
+  return prec == CHFSI_F64 || prec == CHFSI_F32 || prec == CHFSI_BF16;
+}
+
+size_t prec_bytes(int prec) {
+  switch (prec) {
+    case CHFSI_F64: return 8;
+    case CHFSI_F32: case CHFSI_BF16: return 4;
+    case CHFSI_C128: return 16;
+    case CHFSI_C64: return 8;
+    default: return 0;
+  }
+}
+
+// storage precision used for a given arithmetic precision
+int storage_of(int prec) { return prec == CHFSI_BF16 ? CHFSI_F32 : prec; }
+bool is_single(int prec) { return prec == CHFSI_F32 || prec == CHFSI_BF16 || prec == CHFSI_C64; }
+
+// Y = alpha (H~ Xk - c Xk) - beta Xp  accumulated into T (which must hold 0
+// on entry).  Xk, Xp, T are in the storage type of prec, logical ld.
+int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp, int64_t ldp, void* T,
+            int64_t ldt, int64_t ncols, double alpha, double c, double beta, bool zero_prev) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int cf = t.cplx ? 2 : 1;
+  const bool single = is_single(prec);
+  void* hP = nullptr;
+  int64_t ldhp = 0;
+  if (t.has_proj) {
+    ldhp = (ncols * cf + 63) / 64 * 64;
+    const size_t eb = single ? 4 : 8;
+    void* part = nullptr;
+    CHECK(ws_get(ctx, WS_NLPART, static_cast<size_t>(op->nchunks) * 4 * ldhp * eb, &part));
+    CHECK(ws_get(ctx, WS_HP, static_cast<size_t>(t.natoms) * 4 * ldhp * eb, &hP));
+    NlLaunch nl;
+    nl.natoms = t.natoms;
+    nl.cplx = t.cplx;
+    nl.ncols = static_cast<int>(ncols);
+    nl.atom_ptr = op->atom_ptr;
+    nl.atom_node = op->atom_node;
+    nl.atom_val = op->atom_val;
+    nl.chunk_atom = op->chunk_atom;
+    nl.chunk_begin = op->chunk_begin;
+    nl.nchunks = op->nchunks;
+    nl.atom_chunk_ptr = op->atom_chunk_ptr;
+    nl.hcoef = op->hcoef;
+    nl.X = Xk;
+    nl.ldx = ldx;
+    nl.partial = part;
+    nl.hP = hP;
+    nl.ldhp = ldhp;
+    HIP_TRY(ctx, launch_nl_project(nl, prec, ctx->stream));
+  }
+  HxLaunch L;
+  L.p = t.p;
+  L.nc = t.ncell;
+  L.ncols = static_cast<int>(ncols * cf);
+  L.cplx = t.cplx;
+  L.A = single ? op->A32 : op->A64;
+  L.Ai = single ? op->Ai32 : op->Ai64;
+  L.vdiag = op->vdiag;
+  L.Xk = Xk;
+  L.ldx = ldx * cf;
+  L.Xp = Xp;
+  L.ldp = ldp * cf;
+  L.T = T;
+  L.ldt = ldt * cf;
+  L.zero_prev = zero_prev;
+  L.alpha = alpha;
+  L.c = c;
+  L.beta = beta;
+  L.pair_ptr = t.has_proj ? op->pair_ptr : nullptr;
+  L.pair_atom = op->pair_atom;
+  L.pair_re = single ? op->pair_re32 : op->pair_re64;
+  L.pair_im = single ? op->pair_im32 : op->pair_im64;
+  L.hP = hP;
+  L.ldhp = ldhp;
+  const int kp = (prec == CHFSI_BF16) ? CHFSI_F32 : prec;
+  HIP_TRY(ctx, launch_cell_hx(L, kp, ctx->stream));
+  return 0;
+}
+
+// Scaled Chebyshev coefficients (Section 3.1 filter; the three-term recurrence
+// rescaled each step): step 1 Y = a1 (H~X - cX); step i >= 2
+// Z = a_i (H~Y - cY) - b_i X.
+void cheb_coeffs(int m, double a, double b, double aL, double* c, std::vector<double>& al,
+                 std::vector<double>& be) {
+  const double e = (b - a) / 2.0;
+  *c = (b + a) / 2.0;
+  const double s1 = e / (aL - *c);
+  double s = s1;
+  al.assign(m, 0.0);
+  be.assign(m, 0.0);
+  al[0] = s1 / e;
+  for (int i = 1; i < m; ++i) {
+    const double sn = 1.0 / (2.0 / s1 - s);
+    al[i] = 2.0 * sn / e;
+    be[i] = s * sn;
+    s = sn;
+  }
+}
+
+// Filter one block already converted into R0 (storage of prec, ld = ncols).
+// Returns the index of the buffer holding the result.
+int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int m, double a, double b,
+                 double aL, int* out_idx) {
+  chfsi_ctx* ctx = op->ctx;
+  const int cf = op->t.cplx ? 2 : 1;
+  const int64_t M = op->t.M;
+  double c;
+  std::vector<double> al, be;
+  cheb_coeffs(m, a, b, aL, &c, al, be);
+  const int sp = storage_of(prec);
+  for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R[i], M, ncols * cf, ncols * cf, sp, ctx->stream));
+  CHECK(hx_step(op, prec, R[0], ncols, nullptr, ncols, R[1], ncols, ncols, al[0], c, 0.0, false));
+  for (int i = 2; i <= m; ++i) {
+    CHECK(hx_step(op, prec, R[(i - 1) % 4], ncols, R[(i - 2) % 4], ncols, R[i % 4], ncols, ncols, al[i - 1], c,
+                  be[i - 1], true));
+  }
+  *out_idx = m % 4;
+  return 0;
+}
+
+int do_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int m, double a, double b, double aL, int prec,
+              int64_t block) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int cf = t.cplx ? 2 : 1;
+  const int xprec = t.cplx ? CHFSI_C128 : CHFSI_F64;
+  const int sp = storage_of(prec);
+  if (block <= 0 || block > ncols) block = ncols;
+  const size_t eb = prec_bytes(sp);
+  void* R[4];
+  for (int i = 0; i < 4; ++i) CHECK(ws_get(ctx, WS_R0 + i, static_cast<size_t>(t.M) * block * eb, &R[i]));
+  for (int64_t c0 = 0; c0 < ncols; c0 += block) {
+    const int64_t nb = std::min<int64_t>(block, ncols - c0);
+    double* Xb = static_cast<double*>(X) + c0 * cf;
+    HIP_TRY(ctx, launch_convert(R[0], nb * cf, sp, Xb, ld * cf, xprec, t.M, nb * cf, ctx->stream));
+    int idx = 0;
+    CHECK(filter_block(op, prec, R, nb, m, a, b, aL, &idx));
+    HIP_TRY(ctx, launch_convert(Xb, ld * cf, xprec, R[idx], nb * cf, sp, t.M, nb * cf, ctx->stream));
+  }
+  return 0;
+}
+
+// ---- dense helpers ----------------------------------------------------------
+
+// S (N x N, column-major; complex interleaved) = X^H Y over real views.
+int gram(chfsi_op* op, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t N, double** S_out) {
+  chfsi_ctx* ctx = op->ctx;
+  const int cf = op->t.cplx ? 2 : 1;
+  const int n = static_cast<int>(N * cf);
+  void *part, *G, *S;
+  CHECK(ws_get(ctx, WS_GPART, gram_partial_bytes(op->t.M, n), &part));
+  CHECK(ws_get(ctx, WS_G, static_cast<size_t>(n) * n * 8, &G));
+  CHECK(ws_get(ctx, WS_S, static_cast<size_t>(N) * N * 8 * cf, &S));
+  HIP_TRY(ctx, launch_gram(X, ldx * cf, Y, ldy * cf, op->t.M, n, static_cast<double*>(part),
+                           static_cast<double*>(G), n, ctx->stream));
+  if (op->t.cplx)
+    HIP_TRY(ctx, launch_gram_combine_complex(static_cast<double*>(G), n, static_cast<double*>(S),
+                                             static_cast<int>(N), ctx->stream));
+  else
+    HIP_TRY(ctx, launch_sym_from_lower(static_cast<double*>(G), n, static_cast<double*>(S), n, ctx->stream));
+  *S_out = static_cast<double*>(S);
+  return 0;
+}
+
+int read_info(chfsi_ctx* ctx, rocblas_int* dinfo, int* info) {
+  rocblas_int h = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&h, dinfo, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  *info = h;
+  return 0;
+}
+
+// CholGS: Xout = X L^-H with S = X^H X = L L^H.  Xout may not alias X.
+int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo, int64_t N, double* L_host) {
+  chfsi_ctx* ctx = op->ctx;
+  const bool cplx = op->t.cplx;
+  const int cf = cplx ? 2 : 1;
+  double* S = nullptr;
+  CHECK(gram(op, X, ldx, X, ldx, N, &S));
+  void* dinfo;
+  CHECK(ws_get(ctx, WS_INFO, 64, &dinfo));
+  const rocblas_int n = static_cast<rocblas_int>(N);
+  if (cplx)
+    RB_TRY(ctx, rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, reinterpret_cast<rocblas_double_complex*>(S), n,
+                                 static_cast<rocblas_int*>(dinfo)));
+  else
+    RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, n, S, n, static_cast<rocblas_int*>(dinfo)));
+  int info = 0;
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0)
+    return fail(ctx, CHFSI_ECHOL, "overlap matrix is not positive definite (leading minor " + std::to_string(info) +
+                                      ")");
+  if (L_host) {
+    std::vector<double> Lcm(static_cast<size_t>(N) * N * cf);
+    HIP_TRY(ctx, hipMemcpyAsync(Lcm.data(), S, Lcm.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t j = 0; j < N; ++j)
+        for (int q = 0; q < cf; ++q)
+          L_host[(i * N + j) * cf + q] = (i >= j) ? Lcm[(i + j * N) * cf + q] : 0.0;
+  }
+  if (cplx)
+    RB_TRY(ctx, rocsolver_ztrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n,
+                                 reinterpret_cast<rocblas_double_complex*>(S), n, static_cast<rocblas_int*>(dinfo)));
+  else
+    RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n, S, n,
+                                 static_cast<rocblas_int*>(dinfo)));
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0) return fail(ctx, CHFSI_ECHOL, "Cholesky factor is singular");
+  // Z = L^-H (upper triangular), as a real-view matrix
+  const double* Z = nullptr;
+  int64_t ldz = 0;
+  if (cplx) {
+    void* Z2;
+    CHECK(ws_get(ctx, WS_Z2, static_cast<size_t>(N) * N * 4 * 8, &Z2));
+    HIP_TRY(ctx, launch_expand_complex(S, n, n, 1, static_cast<double*>(Z2), ctx->stream));
+    Z = static_cast<double*>(Z2);
+    ldz = 2 * N;
+  } else {
+    HIP_TRY(ctx, launch_zero_strict_lower(S, n, N, ctx->stream));
+    Z = S;
+    ldz = N;
+  }
+  HIP_TRY(ctx, launch_rotate(X, ldx * cf, Z, ldz, Xout, ldo * cf, op->t.M, static_cast<int>(N * cf),
+                             static_cast<int>(N * cf), true, ctx->stream));
+  return 0;
+}
+
+// Rayleigh-Ritz on orthonormal X.  Writes Psi to Psi_out (may not alias X),
+// theta (host), resid (host, nullable).  W is scratch.
+int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64_t ldpsi, int64_t N,
+                  double* theta, double* resid) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const bool cplx = t.cplx;
+  const int cf = cplx ? 2 : 1;
+  const int prec = cplx ? CHFSI_C128 : CHFSI_F64;
+  void *W, *HPsi;
+  CHECK(ws_get(ctx, WS_W, static_cast<size_t>(t.M) * N * 8 * cf, &W));
+  HIP_TRY(ctx, launch_fill(W, t.M, N * cf, N * cf, prec, ctx->stream));
+  CHECK(hx_step(op, prec, X, ldx, nullptr, 0, W, N, N, 1.0, 0.0, 0.0, false));
+  double* Hh = nullptr;
+  CHECK(gram(op, X, ldx, static_cast<double*>(W), N, N, &Hh));
+  void *dinfo, *eig;
+  CHECK(ws_get(ctx, WS_INFO, 64, &dinfo));
+  CHECK(ws_get(ctx, WS_EIG, static_cast<size_t>(N) * 2 * 8, &eig));
+  double* D = static_cast<double*>(eig);
+  double* Ework = D + N;
+  const rocblas_int n = static_cast<rocblas_int>(N);
+  if (cplx)
+    RB_TRY(ctx, rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                 reinterpret_cast<rocblas_double_complex*>(Hh), n, D, Ework,
+                                 static_cast<rocblas_int*>(dinfo)));
+  else
+    RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n, Hh, n, D, Ework,
+                                 static_cast<rocblas_int*>(dinfo)));
+  int info = 0;
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
+  const double* Z = nullptr;
+  int64_t ldz = 0;
+  void* Zb;
+  if (cplx) {
+    CHECK(ws_get(ctx, WS_Z2, static_cast<size_t>(N) * N * 4 * 8, &Zb));
+    HIP_TRY(ctx, launch_expand_complex(Hh, n, n, 2, static_cast<double*>(Zb), ctx->stream));
+    ldz = 2 * N;
+  } else {
+    CHECK(ws_get(ctx, WS_Z, static_cast<size_t>(N) * N * 8, &Zb));
+    HIP_TRY(ctx, launch_transpose(Hh, static_cast<double*>(Zb), n, ctx->stream));
+    ldz = N;
+  }
+  Z = static_cast<double*>(Zb);
+  HIP_TRY(ctx, launch_rotate(X, ldx * cf, Z, ldz, Psi, ldpsi * cf, t.M, static_cast<int>(N * cf),
+                             static_cast<int>(N * cf), false, ctx->stream));
+  if (resid) {
+    CHECK(ws_get(ctx, WS_HPSI, static_cast<size_t>(t.M) * N * 8 * cf, &HPsi));
+    HIP_TRY(ctx, launch_rotate(static_cast<double*>(W), N * cf, Z, ldz, static_cast<double*>(HPsi), N * cf, t.M,
+                               static_cast<int>(N * cf), static_cast<int>(N * cf), false, ctx->stream));
+    void* rp;
+    CHECK(ws_get(ctx, WS_RPART, resid_partial_count(t.M, static_cast<int>(N)) * 8, &rp));
+    int nch = 0;
+    HIP_TRY(ctx, launch_resid(static_cast<double*>(HPsi), N, Psi, ldpsi, D, t.M, static_cast<int>(N), cplx,
+                              static_cast<double*>(rp), &nch, ctx->stream));
+    std::vector<double> hp(static_cast<size_t>(nch) * N);
+    HIP_TRY(ctx, hipMemcpyAsync(hp.data(), rp, hp.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int64_t j = 0; j < N; ++j) {
+      double s = 0.0;
+      for (int c = 0; c < nch; ++c) s += hp[static_cast<size_t>(c) * N + j];
+      resid[j] = std::sqrt(s);
+    }
+  } else {
+    HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return 0;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) + Box-Muller: the library's own
+// generator for start vectors when the caller gives none.
+struct SplitMix {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+  double normal() {
+    const double u1 = uniform(), u2 = uniform();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+  }
+};
+
+// Eigenvalues of a small symmetric matrix by cyclic Jacobi rotations.
+std::vector<double> small_eigvals(std::vector<double> A, int n) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double th = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double tt = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = cs * akp - sn * akq;
+          A[k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = cs * apk - sn * aqk;
+          A[q * n + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  std::vector<double> ev(n);
+  for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+  std::sort(ev.begin(), ev.end());
+  return ev;
+}
+
+int dot_host(chfsi_ctx* ctx, const double* x, const double* y, int64_t n, double* out) {
+  void* part;
+  CHECK(ws_get(ctx, WS_SMALL, dot_blocks() * 8, &part));
+  HIP_TRY(ctx, launch_dot(x, y, n, static_cast<double*>(part), ctx->stream));
+  std::vector<double> h(dot_blocks());
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double s = 0.0;
+  for (double v : h) s += v;
+  *out = s;
+  return 0;
+}
+
+int do_bounds(chfsi_op* op, int steps, const double* v0_dev, const double* v0_host, uint64_t seed,
+              double* b_upper, double* lmin) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int cf = t.cplx ? 2 : 1;
+  const int prec = t.cplx ? CHFSI_C128 : CHFSI_F64;
+  const int64_t nr = t.M * cf;  // reals per vector
+  void* vb;
+  CHECK(ws_get(ctx, WS_VEC, static_cast<size_t>(nr) * 3 * 8, &vb));
+  double* v = static_cast<double*>(vb);
+  double* vprev = v + nr;
+  double* f = v + 2 * nr;
+  if (v0_dev) {
+    HIP_TRY(ctx, hipMemcpyAsync(v, v0_dev, nr * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    std::vector<double> h(nr);
+    if (v0_host) {
+      std::memcpy(h.data(), v0_host, nr * 8);
+    } else {
+      SplitMix g{seed};
+      for (auto& x : h) x = g.normal();
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(v, h.data(), nr * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  double nv;
+  CHECK(dot_host(ctx, v, v, nr, &nv));
+  if (!(nv > 0.0) || !std::isfinite(nv)) return fail(ctx, CHFSI_EINVAL, "Lanczos start vector is zero or non-finite");
+  HIP_TRY(ctx, launch_axpby(0.0, v, 1.0 / std::sqrt(nv), v, nr, ctx->stream));
+  std::vector<double> al, be;
+  // f = H v ; alpha = v.f ; f -= alpha v
+  HIP_TRY(ctx, launch_fill(f, t.M, cf, cf, prec, ctx->stream));
+  CHECK(hx_step(op, prec, v, 1, nullptr, 1, f, 1, 1, 1.0, 0.0, 0.0, false));
+  double alpha;
+  CHECK(dot_host(ctx, v, f, nr, &alpha));
+  HIP_TRY(ctx, launch_axpby(-alpha, v, 1.0, f, nr, ctx->stream));
+  al.push_back(alpha);
+  for (int k = 1; k < steps; ++k) {
+    double bb;
+    CHECK(dot_host(ctx, f, f, nr, &bb));
+    const double beta = std::sqrt(bb);
+    if (!(beta > 0.0)) break;
+    // vprev <- v ; v <- f / beta ; f <- H v - beta vprev ; alpha ; f -= alpha v
+    std::swap(v, vprev);
+    HIP_TRY(ctx, launch_axpby(1.0 / beta, f, 0.0, v, nr, ctx->stream));
+    HIP_TRY(ctx, launch_fill(f, t.M, cf, cf, prec, ctx->stream));
+    CHECK(hx_step(op, prec, v, 1, nullptr, 1, f, 1, 1, 1.0, 0.0, 0.0, false));
+    HIP_TRY(ctx, launch_axpby(-beta, vprev, 1.0, f, nr, ctx->stream));
+    CHECK(dot_host(ctx, v, f, nr, &alpha));
+    HIP_TRY(ctx, launch_axpby(-alpha, v, 1.0, f, nr, ctx->stream));
+    al.push_back(alpha);
+    be.push_back(beta);
+  }
+  double ff;
+  CHECK(dot_host(ctx, f, f, nr, &ff));
+  const int k = static_cast<int>(al.size());
+  std::vector<double> T(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) T[i * k + i] = al[i];
+  for (int i = 0; i + 1 < k; ++i) T[i * k + i + 1] = T[(i + 1) * k + i] = be[i];
+  std::vector<double> ev = small_eigvals(T, k);
+  if (b_upper) *b_upper = ev.back() + std::sqrt(ff);
+  if (lmin) *lmin = ev.front();
+  if (!std::isfinite(ev.back()) || !std::isfinite(ff)) return fail(ctx, CHFSI_EDIVERGE, "non-finite Lanczos run");
+  return 0;
+}
+
+int check_block(chfsi_op* op, const void* X, int64_t ncols, int64_t ld) {
+  if (!X) return fail(op->ctx, CHFSI_EINVAL, "null block pointer");
+  if (ncols <= 0) return fail(op->ctx, CHFSI_EINVAL, "ncols must be positive");
+  if (ld < ncols) return fail(op->ctx, CHFSI_EINVAL, "ld < ncols");
+  if (ncols > op->t.M) return fail(op->ctx, CHFSI_EINVAL, "ncols > M");
+  return 0;
+}
+
+double event_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+  return ms;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* chfsi_version(void) { return "chfsi 0.1 (gfx950)"; }
+
+int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(nullptr, CHFSI_EINVAL, "null output pointer");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(nullptr, CHFSI_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(nullptr, CHFSI_EINVAL, "device index out of range");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, CHFSI_EHIP, "hipSetDevice failed");
+  std::unique_ptr<chfsi_ctx> c(new chfsi_ctx());
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (rocblas_create_handle(&c->blas) != rocblas_status_success)
+    return fail(nullptr, CHFSI_EHIP, "rocblas_create_handle failed");
+  if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+    return fail(nullptr, CHFSI_EHIP, "rocblas_set_stream failed");
+  *out = c.release();
+  return 0;
+}
+
+int chfsi_ctx_destroy(chfsi_ctx* ctx) {
+  if (!ctx) return 0;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int i = 0; i < WS_COUNT; ++i)
+    if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  delete ctx;
+  return 0;
+}
+
+const char* chfsi_last_error(const chfsi_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int chfsi_sync(chfsi_ctx* ctx) {
+  if (!ctx) return CHFSI_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (!sys || !out) return fail(ctx, CHFSI_EINVAL, "null argument");
+  *out = nullptr;
+  if (sys->p < kMinOrder || sys->p > kMaxOrder) return fail(ctx, CHFSI_EINVAL, "order p must be in [2, 7]");
+  if (sys->ncell < 1 || !(sys->L > 0.0) || sys->natoms < 0) return fail(ctx, CHFSI_EINVAL, "bad mesh size");
+  const int64_t n = static_cast<int64_t>(sys->ncell) * sys->p;
+  if (n * n * n > 0x7fffffffLL) return fail(ctx, CHFSI_EINVAL, "mesh too large (node ids are 32-bit)");
+  if (sys->natoms > 0 && (!sys->pos || !sys->Z || !sys->s)) return fail(ctx, CHFSI_EINVAL, "null atom arrays");
+  if (sys->has_proj && sys->natoms > 0 && (!sys->w || !sys->h_s || !sys->h_p))
+    return fail(ctx, CHFSI_EINVAL, "null projector arrays");
+  for (int i = 0; i < sys->natoms; ++i) {
+    if (!(sys->s[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "Gaussian widths must be positive");
+    if (sys->has_proj && !(sys->w[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "projector widths must be positive");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  std::unique_ptr<chfsi_op> op(new chfsi_op());
+  op->ctx = ctx;
+  HostTables& t = op->t;
+  std::string e = build_tables(*sys, t);
+  if (!e.empty()) return fail(ctx, CHFSI_EINVAL, e);
+  auto cleanup = [&]() {
+    for (void* p : op->allocs) (void)hipFree(p);
+    op->allocs.clear();
+  };
+  int rc = 0;
+  do {
+    std::vector<double> sw(static_cast<size_t>(t.mpad / 16) * (t.mpad / 4) * 64);
+    swizzle_cell_matrix(t.cell_re.data(), t.mcell, t.mpad, sw.data());
+    double* d;
+    if ((rc = upload(op.get(), sw, &d)) < 0) break;
+    op->A64 = d;
+    if ((rc = upload_f32(op.get(), sw, &op->A32)) < 0) break;
+    if (t.cplx) {
+      swizzle_cell_matrix(t.cell_im.data(), t.mcell, t.mpad, sw.data());
+      if ((rc = upload(op.get(), sw, &d)) < 0) break;
+      op->Ai64 = d;
+      if ((rc = upload_f32(op.get(), sw, &op->Ai32)) < 0) break;
+    }
+    if ((rc = upload(op.get(), t.vdiag, &op->vdiag)) < 0) break;
+    if (t.has_proj) {
+      if ((rc = upload(op.get(), t.atom_ptr, &op->atom_ptr)) < 0) break;
+      if ((rc = upload(op.get(), t.atom_node, &op->atom_node)) < 0) break;
+      if ((rc = upload(op.get(), t.atom_val, &op->atom_val)) < 0) break;
+      if ((rc = upload(op.get(), t.hcoef, &op->hcoef)) < 0) break;
+      // fixed-size chunks of each atom's node list
+      std::vector<int32_t> ca, acp(1, 0);
+      std::vector<int64_t> cb;
+      for (int a = 0; a < t.natoms; ++a) {
+        for (int64_t b = t.atom_ptr[a]; b < t.atom_ptr[a + 1]; b += 512) {
+          ca.push_back(a);
+          cb.push_back(b);
+        }
+        acp.push_back(static_cast<int32_t>(ca.size()));
+      }
+      op->nchunks = static_cast<int>(ca.size());
+      if ((rc = upload(op.get(), ca, &op->chunk_atom)) < 0) break;
+      if ((rc = upload(op.get(), cb, &op->chunk_begin)) < 0) break;
+      if ((rc = upload(op.get(), acp, &op->atom_chunk_ptr)) < 0) break;
+      if ((rc = upload(op.get(), t.pair_ptr, &op->pair_ptr)) < 0) break;
+      if ((rc = upload(op.get(), t.pair_atom, &op->pair_atom)) < 0) break;
+      op->npairs = static_cast<int64_t>(t.pair_atom.size());
+      if ((rc = upload(op.get(), t.pair_re, &d)) < 0) break;
+      op->pair_re64 = d;
+      if ((rc = upload_f32(op.get(), t.pair_re, &op->pair_re32)) < 0) break;
+      if (t.cplx) {
+        if ((rc = upload(op.get(), t.pair_im, &d)) < 0) break;
+        op->pair_im64 = d;
+        if ((rc = upload_f32(op.get(), t.pair_im, &op->pair_im32)) < 0) break;
+      }
+    }
+  } while (0);
+  if (rc < 0) {
+    cleanup();
+    return rc;
+  }
+  // large projector arrays live on the device only
+  std::vector<double>().swap(t.atom_val);
+  std::vector<int32_t>().swap(t.atom_node);
+  std::vector<double>().swap(t.pair_re);
+  std::vector<double>().swap(t.pair_im);
+  *out = op.release();
+  return 0;
+}
+
+int chfsi_op_destroy(chfsi_op* op) {
+  if (!op) return 0;
+  (void)hipStreamSynchronize(op->ctx->stream);
+  for (void* p : op->allocs) (void)hipFree(p);
+  delete op;
+  return 0;
+}
+
+int chfsi_op_info(const chfsi_op* op, int64_t* M, int64_t* E, int32_t* mcell, int32_t* nproj, int64_t* npairs,
+                  int32_t* is_complex) {
+  if (!op) return CHFSI_EINVAL;
+  if (M) *M = op->t.M;
+  if (E) *E = op->t.E;
+  if (mcell) *mcell = op->t.mcell;
+  if (nproj) *nproj = op->t.has_proj ? 4 * op->t.natoms : 0;
+  if (npairs) *npairs = op->npairs;
+  if (is_complex) *is_complex = op->t.cplx ? 1 : 0;
+  return 0;
+}
+
+int chfsi_op_tables(const chfsi_op* op, double* xyz, double* cell_re, double* cell_im, double* vdiag,
+                    double* dscale) {
+  if (!op) return CHFSI_EINVAL;
+  const HostTables& t = op->t;
+  if (xyz) {
+    const int64_t n = t.n;
+    for (int64_t j = 0; j < t.M; ++j) {
+      xyz[3 * j] = t.x1d[j % n];
+      xyz[3 * j + 1] = t.x1d[(j / n) % n];
+      xyz[3 * j + 2] = t.x1d[j / (n * n)];
+    }
+  }
+  if (cell_re) std::memcpy(cell_re, t.cell_re.data(), t.cell_re.size() * 8);
+  if (cell_im) {
+    if (t.cplx) std::memcpy(cell_im, t.cell_im.data(), t.cell_im.size() * 8);
+    else std::memset(cell_im, 0, static_cast<size_t>(t.mcell) * t.mcell * 8);
+  }
+  if (vdiag) std::memcpy(vdiag, t.vdiag.data(), t.M * 8);
+  if (dscale) std::memcpy(dscale, t.dscale.data(), t.M * 8);
+  return 0;
+}
+
+int chfsi_apply(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld, int32_t prec) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  if (!Y) return fail(ctx, CHFSI_EINVAL, "null output");
+  if (!prec_valid_for(op, prec)) return fail(ctx, CHFSI_EINVAL, "precision does not match the operator");
+  if (X == Y) return fail(ctx, CHFSI_EINVAL, "X and Y must not overlap");
+  const int cf = op->t.cplx ? 2 : 1;
+  const int sp = storage_of(prec);
+  HIP_TRY(ctx, launch_fill(Y, op->t.M, ncols * cf, ld * cf, sp, ctx->stream));
+  return hx_step(op, prec, X, ld, nullptr, ld, Y, ld, ncols, 1.0, 0.0, 0.0, false);
+}
+
+int chfsi_bounds(chfsi_op* op, int32_t steps, const void* v0, uint64_t seed, double* b_upper, double* lmin_est) {
+  if (!op) return CHFSI_EINVAL;
+  if (steps < 1 || steps > 1000) return fail(op->ctx, CHFSI_EINVAL, "steps must be in [1, 1000]");
+  if (!b_upper) return fail(op->ctx, CHFSI_EINVAL, "null output");
+  return do_bounds(op, steps, static_cast<const double*>(v0), nullptr, seed, b_upper, lmin_est);
+}
+
+int chfsi_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int32_t m, double a, double b, double aL,
+                 int32_t prec, int32_t block) {
+  if (!op) return CHFSI_EINVAL;
+  CHECK(check_block(op, X, ncols, ld));
+  if (!prec_valid_for(op, prec)) return fail(op->ctx, CHFSI_EINVAL, "precision does not match the operator");
+  if (m < 1) return fail(op->ctx, CHFSI_EINVAL, "degree m must be >= 1");
+  if (!(aL < a && a < b) || !std::isfinite(aL) || !std::isfinite(b))
+    return fail(op->ctx, CHFSI_EINVAL, "need aL < a < b");
+  if (prec == CHFSI_BF16) return fail(op->ctx, CHFSI_EINVAL, "bf16 filter not available in this build");
+  return do_filter(op, X, ncols, ld, m, a, b, aL, prec, block);
+}
+
+int chfsi_orthonormalize(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double* L_host) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  const int cf = op->t.cplx ? 2 : 1;
+  void* X2;
+  CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * ncols * 8 * cf, &X2));
+  CHECK(cholgs(op, static_cast<double*>(X), ld, static_cast<double*>(X2), ncols, ncols, L_host));
+  HIP_TRY(ctx, launch_convert(X, ld * cf, CHFSI_F64, X2, ncols * cf, CHFSI_F64, op->t.M, ncols * cf, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double* theta, double* resid) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  if (!theta) return fail(ctx, CHFSI_EINVAL, "null theta");
+  const int cf = op->t.cplx ? 2 : 1;
+  void* X2;
+  CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * ncols * 8 * cf, &X2));
+  CHECK(rayleigh_ritz(op, static_cast<double*>(X), ld, static_cast<double*>(X2), ncols, ncols, theta, resid));
+  HIP_TRY(ctx, launch_convert(X, ld * cf, CHFSI_F64, X2, ncols * cf, CHFSI_F64, op->t.M, ncols * cf, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, double* theta, double* resid,
+                chfsi_stats* stats) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  if (!prm || !theta) return fail(ctx, CHFSI_EINVAL, "null argument");
+  const HostTables& t = op->t;
+  const int64_t N = static_cast<int64_t>(prm->nwanted) + prm->n_buf;
+  if (prm->nwanted < 1 || prm->n_buf < 0) return fail(ctx, CHFSI_EINVAL, "nwanted >= 1, n_buf >= 0");
+  CHECK(check_block(op, Xv, N, ld));
+  if (prm->m < 1) return fail(ctx, CHFSI_EINVAL, "degree m must be >= 1");
+  if (!prec_valid_for(op, prm->filter_prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
+  if (prm->filter_prec == CHFSI_BF16) return fail(ctx, CHFSI_EINVAL, "bf16 filter not available in this build");
+  if (prm->fixed_passes <= 0 && !(prm->tol > 0.0)) return fail(ctx, CHFSI_EINVAL, "need fixed_passes or tol");
+  const int cf = t.cplx ? 2 : 1;
+  hipEvent_t ev[8];
+  for (auto& e : ev) HIP_TRY(ctx, hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); }
+  } guard{ev};
+  chfsi_stats st;
+  std::memset(&st, 0, sizeof(st));
+  HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
+  double b = prm->b_upper;
+  if (!(b > 0.0)) {
+    const int steps = prm->lanczos_steps > 0 ? prm->lanczos_steps : 20;
+    double lmin;
+    CHECK(do_bounds(op, steps, nullptr, prm->lanczos_v0, prm->seed, &b, &lmin));
+    st.hx_columns += steps;
+  }
+  HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+  st.t_bounds = 0.0;
+  double* X = static_cast<double*>(Xv);
+  void* X2v;
+  CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(t.M) * N * 8 * cf, &X2v));
+  double* X2 = static_cast<double*>(X2v);
+  std::vector<double> th(N), r(N);
+  // initial CholGS + RR: X -> X2 (orthonormal) -> X (Ritz vectors)
+  CHECK(cholgs(op, X, ld, X2, N, N, nullptr));
+  CHECK(rayleigh_ritz(op, X2, N, X, ld, N, th.data(), r.data()));
+  st.hx_columns += N;
+  auto max_r = [&]() {
+    double m = 0.0;
+    for (int i = 0; i < prm->nwanted; ++i) m = std::max(m, r[i]);
+    return m;
+  };
+  const int limit = prm->fixed_passes > 0 ? prm->fixed_passes : (prm->max_passes > 0 ? prm->max_passes : 100);
+  int passes = 0;
+  double a = th[N - 1], aL = th[0];
+  while (passes < limit) {
+    if (prm->fixed_passes <= 0 && max_r() <= prm->tol) break;
+    a = th[N - 1];
+    aL = th[0];
+    if (!(aL < a && a < b)) return fail(ctx, CHFSI_EDIVERGE, "filter interval collapsed (b below the Ritz values?)");
+    HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
+    CHECK(do_filter(op, X, N, ld, prm->m, a, b, aL, prm->filter_prec, prm->block));
+    HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
+    CHECK(cholgs(op, X, ld, X2, N, N, nullptr));
+    HIP_TRY(ctx, hipEventRecord(ev[4], ctx->stream));
+    CHECK(rayleigh_ritz(op, X2, N, X, ld, N, th.data(), r.data()));
+    HIP_TRY(ctx, hipEventRecord(ev[5], ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(ev[5]));
+    st.t_filter += event_ms(ev[2], ev[3]);
+    st.t_cholgs += event_ms(ev[3], ev[4]);
+    st.t_rr += event_ms(ev[4], ev[5]);
+    st.hx_columns += static_cast<int64_t>(N) * prm->m + N;
+    ++passes;
+    for (int64_t i = 0; i < N; ++i)
+      if (!std::isfinite(th[i]) || !std::isfinite(r[i]))
+        return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
+  }
+  HIP_TRY(ctx, hipEventRecord(ev[6], ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(ev[6]));
+  st.t_bounds = event_ms(ev[0], ev[1]);
+  st.t_total = event_ms(ev[0], ev[6]);
+  st.passes = passes;
+  st.b_upper = b;
+  st.a_last = a;
+  st.aL_last = aL;
+  st.max_resid = max_r();
+  st.hx_flops = static_cast<double>(st.hx_columns) * 2.0 * t.mcell * t.mcell * t.E * (t.cplx ? 4.0 : 1.0);
+  std::memcpy(theta, th.data(), N * 8);
+  if (resid) std::memcpy(resid, r.data(), N * 8);
+  if (stats) *stats = st;
+  if (prm->fixed_passes <= 0 && st.max_resid > prm->tol) {
+    ctx->err = "tolerance not met";
+    return CHFSI_NOTCONV;
+  }
+  return 0;
+}
+
+}  // extern "C"

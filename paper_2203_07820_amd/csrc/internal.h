@@ -1,0 +1,133 @@
+// Internal declarations shared by the host driver and the HIP kernels of
+// libchfsi.  Not part of the public ABI (include/chfsi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chfsi.h"
+
+namespace chfsi {
+
+// Orders with compiled cell kernels.
+constexpr int kMinOrder = 2;
+constexpr int kMaxOrder = 7;
+
+inline int mcell_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
+// Cell rows/k padded to a multiple of 16 (MFMA row tiles and 4-wide k steps).
+inline int mpad_of(int p) { return (mcell_of(p) + 15) / 16 * 16; }
+
+// Host-side tables of one operator (everything the kernels read).
+struct HostTables {
+  int p = 0, ncell = 0, n = 0;
+  int64_t M = 0, E = 0;
+  int mcell = 0, mpad = 0;
+  bool cplx = false;
+  double L = 0.0, h = 0.0, k[3] = {0, 0, 0};
+  std::vector<double> x1d;          // n node coordinates along one axis
+  std::vector<double> cell_re;      // mcell x mcell
+  std::vector<double> cell_im;      // mcell x mcell (complex only)
+  std::vector<double> dscale;       // per node M^-1/2 (M)
+  std::vector<double> vdiag;        // V + |k|^2/2 (M)
+  int natoms = 0;
+  bool has_proj = false;
+  std::vector<double> hcoef;        // 4 * natoms couplings
+  // atom-major projector node lists: for atom a, entries
+  // [atom_ptr[a], atom_ptr[a+1]) of (node, 4 values c~ (x2 if complex)).
+  std::vector<int64_t> atom_ptr;
+  std::vector<int32_t> atom_node;
+  std::vector<double> atom_val;     // per entry 4 (real) or 8 (re,im x 4)
+  // (cell, atom) pairs sorted by cell, with the cell-local projector matrix
+  // (mcell x 4, split by node multiplicity) in MFMA operand layout.
+  std::vector<int32_t> pair_ptr;    // E + 1
+  std::vector<int32_t> pair_atom;   // npairs
+  std::vector<double> pair_re;      // npairs * (mpad/16) * 64
+  std::vector<double> pair_im;      // complex only
+};
+
+// Builds the tables on the host (op_build.cpp).  Returns "" or an error text.
+std::string build_tables(const chfsi_system& sys, HostTables& t);
+
+// Swizzles a row-major mcell x mcell matrix into MFMA A-operand layout:
+// out[(rt * ks_count + ks) * 64 + lane] = A[rt*16 + lane%16][ks*4 + lane/16].
+void swizzle_cell_matrix(const double* A, int mcell, int mpad, double* out);
+
+// ---- kernel launchers (kernels_hx.hip, kernels_dense.hip) -----------------
+
+struct HxLaunch {
+  int p, nc;                       // order, cells per side
+  int ncols;                       // real columns (2x complex columns)
+  bool cplx;
+  const void* A;                   // swizzled real part
+  const void* Ai;                  // swizzled imaginary part (complex)
+  const double* vdiag;             // V + |k|^2/2
+  const void* Xk; int64_t ldx;     // X_k (real view)
+  const void* Xp; int64_t ldp;     // X_{k-1} (nullable)
+  void* T; int64_t ldt;            // accumulation target
+  bool zero_prev;                  // owners write 0 into Xp after reading it
+  double alpha, c, beta;
+  // nonlocal (nullable when no projectors)
+  const int32_t* pair_ptr; const int32_t* pair_atom;
+  const void* pair_re; const void* pair_im;
+  const void* hP; int64_t ldhp;    // scaled projector coefficients (real view)
+};
+
+// prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).
+hipError_t launch_cell_hx(const HxLaunch& a, int prec, hipStream_t s);
+
+struct NlLaunch {
+  int natoms;
+  bool cplx;
+  int ncols;                        // complex or real columns (logical)
+  const int64_t* atom_ptr; const int32_t* atom_node; const double* atom_val;
+  const int32_t* chunk_atom; const int64_t* chunk_begin; int nchunks;
+  const int32_t* atom_chunk_ptr;
+  const double* hcoef;
+  const void* X; int64_t ldx;       // logical ld (complex entries for complex)
+  void* partial;                    // nchunks x 4 x ldhp (real view)
+  void* hP; int64_t ldhp;           // natoms*4 x ldhp (real view)
+};
+hipError_t launch_nl_project(const NlLaunch& a, int prec, hipStream_t s);
+
+// Elementwise helpers on row-major blocks (real view).
+hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);
+// dst (type dprec) <- src (type sprec), rows x cols (real view)
+hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, int64_t lds, int sprec,
+                          int64_t rows, int64_t cols, hipStream_t s);
+
+// Dense FP64 kernels on real views.
+// Lower-triangular Gram G = X^T Y (n x n, real view) -> partial buffers then
+// reduced into G (row-major, ldg), upper triangle mirrored.
+size_t gram_partial_bytes(int64_t M, int n);
+hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
+                       double* partial, double* G, int64_t ldg, hipStream_t s);
+// C = X Z, X: M x K (ldx), Z: K x N2 row-major (ldz); upper = Z upper-triangular.
+hipError_t launch_rotate(const double* X, int64_t ldx, const double* Z, int64_t ldz, double* C,
+                         int64_t ldc, int64_t M, int K, int N2, bool upper, hipStream_t s);
+// Residual column sums: partial[chunk][j] = sum_rows |HX[r][j] - th[j] X[r][j]|^2
+// (complex: j indexes complex columns, data interleaved).
+size_t resid_partial_count(int64_t M, int ncols);
+hipError_t launch_resid(const double* HX, int64_t ldh, const double* X, int64_t ldx,
+                        const double* theta, int64_t M, int ncols, bool cplx, double* partial,
+                        int* nchunks_out, hipStream_t s);
+// dot partial sums of two real-view vectors of length n: partial[block]
+int dot_blocks();
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partial, hipStream_t s);
+// y = a*x + b*y over n reals
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+// small matrix helpers (n x n)
+hipError_t launch_transpose(const double* in, double* out, int n, hipStream_t s);
+hipError_t launch_zero_strict_lower(double* A, int n, int64_t lda, hipStream_t s);
+// S[i][j] = G[max(i,j)][min(i,j)] (real symmetric from the lower Gram tiles)
+hipError_t launch_sym_from_lower(const double* G, int64_t ldg, double* S, int n, hipStream_t s);
+// complex Hermitian S (n x n column-major interleaved) from the real-view Gram
+hipError_t launch_gram_combine_complex(const double* G2, int64_t ldg2, double* S, int n, hipStream_t s);
+// real 2n1 x 2n2 expansion of a complex matrix: mode 0 row-major Z, mode 1
+// column-major L^-1 -> Z = L^-H (upper), mode 2 column-major Q -> Z = Q
+hipError_t launch_expand_complex(const double* Z, int n1, int n2, int mode, double* Z2, hipStream_t s);
+
+}  // namespace chfsi

@@ -1,0 +1,408 @@
+// Tall-skinny FP64 subspace kernels of the Rayleigh-Ritz step (DFT-FE 1.0,
+// Section 4.4 and Algorithm 2): the overlap / projected-Hamiltonian Gram
+// products A = X^H Y (lower triangle only, split over rows with a
+// deterministic two-phase reduction, the single-GPU counterpart of the
+// blocked, all-reduced N x B_v slabs), the subspace rotation X' = X Z, and
+// residual column norms.  Complex data is handled through its real view
+// (interleaved re, im): X^H Y and X Z become real products of twice the width
+// whose entries are recombined, which costs exactly the complex flop count.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace chfsi {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register i holds D[4 i + l / 16][l % 16].
+__device__ __forceinline__ d4 mma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int acc_row(int lane, int i) { return 4 * i + lane / 16; }
+
+// ---- Gram: partial[chunk] tile (I, J), I >= J, of X^T Y --------------------
+constexpr int kGT = 128;  // Gram tile
+constexpr int kGK = 16;   // rows per LDS stage
+
+__global__ void __launch_bounds__(256)
+gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y, int64_t ldy,
+            int64_t M, int n, int64_t rows_per_chunk, int npad, double* __restrict__ part) {
+  __shared__ double xs[kGK][kGT];
+  __shared__ double ys[kGK][kGT];
+  const int t = blockIdx.x;
+  // lower-triangular tile index -> (I, J)
+  int I = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int chunk = blockIdx.y;
+  const int64_t m0 = chunk * rows_per_chunk;
+  int64_t m1 = m0 + rows_per_chunk;
+  if (m1 > M) m1 = M;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wi = (wave / 2) * 64, wj = (wave % 2) * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  const int lc = tid % kGT, lr = tid / kGT;  // loader: column, row phase (0..1)
+  const int gi = I * kGT + lc, gj = J * kGT + lc;
+  for (int64_t m = m0; m < m1; m += kGK) {
+#pragma unroll
+    for (int i = 0; i < kGK / 2; ++i) {
+      const int r = lr + 2 * i;
+      const int64_t row = m + r;
+      double xv = 0.0, yv = 0.0;
+      if (row < m1) {
+        if (gi < n) xv = X[row * ldx + gi];
+        if (gj < n) yv = Y[row * ldy + gj];
+      }
+      xs[r][lc] = xv;
+      ys[r][lc] = yv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kGK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = xs[kr][wi + q * 16 + lane % 16];
+        bv[q] = ys[kr][wj + q * 16 + lane % 16];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = part + static_cast<int64_t>(chunk) * npad * npad;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = I * kGT + wi + a * 16 + acc_row(lane, i);
+        const int col = J * kGT + wj + b * 16 + lane % 16;
+        out[static_cast<int64_t>(row) * npad + col] = acc[a][b][i];
+      }
+}
+
+// G[i][j] = sum over chunks, for entries of lower tiles (tile(i) >= tile(j)).
+__global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks, int n, int npad,
+                                   double* __restrict__ G, int64_t ldg) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  if (i / kGT < j / kGT) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += part[(static_cast<int64_t>(c) * npad + i) * npad + j];
+  G[static_cast<int64_t>(i) * ldg + j] = s;
+}
+
+// Real symmetric result from the lower entries: S[i][j] = G[max][min].
+__global__ void sym_from_lower_kernel(const double* __restrict__ G, int64_t ldg, double* __restrict__ S,
+                                      int n) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  const int a = i > j ? i : j, b = i > j ? j : i;
+  S[idx] = G[static_cast<int64_t>(a) * ldg + b];
+}
+
+// Complex Hermitian S (n x n, column-major interleaved) from the real-view
+// Gram G2 (2n x 2n) of interleaved X, Y:
+// S_ij = (G[2i][2j] + G[2i+1][2j+1]) + i (G[2i][2j+1] - G[2i+1][2j]) for
+// i >= j, S_ji = conj(S_ij).
+__global__ void gram_combine_complex_kernel(const double* __restrict__ G, int64_t ldg,
+                                            double* __restrict__ S, int n) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  const int a = i > j ? i : j, b = i > j ? j : i;
+  const double g00 = G[static_cast<int64_t>(2 * a) * ldg + 2 * b];
+  const double g11 = G[static_cast<int64_t>(2 * a + 1) * ldg + 2 * b + 1];
+  const double g01 = G[static_cast<int64_t>(2 * a) * ldg + 2 * b + 1];
+  const double g10 = G[static_cast<int64_t>(2 * a + 1) * ldg + 2 * b];
+  const double re = g00 + g11;
+  double im = g01 - g10;
+  if (i < j) im = -im;   // conjugate for the upper triangle
+  if (i == j) im = 0.0;
+  // column-major: element (i, j) at i + j n
+  const int64_t o = (static_cast<int64_t>(i) + static_cast<int64_t>(j) * n) * 2;
+  S[o] = re;
+  S[o + 1] = im;
+}
+
+// ---- rotation C = X Z --------------------------------------------------------
+constexpr int kRM = 64;   // rows per workgroup
+constexpr int kRN = 128;  // columns per workgroup
+constexpr int kRK = 16;   // k per LDS stage
+
+__global__ void __launch_bounds__(256)
+rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Z, int64_t ldz,
+              double* __restrict__ C, int64_t ldc, int64_t M, int K, int N2, int upper) {
+  __shared__ double xs[kRM][kRK + 1];
+  __shared__ double zs[kRK][kRN];
+  const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRM);
+  const int c0 = blockIdx.y * kRN;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  d4 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+  int kend = K;
+  if (upper && c0 + kRN < kend) kend = c0 + kRN;
+  const int xk = tid % kRK, xr = tid / kRK;        // X loader: 16 k x 16 rows per pass
+  const int zc = tid % kRN, zr = tid / kRN;        // Z loader: 128 cols x 2 rows per pass
+  for (int k0 = 0; k0 < kend; k0 += kRK) {
+#pragma unroll
+    for (int i = 0; i < kRM / 16; ++i) {
+      const int r = xr + 16 * i;
+      const int64_t row = r0 + r;
+      const int k = k0 + xk;
+      xs[r][xk] = (row < M && k < K) ? X[row * ldx + k] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kRK / 2; ++i) {
+      const int r = zr + 2 * i;
+      const int k = k0 + r, c = c0 + zc;
+      zs[r][zc] = (k < K && c < N2) ? Z[static_cast<int64_t>(k) * ldz + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kRK / 4; ++ks) {
+      const double av = xs[wave * 16 + lane % 16][ks * 4 + lane / 16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = mma(av, zs[ks * 4 + lane / 16][q * 16 + lane % 16], acc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = r0 + wave * 16 + acc_row(lane, i);
+      const int col = c0 + q * 16 + lane % 16;
+      if (row < M && col < N2) C[row * ldc + col] = acc[q][i];
+    }
+}
+
+// ---- residual column sums ------------------------------------------------
+__global__ void __launch_bounds__(256)
+resid_kernel(const double* __restrict__ HX, int64_t ldh, const double* __restrict__ X, int64_t ldx,
+             const double* __restrict__ th, int64_t M, int ncols, int cplx, int64_t rows_per_chunk,
+             double* __restrict__ part) {
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= ncols) return;
+  const int64_t m0 = blockIdx.x * rows_per_chunk;
+  int64_t m1 = m0 + rows_per_chunk;
+  if (m1 > M) m1 = M;
+  const double t = th[j];
+  double s = 0.0;
+  if (cplx) {
+    for (int64_t r = m0; r < m1; ++r) {
+      const double dr = HX[(r * ldh + j) * 2] - t * X[(r * ldx + j) * 2];
+      const double di = HX[(r * ldh + j) * 2 + 1] - t * X[(r * ldx + j) * 2 + 1];
+      s += dr * dr + di * di;
+    }
+  } else {
+    for (int64_t r = m0; r < m1; ++r) {
+      const double d = HX[r * ldh + j] - t * X[r * ldx + j];
+      s += d * d;
+    }
+  }
+  part[static_cast<int64_t>(blockIdx.x) * ncols + j] = s;
+}
+
+// ---- vector helpers --------------------------------------------------------
+constexpr int kDotBlocks = 1024;
+
+__global__ void __launch_bounds__(256)
+dot_kernel(const double* __restrict__ x, const double* __restrict__ y, int64_t n, double* part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += static_cast<int64_t>(gridDim.x) * 256)
+    s += x[i] * y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y,
+                             int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void transpose_kernel(const double* __restrict__ in, double* __restrict__ out, int n) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  out[static_cast<int64_t>(j) * n + i] = in[idx];
+}
+
+__global__ void zero_strict_lower_kernel(double* A, int n, int64_t lda) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  if (i > j) A[static_cast<int64_t>(i) * lda + j] = 0.0;
+}
+
+// Real 2n1 x 2n2 expansion of a complex matrix Z (row-major interleaved,
+// Z[k][j] at (k n2 + j)), or of the conjugate of a column-major upper
+// Cholesky-inverse read as row-major, so that [re im] rows times it give the
+// complex product.  mode 0: Z given row-major.  mode 1: src is column-major
+// L^-1 (n1 = n2); Z = L^-H, i.e. Z[k][j] = conj(src[k n + j]) for k <= j,
+// 0 below the diagonal.  mode 2: src is column-major Q (eigenvectors); Z = Q,
+// Z[k][j] = src[k + j n].
+__global__ void expand_complex_kernel(const double* __restrict__ src, int n1, int n2, int mode,
+                                      double* __restrict__ Z2) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n1) * n2) return;
+  const int k = static_cast<int>(idx / n2), j = static_cast<int>(idx % n2);
+  double zr, zi;
+  if (mode == 0) {
+    zr = src[idx * 2];
+    zi = src[idx * 2 + 1];
+  } else if (mode == 1) {
+    if (k > j) {
+      zr = 0.0;
+      zi = 0.0;
+    } else {
+      zr = src[idx * 2];
+      zi = -src[idx * 2 + 1];
+    }
+  } else {
+    const int64_t o = (static_cast<int64_t>(k) + static_cast<int64_t>(j) * n1) * 2;
+    zr = src[o];
+    zi = src[o + 1];
+  }
+  const int64_t ld = 2 * static_cast<int64_t>(n2);
+  Z2[(2 * static_cast<int64_t>(k)) * ld + 2 * j] = zr;
+  Z2[(2 * static_cast<int64_t>(k)) * ld + 2 * j + 1] = zi;
+  Z2[(2 * static_cast<int64_t>(k) + 1) * ld + 2 * j] = -zi;
+  Z2[(2 * static_cast<int64_t>(k) + 1) * ld + 2 * j + 1] = zr;
+}
+
+unsigned blocks_for(int64_t total, int per = 256) {
+  return static_cast<unsigned>((total + per - 1) / per);
+}
+
+int gram_chunks(int64_t M, int n) {
+  const int nt = (n + kGT - 1) / kGT;
+  const int ntiles = nt * (nt + 1) / 2;
+  int64_t ch = (1024 + ntiles - 1) / ntiles;
+  const int64_t max_ch = (M + 255) / 256;  // at least 256 rows per chunk
+  if (ch > max_ch) ch = max_ch;
+  if (ch < 1) ch = 1;
+  return static_cast<int>(ch);
+}
+
+}  // namespace
+
+size_t gram_partial_bytes(int64_t M, int n) {
+  const int npad = (n + kGT - 1) / kGT * kGT;
+  return static_cast<size_t>(gram_chunks(M, n)) * npad * npad * sizeof(double);
+}
+
+hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
+                       double* partial, double* G, int64_t ldg, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int nt = (n + kGT - 1) / kGT;
+  const int ntiles = nt * (nt + 1) / 2;
+  const int npad = nt * kGT;
+  const int nch = gram_chunks(M, n);
+  int64_t rpc = (M + nch - 1) / nch;
+  rpc = (rpc + kGK - 1) / kGK * kGK;
+  hipLaunchKernelGGL(gram_kernel, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
+                     partial, nch, n, npad, G, ldg);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_from_lower(const double* G, int64_t ldg, double* S, int n, hipStream_t s) {
+  hipLaunchKernelGGL(sym_from_lower_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
+                     G, ldg, S, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_combine_complex(const double* G2, int64_t ldg2, double* S, int n, hipStream_t s) {
+  hipLaunchKernelGGL(gram_combine_complex_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0,
+                     s, G2, ldg2, S, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate(const double* X, int64_t ldx, const double* Z, int64_t ldz, double* C, int64_t ldc,
+                         int64_t M, int K, int N2, bool upper, hipStream_t s) {
+  if (M <= 0 || N2 <= 0) return hipSuccess;
+  const int64_t gx = (M + kRM - 1) / kRM;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rotate_kernel, dim3(static_cast<unsigned>(gx), (N2 + kRN - 1) / kRN), dim3(256), 0, s, X,
+                     ldx, Z, ldz, C, ldc, M, K, N2, upper ? 1 : 0);
+  return hipGetLastError();
+}
+
+size_t resid_partial_count(int64_t M, int ncols) {
+  (void)M;
+  const int ny = (ncols + 255) / 256;
+  int nch = 1024 / ny;
+  if (nch < 1) nch = 1;
+  return static_cast<size_t>(nch) * ncols;
+}
+
+hipError_t launch_resid(const double* HX, int64_t ldh, const double* X, int64_t ldx, const double* theta,
+                        int64_t M, int ncols, bool cplx, double* partial, int* nchunks_out, hipStream_t s) {
+  const int ny = (ncols + 255) / 256;
+  int nch = 1024 / ny;
+  if (nch < 1) nch = 1;
+  const int64_t rpc = (M + nch - 1) / nch;
+  *nchunks_out = nch;
+  hipLaunchKernelGGL(resid_kernel, dim3(nch, ny), dim3(256), 0, s, HX, ldh, X, ldx, theta, M, ncols,
+                     cplx ? 1 : 0, rpc, partial);
+  return hipGetLastError();
+}
+
+int dot_blocks() { return kDotBlocks; }
+
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel, dim3(kDotBlocks), dim3(256), 0, s, x, y, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(axpby_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* in, double* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(transpose_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s, in, out,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_strict_lower(double* A, int n, int64_t lda, hipStream_t s) {
+  hipLaunchKernelGGL(zero_strict_lower_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
+                     A, n, lda);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_complex(const double* Z, int n1, int n2, int mode, double* Z2, hipStream_t s) {
+  hipLaunchKernelGGL(expand_complex_kernel, dim3(blocks_for(static_cast<int64_t>(n1) * n2)), dim3(256), 0, s,
+                     Z, n1, n2, mode, Z2);
+  return hipGetLastError();
+}
+
+}  // namespace chfsi

@@ -1,0 +1,472 @@
+// Cell-wise H~.X on gfx950 (DFT-FE 1.0, Section 4.3, Eq. celldgemm and
+// Algorithm 4), fused with one step of the scaled Chebyshev recurrence
+// (Section 3.1).
+//
+// One workgroup owns one hexahedral cell and a 64-wide tile of columns.  It
+//   1. gathers the cell's nodal rows X^c (node-major, 64 contiguous values per
+//      node) through LDS in 16-row chunks, double buffered;
+//   2. multiplies the shared reference cell matrix A (mcell x mcell, streamed
+//      from L2 in MFMA operand order) by X^c with 16x16x4 MFMA (f64 or f32),
+//      accumulating in registers; for complex operators A_r X + A_i X' where
+//      X' is X with (re, im) -> (-im, re);
+//   3. adds the nonlocal term C^{c,a} (h P_a) for every atom a whose
+//      projectors touch the cell, as extra 4-wide k steps (Algorithm 4 steps
+//      5-6, with P_a from the node-level contraction below);
+//   4. scatters alpha * Y^c into the target with atomic adds (ASEMB_FEM).
+//      The owner cell of each node (local indices all < p) also adds
+//      alpha (V_j - c) X_k[j] - beta X_{k-1}[j], so the target ends up holding
+//      X_{k+1} = alpha (H~ X_k - c X_k) - beta X_{k-1} without a separate pass;
+//      the owner then zeroes X_{k-1}[j], which becomes the target two steps on.
+//
+// Node numbering: n = ncell * p nodes per direction, node (ix, iy, iz) has id
+// ix + n (iy + n iz); cell (cx, cy, cz) local node (a, b, c) is global node
+// ((cx p + a) mod n, ...).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace chfsi {
+namespace {
+
+constexpr int kNT = 64;     // columns per workgroup tile
+constexpr int kKC = 16;     // cell rows (k values) per LDS chunk
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mma;
+// Operand layouts (both types): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Accumulator register i of lane l holds D[row][l % 16]
+// with row = 4 i + l / 16 for f64 and row = 4 (l / 16) + i for f32.
+template <> struct Mma<double> {
+  typedef d4 acc_t;
+  __device__ __forceinline__ static acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * i + lane / 16; }
+};
+template <> struct Mma<float> {
+  typedef f4 acc_t;
+  __device__ __forceinline__ static acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane / 16) + i; }
+};
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD works on a contiguous range of cells (neighbouring cells share nodes,
+// which then hit the same L2).
+__device__ __forceinline__ int xcd_remap(int pid, int nblk) {
+  const int q = nblk / 8, r = nblk % 8;
+  const int xcd = pid % 8, slot = pid / 8;
+  return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+template <typename T>
+struct HxArgs {
+  const T* A;
+  const T* Ai;
+  const double* vdiag;
+  const T* Xk;
+  const T* Xp;
+  T* Tg;
+  int64_t ldx, ldp, ldt;
+  int ncols, nc;
+  int zero_prev;
+  T alpha, c, beta;
+  const int32_t* pair_ptr;
+  const int32_t* pair_atom;
+  const T* pair_re;
+  const T* pair_im;
+  const T* hP;
+  int64_t ldhp;
+};
+
+template <int P, typename T, bool CPLX, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+cell_hx_kernel(const HxArgs<T> a) {
+  constexpr int Q = P + 1;
+  constexpr int MC = Q * Q * Q;
+  constexpr int MP = (MC + 15) / 16 * 16;
+  constexpr int RT = MP / 16;           // row tiles
+  constexpr int KS = MP / 4;            // 4-wide k steps
+  constexpr int NCH = MP / kKC;         // LDS chunks
+  constexpr int RW = (RT + WAVES - 1) / WAVES;  // row tiles per wave
+  using acc_t = typename Mma<T>::acc_t;
+
+  __shared__ T xs[2][kKC][kNT];
+
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int nc = a.nc, n = nc * P;
+  const int E = nc * nc * nc;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int cell = bid % E;
+  const int col0 = (bid / E) * kNT;
+  const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
+
+  auto gnode = [&](int l) -> int64_t {
+    const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
+    int gx = cx * P + la; if (gx >= n) gx -= n;
+    int gy = cy * P + lb; if (gy >= n) gy -= n;
+    int gz = cz * P + lc; if (gz >= n) gz -= n;
+    return gx + static_cast<int64_t>(n) * (gy + static_cast<int64_t>(n) * gz);
+  };
+
+  // gather: thread owns column `lane` of rows wave, wave + WAVES, ...
+  T g[kKC / WAVES];
+  const bool col_ok = (col0 + lane) < a.ncols;
+  auto load_chunk = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < kKC / WAVES; ++i) {
+      const int l = ch * kKC + wave + WAVES * i;
+      T v = T(0);
+      if (l < MC && col_ok) v = a.Xk[gnode(l) * a.ldx + col0 + lane];
+      g[i] = v;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kKC / WAVES; ++i) xs[buf][wave + WAVES * i][lane] = g[i];
+  };
+
+  acc_t acc[RW][4];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = acc_t{0, 0, 0, 0};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < NCH) load_chunk(ch + 1);
+#pragma unroll
+    for (int ks = 0; ks < kKC / 4; ++ks) {
+      const int krow = ks * 4 + lane / 16;
+      T b[4], bs[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int cc = ct * 16 + lane % 16;
+        b[ct] = xs[buf][krow][cc];
+        if constexpr (CPLX) {
+          const T o = xs[buf][krow][cc ^ 1];
+          bs[ct] = (cc & 1) ? o : -o;
+        }
+      }
+      const int kg = ch * (kKC / 4) + ks;
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int rt = wave + WAVES * r;
+        if (rt < RT) {
+          const T av = a.A[(static_cast<int64_t>(rt) * KS + kg) * 64 + lane];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(av, b[ct], acc[r][ct]);
+          if constexpr (CPLX) {
+            const T ai = a.Ai[(static_cast<int64_t>(rt) * KS + kg) * 64 + lane];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(ai, bs[ct], acc[r][ct]);
+          }
+        }
+      }
+    }
+    if (ch + 1 < NCH) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell
+  if (a.pair_ptr != nullptr) {
+    const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
+    for (int pr = p0; pr < p1; ++pr) {
+      const int at = a.pair_atom[pr];
+      T b[4], bs[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int cc = ct * 16 + lane % 16;
+        const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
+        b[ct] = hrow[cc];
+        if constexpr (CPLX) {
+          const T o = hrow[cc ^ 1];
+          bs[ct] = (cc & 1) ? o : -o;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int rt = wave + WAVES * r;
+        if (rt < RT) {
+          const T cv = a.pair_re[(static_cast<int64_t>(pr) * RT + rt) * 64 + lane];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(cv, b[ct], acc[r][ct]);
+          if constexpr (CPLX) {
+            const T ci = a.pair_im[(static_cast<int64_t>(pr) * RT + rt) * 64 + lane];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(ci, bs[ct], acc[r][ct]);
+          }
+        }
+      }
+    }
+  }
+
+  // epilogue: scale, owner terms, atomic assembly
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int rt = wave + WAVES * r;
+    if (rt >= RT) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rt * 16 + Mma<T>::row(lane, i);
+      if (row >= MC) continue;
+      const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
+      const bool owner = (la < P) && (lb < P) && (lc < P);
+      const int64_t gn = gnode(row);
+      T vc = T(0);
+      if (owner) vc = a.alpha * (static_cast<T>(a.vdiag[gn]) - a.c);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int col = col0 + ct * 16 + lane % 16;
+        if (col >= a.ncols) continue;
+        T v = a.alpha * acc[r][ct][i];
+        if (owner) {
+          v += vc * a.Xk[gn * a.ldx + col];
+          if (a.Xp != nullptr) {
+            T* xp = const_cast<T*>(a.Xp) + gn * a.ldp + col;
+            v -= a.beta * (*xp);
+            if (a.zero_prev) *xp = T(0);
+          }
+        }
+        atomic_add(a.Tg + gn * a.ldt + col, v);
+      }
+    }
+  }
+}
+
+template <int P, typename T, bool CPLX>
+hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
+  HxArgs<T> a;
+  a.A = static_cast<const T*>(L.A);
+  a.Ai = static_cast<const T*>(L.Ai);
+  a.vdiag = L.vdiag;
+  a.Xk = static_cast<const T*>(L.Xk);
+  a.Xp = static_cast<const T*>(L.Xp);
+  a.Tg = static_cast<T*>(L.T);
+  a.ldx = L.ldx;
+  a.ldp = L.ldp;
+  a.ldt = L.ldt;
+  a.ncols = L.ncols;
+  a.nc = L.nc;
+  a.zero_prev = L.zero_prev ? 1 : 0;
+  a.alpha = static_cast<T>(L.alpha);
+  a.c = static_cast<T>(L.c);
+  a.beta = static_cast<T>(L.beta);
+  a.pair_ptr = L.pair_ptr;
+  a.pair_atom = L.pair_atom;
+  a.pair_re = static_cast<const T*>(L.pair_re);
+  a.pair_im = static_cast<const T*>(L.pair_im);
+  a.hP = static_cast<const T*>(L.hP);
+  a.ldhp = L.ldhp;
+  const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
+  const int64_t nct = (L.ncols + kNT - 1) / kNT;
+  const int64_t nblk = E * nct;
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
+  constexpr int WAVES = RT > 24 ? 8 : 4;
+  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES>), dim3(static_cast<unsigned>(nblk)),
+                     dim3(64 * WAVES), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool CPLX>
+hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
+  switch (L.p) {
+    case 2: return launch_p<2, T, CPLX>(L, s);
+    case 3: return launch_p<3, T, CPLX>(L, s);
+    case 4: return launch_p<4, T, CPLX>(L, s);
+    case 5: return launch_p<5, T, CPLX>(L, s);
+    case 6: return launch_p<6, T, CPLX>(L, s);
+    case 7: return launch_p<7, T, CPLX>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---- node-level projector contraction (Algorithm 4 steps 1-4) -------------
+// P_a = h_a * sum_j conj(c~_{a,j}) X[j, :], computed from atom-major node
+// lists (each node row read once per atom), in two deterministic phases:
+// fixed-size chunks of an atom's list give partial sums, then the chunks of
+// each atom are summed in order and scaled by the couplings.
+constexpr int kNlChunk = 512;
+
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256)
+nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const int64_t* atom_ptr,
+                  const int32_t* atom_node, const double* atom_val, const T* X, int64_t ldx,
+                  int ncols, T* partial, int64_t ldhp) {
+  __shared__ T red[4][CPLX ? 8 : 4][64];
+  const int chunk = blockIdx.x;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int col = blockIdx.y * 64 + lane;  // logical column
+  const int at = chunk_atom[chunk];
+  const int64_t e0 = chunk_begin[chunk];
+  int64_t e1 = e0 + kNlChunk;
+  if (e1 > atom_ptr[at + 1]) e1 = atom_ptr[at + 1];
+  constexpr int NV = CPLX ? 8 : 4;
+  T acc[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) acc[m] = T(0);
+  if (col < ncols) {
+    for (int64_t e = e0 + wave; e < e1; e += 4) {
+      const int64_t j = atom_node[e];
+      const double* v = atom_val + e * NV;
+      if constexpr (CPLX) {
+        const T xr = X[(j * ldx + col) * 2], xi = X[(j * ldx + col) * 2 + 1];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const T cr = static_cast<T>(v[2 * m]), ci = static_cast<T>(v[2 * m + 1]);
+          acc[2 * m] += cr * xr + ci * xi;       // conj(c) x, real part
+          acc[2 * m + 1] += cr * xi - ci * xr;   // imaginary part
+        }
+      } else {
+        const T x = X[j * ldx + col];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[m] += static_cast<T>(v[m]) * x;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NV; ++m) red[wave][m][lane] = acc[m];
+  __syncthreads();
+  if (wave == 0 && col < ncols) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const T s = ((red[0][m][lane] + red[1][m][lane]) + red[2][m][lane]) + red[3][m][lane];
+      if constexpr (CPLX) {
+        partial[(static_cast<int64_t>(chunk) * 4 + m / 2) * ldhp + 2 * col + (m & 1)] = s;
+      } else {
+        partial[(static_cast<int64_t>(chunk) * 4 + m) * ldhp + col] = s;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* partial, T* hP,
+                 int64_t ldhp, int nreal) {
+  const int am = blockIdx.x;  // atom * 4 + component
+  const int at = am / 4, m = am % 4;
+  const int j = blockIdx.y * 256 + threadIdx.x;
+  if (j >= ldhp) return;
+  T s = T(0);
+  if (j < nreal) {
+    for (int ch = atom_chunk_ptr[at]; ch < atom_chunk_ptr[at + 1]; ++ch)
+      s += partial[(static_cast<int64_t>(ch) * 4 + m) * ldhp + j];
+    s *= static_cast<T>(hcoef[am]);
+  }
+  hP[static_cast<int64_t>(am) * ldhp + j] = s;
+}
+
+template <typename T, bool CPLX>
+hipError_t nl_launch(const NlLaunch& L, hipStream_t s) {
+  if (L.nchunks <= 0) return hipSuccess;
+  const int nct = (L.ncols + 63) / 64;
+  hipLaunchKernelGGL((nl_partial_kernel<T, CPLX>), dim3(L.nchunks, nct), dim3(256), 0, s,
+                     L.chunk_atom, L.chunk_begin, L.atom_ptr, L.atom_node, L.atom_val,
+                     static_cast<const T*>(L.X), L.ldx, L.ncols, static_cast<T*>(L.partial), L.ldhp);
+  const int nreal = CPLX ? 2 * L.ncols : L.ncols;
+  hipLaunchKernelGGL((nl_reduce_kernel<T>), dim3(L.natoms * 4, (L.ldhp + 255) / 256), dim3(256), 0, s,
+                     L.atom_chunk_ptr, L.hcoef, static_cast<const T*>(L.partial), static_cast<T*>(L.hP),
+                     L.ldhp, nreal);
+  return hipGetLastError();
+}
+
+// ---- elementwise helpers ----------------------------------------------------
+template <typename T>
+__global__ void fill_kernel(T* dst, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / cols, c = i % cols;
+    dst[r * ld + c] = T(0);
+  }
+}
+
+template <typename TD, typename TS>
+__global__ void convert_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds, int64_t rows,
+                               int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / cols, c = i % cols;
+    dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
+  }
+}
+
+inline bool is_double(int prec) { return prec == CHFSI_F64 || prec == CHFSI_C128; }
+
+unsigned grid_for(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return static_cast<unsigned>(g);
+}
+
+}  // namespace
+
+hipError_t launch_cell_hx(const HxLaunch& L, int prec, hipStream_t s) {
+  if (L.p < kMinOrder || L.p > kMaxOrder) return hipErrorInvalidValue;
+  switch (prec) {
+    case CHFSI_F64: return launch_t<double, false>(L, s);
+    case CHFSI_F32: return launch_t<float, false>(L, s);
+    case CHFSI_C128: return launch_t<double, true>(L, s);
+    case CHFSI_C64: return launch_t<float, true>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_nl_project(const NlLaunch& L, int prec, hipStream_t s) {
+  switch (prec) {
+    case CHFSI_F64: return nl_launch<double, false>(L, s);
+    case CHFSI_F32:
+    case CHFSI_BF16: return nl_launch<float, false>(L, s);
+    case CHFSI_C128: return nl_launch<double, true>(L, s);
+    case CHFSI_C64: return nl_launch<float, true>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const unsigned g = grid_for(rows * cols);
+  if (is_double(prec))
+    hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(dst), rows, cols, ld);
+  else
+    hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(dst), rows, cols, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, int64_t lds, int sprec,
+                          int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const unsigned g = grid_for(rows * cols);
+  const bool dd = is_double(dprec), sd = is_double(sprec);
+  if (dd && sd)
+    hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
+                       static_cast<const double*>(src), lds, rows, cols);
+  else if (dd && !sd)
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
+                       static_cast<const float*>(src), lds, rows, cols);
+  else if (!dd && sd)
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
+                       static_cast<const double*>(src), lds, rows, cols);
+  else
+    hipLaunchKernelGGL((convert_kernel<float, float>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
+                       static_cast<const float*>(src), lds, rows, cols);
+  return hipGetLastError();
+}
+
+}  // namespace chfsi

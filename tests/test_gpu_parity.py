@@ -1,0 +1,249 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances.  FP64 paths: the cell products sum at most 8 * mcell terms of
+size |A| |X| per entry, so rounding stays below 1e-13 of max|Y|; the tests
+use 1e-12 relative to the max-norm.  Single-precision paths: unit roundoff
+6e-8 times the same growth, tested at 2e-5 relative.  Eigenvalues after
+the same number of passes: 1e-8 Ha (FP64).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import chfsi as ochfsi
+from oracle import fe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2203_07820_amd as lib  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+SMALL = [
+    # (ncell, p, natoms, proj, k, seed)
+    (2, 2, 1, False, (0, 0, 0), 1),
+    (3, 3, 2, True, (0, 0, 0), 2),
+    (2, 4, 2, True, (0, 0, 0), 3),
+    (3, 5, 3, True, (0, 0, 0), 4),
+    (2, 6, 2, True, (0, 0, 0), 5),
+    (3, 4, 2, True, (0.1, -0.2, 0.3), 6),
+    (2, 5, 2, True, (0.25, 0.0, -0.1), 7),
+    (2, 7, 1, True, (0, 0, 0), 8),
+]
+
+
+def _sys(nc, p, na, proj, k, seed, L=None):
+    return workloads.small_system(nc, p, na, seed=seed, has_proj=proj, k=k, L=L)
+
+
+@pytest.mark.parametrize("case", SMALL)
+def test_operator_tables_match_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    t = op.tables()
+    assert op.M == ref.M and op.E == ref.E
+    assert np.max(np.abs(t["xyz"] - fe.node_coords(s.ncell, s.p, s.L))) < 1e-13
+    assert relerr(t["dscale"], ref.D) < 1e-14
+    assert np.max(np.abs(t["vdiag"] - (ref.V + 0.5 * ref.k @ ref.k))) < 1e-13
+    # the GPU's shared cell matrix is D_c (K^c/2 - i skew(k.G^c)/2) D_c
+    Dc = ref.D[ref.cells[0]]
+    Ge = np.einsum("a,aij->ij", ref.k, ref.ct.G)
+    A = Dc[:, None] * (0.5 * ref.ct.K - 0.5j * (Ge - Ge.T)) * Dc[None, :]
+    if not op.is_complex:
+        A = A.real
+    assert relerr(t["cell"], A) < 1e-13
+
+
+@pytest.mark.parametrize("case", SMALL)
+@pytest.mark.parametrize("ncols", [1, 37, 64, 130])
+def test_apply_fp64_matches_oracle(ctx, case, ncols):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    H = fe.assemble(ref)
+    X = workloads.start_block(op.M, ncols, seed=100 + ncols, complex_=op.is_complex)
+    Y = np.zeros_like(X)
+    Xd, Yd = dev(X), dev(Y)
+    op.apply(Xd, Yd)
+    Yg = host(Yd)
+    assert relerr(Yg, H @ X) < 1e-12
+
+
+@pytest.mark.parametrize("case", [SMALL[2], SMALL[4], SMALL[5]])
+def test_apply_with_leading_dimension(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    X = workloads.start_block(op.M, 50, seed=3, complex_=op.is_complex)
+    Xd = dev(X)
+    Yd = torch.zeros_like(Xd)
+    # a 20-column view with ld = 50 is not contiguous: use a padded copy
+    Xs, Ys = Xd[:, :20], Yd[:, :20]
+    ncols, ld = 20, 50
+    op.ctx.check(op.ctx.lib.chfsi_apply(op.h, lib._tptr(Xd), lib._tptr(Yd), ncols, ld,
+                                        lib.C128 if op.is_complex else lib.F64))
+    Yg = host(Yd)
+    assert relerr(Yg[:, :20], H @ X[:, :20]) < 1e-12
+    assert np.all(Yg[:, 20:] == 0)
+    del Xs, Ys
+
+
+@pytest.mark.parametrize("case", [SMALL[1], SMALL[4], SMALL[5]])
+def test_apply_fp32_matches_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    X = workloads.start_block(op.M, 70, seed=11, complex_=op.is_complex)
+    dt = np.complex64 if op.is_complex else np.float32
+    Xd = dev(X.astype(dt))
+    Yd = torch.zeros_like(Xd)
+    op.apply(Xd, Yd, lib.C64 if op.is_complex else lib.F32)
+    Yg = host(Yd).astype(np.complex128 if op.is_complex else np.float64)
+    ref = H @ X.astype(dt).astype(X.dtype)
+    assert relerr(Yg, ref) < 2e-5
+
+
+@pytest.mark.parametrize("case", [SMALL[1], SMALL[3], SMALL[5]])
+def test_filter_fp64_matches_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    lam = np.linalg.eigvalsh(H.toarray())
+    X = workloads.start_block(op.M, 24, seed=5, complex_=op.is_complex)
+    a, b, aL = lam[24], lam[-1] * 1.05, lam[0]
+    Yref = ochfsi.cheb_filter(lambda v: H @ v, X, 12, a, b, aL)
+    Xd = dev(X)
+    op.filter(Xd, 12, a, b, aL, block=10)
+    assert relerr(host(Xd), Yref) < 1e-11
+
+
+def test_filter_fp32_close_to_oracle(ctx):
+    s = _sys(*SMALL[3])
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    lam = np.linalg.eigvalsh(H.toarray())
+    X = workloads.start_block(op.M, 16, seed=6)
+    a, b, aL = lam[16], lam[-1] * 1.05, lam[0]
+    Yref = ochfsi.cheb_filter(lambda v: H @ v, X, 10, a, b, aL)
+    Xd = dev(X)
+    op.filter(Xd, 10, a, b, aL, prec=lib.F32)
+    assert relerr(host(Xd), Yref) < 1e-4
+
+
+@pytest.mark.parametrize("case", [SMALL[2], SMALL[5]])
+def test_orthonormalize_matches_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    X = workloads.start_block(op.M, 40, seed=8, complex_=op.is_complex)
+    Xo, Lref, _ = ochfsi.cholgs(X)
+    Xd = dev(X)
+    L = op.orthonormalize(Xd, want_L=True)
+    assert relerr(host(Xd), Xo) < 1e-12
+    assert relerr(L, Lref) < 1e-12
+
+
+def test_orthonormalize_rank_deficient_fails(ctx):
+    s = _sys(*SMALL[1])
+    op = lib.Operator(ctx, s)
+    X = workloads.start_block(op.M, 10, seed=9)
+    X[:, 4] = X[:, 2]
+    Xd = dev(X)
+    with pytest.raises(lib.ChfsiError) as ei:
+        op.orthonormalize(Xd)
+    assert ei.value.code == -4
+    assert np.array_equal(host(Xd), X)
+
+
+@pytest.mark.parametrize("case", [SMALL[2], SMALL[5]])
+def test_rayleigh_ritz_matches_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    X = workloads.start_block(op.M, 30, seed=10, complex_=op.is_complex)
+    Xo, _, _ = ochfsi.cholgs(X)
+    th_ref, Psi_ref, _, r_ref, _ = ochfsi.rayleigh_ritz(lambda v: H @ v, Xo)
+    Xd = dev(Xo)
+    th, r = op.rayleigh_ritz(Xd)
+    assert np.max(np.abs(th - th_ref)) < 1e-11 * max(1.0, np.max(np.abs(th_ref)))
+    assert np.max(np.abs(r - r_ref)) < 1e-10
+    Psi = host(Xd)
+    # vectors are unique up to a unit phase per column (distinct Ritz values)
+    ph = np.sum(Psi.conj() * Psi_ref, axis=0)
+    ph = ph / np.abs(ph)
+    assert relerr(Psi * ph[None, :], Psi_ref) < 1e-9
+
+
+@pytest.mark.parametrize("case", [SMALL[2], SMALL[5]])
+def test_bounds_match_oracle(ctx, case):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    v0 = workloads.lanczos_start(op.M, seed=44, complex_=op.is_complex)
+    b_ref, tmin, _, _ = ochfsi.lanczos_bound(lambda v: H @ v, v0, 20)
+    b, lmin = op.bounds(20, dev(v0))
+    assert abs(b - b_ref) < 1e-9 * abs(b_ref)
+    assert abs(lmin - tmin) < 1e-9 * max(1.0, abs(tmin))
+    assert b >= np.linalg.eigvalsh(H.toarray())[-1]
+
+
+def test_solve_config0_matches_oracle_pass_by_pass(ctx):
+    s = workloads.config("c0")
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    N = 32
+    X0 = workloads.start_block(op.M, N, seed=s.seed + 1_000_000)
+    v0 = workloads.lanczos_start(op.M, seed=s.seed + 2_000_000)
+    ref = ochfsi.solve(lambda v: H @ v, X0, N, m=20, block=32, v0=v0, passes=10)
+    Xd = dev(X0)
+    th, r, st = op.solve(Xd, N, m=20, block=32, fixed_passes=10, lanczos_v0=v0)
+    assert st["passes"] == 10
+    assert abs(st["b_upper"] - ref.b) < 1e-9 * ref.b
+    assert np.max(np.abs(th - ref.theta)) < 1e-8
+    lam = np.linalg.eigvalsh(H.toarray())
+    assert np.max(np.abs(th[:28] - lam[:28])) < 1e-8
+    Psi = host(Xd)
+    assert np.max(np.abs(Psi.T @ Psi - np.eye(N))) < 1e-12
+
+
+def test_error_paths(ctx):
+    s = _sys(*SMALL[1])
+    op = lib.Operator(ctx, s)
+    X = dev(np.zeros((op.M, 4)))
+    Y = dev(np.zeros((op.M, 4)))
+    with pytest.raises(lib.ChfsiError):   # precision does not match a real operator
+        op.apply(X, Y, lib.C128)
+    with pytest.raises(lib.ChfsiError):   # aL >= a
+        op.filter(X, 5, 1.0, 2.0, 1.5)
+    with pytest.raises(lib.ChfsiError):   # a >= b
+        op.filter(X, 5, 3.0, 2.0, 0.0)
+    with pytest.raises(lib.ChfsiError):   # X == Y
+        op.apply(X, X)
+    bad = workloads.small_system(2, 9, 1, seed=1)
+    with pytest.raises(lib.ChfsiError):   # order outside [2, 7]
+        lib.Operator(ctx, bad)
