@@ -233,6 +233,26 @@ int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double
 int chfsi_solve(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double* theta,
                 double* resid, chfsi_stats* stats);
 
+/* ---- one ChFSI pass ---------------------------------------------------------
+ * One pass of the loop of chfsi_solve() on the device block X (N + n_buf
+ * columns, the current Ritz vectors): filter every column block of
+ * params->block columns with degree params->m on [a, b] with lower end aL in
+ * params->filter_prec, then CholGS and Rayleigh-Ritz in FP64.  theta and
+ * resid (host, N + n_buf each; resid nullable) receive the new Ritz values
+ * and residual norms.  params->nwanted, n_buf, m, block and filter_prec are
+ * read; the stopping fields are ignored.  Synchronous. */
+int chfsi_pass(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double a, double b, double aL,
+               double* theta, double* resid);
+
+/* ---- kernel timing ---------------------------------------------------------
+ * When enabled, the library brackets every launch of the cell H~.X kernel
+ * with HIP events on the context stream.  chfsi_kernel_time() waits for the
+ * stream and returns the summed duration (ms), the number of launches and the
+ * summed algorithmic flops of those launches since the last reset (reset != 0
+ * clears the counters after reading). */
+int chfsi_set_timing(chfsi_ctx* ctx, int32_t enable);
+int chfsi_kernel_time(chfsi_ctx* ctx, double* total_ms, int64_t* launches, double* flops, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -418,3 +418,33 @@ def apply_rows(op: Operator, X: np.ndarray, rows: np.ndarray) -> np.ndarray:
         P = op.hvec[:, None] * P
         out += op.C[rows] @ P
     return out
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (8-bit significand) with round-to-nearest-even, via
+    float32; returned as float64.  Finite inputs only."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def apply_cellwise_bf16(op: Operator, X: np.ndarray, chunk: int = 512) -> np.ndarray:
+    """H~ X of the bf16 filter scheme (real operators): the cell products use
+    bf16-rounded scaled cell matrices D_c A0 D_c and bf16-rounded cell blocks
+    X^c; the potential and projector terms use X as given.  Products and sums
+    in FP64."""
+    if op.is_complex:
+        raise ValueError("bf16 scheme is defined for real operators")
+    X = np.asarray(X, dtype=np.float64)
+    A0 = op.cell_matrix()
+    Y = np.zeros((op.M, X.shape[1]))
+    for c0 in range(0, op.E, chunk):
+        cs = op.cells[c0:c0 + chunk]
+        for c in range(cs.shape[0]):
+            nodes = cs[c]
+            Ac = bf16_round(op.D[nodes, None] * A0 * op.D[None, nodes])
+            Xc = bf16_round(X[nodes])
+            np.add.at(Y, nodes, Ac @ Xc)
+    Y = Y + op.V[:, None] * X + apply_nonlocal(op, X)
+    return Y

@@ -10,6 +10,7 @@ the library's HIP kernels; nothing here computes.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -69,6 +70,8 @@ class Context:
             raise ChfsiError(rc, self.lib.chfsi_last_error(None).decode())
         self.h = h
         self.device = device
+        # operators must be destroyed before their context
+        self._ops = weakref.WeakSet()
 
     def check(self, rc: int, allow=(0,)):
         if rc not in allow:
@@ -78,8 +81,19 @@ class Context:
     def sync(self):
         self.check(self.lib.chfsi_sync(self.h))
 
+    def set_timing(self, enable: bool):
+        self.check(self.lib.chfsi_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, reset: bool = True):
+        """(total ms, launches, algorithmic flops) of the timed cell-kernel launches."""
+        ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
+        self.check(self.lib.chfsi_kernel_time(self.h, C.byref(ms), C.byref(n), C.byref(fl), 1 if reset else 0))
+        return ms.value, n.value, fl.value
+
     def close(self):
         if getattr(self, "h", None):
+            for op in list(getattr(self, "_ops", ())):
+                op.close()
             self.lib.chfsi_ctx_destroy(self.h)
             self.h = None
 
@@ -123,8 +137,11 @@ class Operator:
         for i in range(3):
             s.k[i] = float(k[i])
         h = C.c_void_p()
+        if not getattr(ctx, "h", None):
+            raise ValueError("context is closed")
         ctx.check(lib.chfsi_op_build(ctx.h, C.byref(s), C.byref(h)))
         self.h = h
+        ctx._ops.add(self)
         self._keep.clear()
         M, E, npairs = C.c_int64(), C.c_int64(), C.c_int64()
         mc, npj, cp = C.c_int32(), C.c_int32(), C.c_int32()
@@ -216,6 +233,22 @@ class Operator:
         stats = {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
         stats["converged"] = rc == 0
         return th, r, stats
+
+    def one_pass(self, X, nwanted: int, m: int, block: int, a: float, b: float, aL: float, n_buf: int = 0,
+                 filter_prec: Optional[int] = None):
+        """One ChFSI pass (filter, CholGS, Rayleigh-Ritz); returns (theta, resid)."""
+        if filter_prec is None:
+            filter_prec = C128 if self.is_complex else F64
+        ncols, ld = _ld_cols(X)
+        if ncols != nwanted + n_buf:
+            raise ValueError("X must have nwanted + n_buf columns")
+        p = _lib.Params()
+        p.nwanted, p.n_buf, p.m, p.block, p.filter_prec = nwanted, n_buf, m, block, int(filter_prec)
+        th = np.zeros(ncols)
+        r = np.zeros(ncols)
+        self.ctx.check(self.ctx.lib.chfsi_pass(self.h, C.byref(p), _tptr(X), ld, float(a), float(b), float(aL),
+                                               _dptr(th), _dptr(r)))
+        return th, r
 
     def close(self):
         if getattr(self, "h", None):

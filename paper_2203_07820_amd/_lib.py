@@ -16,7 +16,7 @@ EXPORTS = [
     "chfsi_ctx_create", "chfsi_ctx_destroy", "chfsi_last_error", "chfsi_sync", "chfsi_version",
     "chfsi_op_build", "chfsi_op_destroy", "chfsi_op_info", "chfsi_op_tables",
     "chfsi_apply", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
-    "chfsi_rayleigh_ritz", "chfsi_solve",
+    "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_kernel_time",
 ]
 
 
@@ -79,6 +79,9 @@ def load() -> C.CDLL:
         "chfsi_orthonormalize": (C.c_int, [vp, vp, i64, i64, pd]),
         "chfsi_rayleigh_ritz": (C.c_int, [vp, vp, i64, i64, pd, pd]),
         "chfsi_solve": (C.c_int, [vp, C.POINTER(Params), vp, i64, pd, pd, C.POINTER(Stats)]),
+        "chfsi_pass": (C.c_int, [vp, C.POINTER(Params), vp, i64, dbl, dbl, dbl, pd, pd]),
+        "chfsi_set_timing": (C.c_int, [vp, i32]),
+        "chfsi_kernel_time": (C.c_int, [vp, pd, C.POINTER(i64), pd, i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -45,6 +45,12 @@ struct chfsi_ctx {
   std::string err;
   void* ws[WS_COUNT] = {};
   size_t ws_size[WS_COUNT] = {};
+  // opt-in timing of the cell kernel: event pairs not yet read, totals
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<double> pending_flops;
+  double t_ms = 0.0, t_flops = 0.0;
+  int64_t t_launches = 0;
 };
 
 struct chfsi_op {
@@ -54,6 +60,7 @@ struct chfsi_op {
   // device tables
   void* A64 = nullptr;  void* Ai64 = nullptr;   // swizzled cell matrix, double
   void* A32 = nullptr;  void* Ai32 = nullptr;   // float
+  void* Abf = nullptr;                          // bf16, 16x16x32 operand order
   double* vdiag = nullptr;
   int64_t* atom_ptr = nullptr;
   int32_t* atom_node = nullptr;
@@ -223,8 +230,25 @@ int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp,
   L.pair_im = single ? op->pair_im32 : op->pair_im64;
   L.hP = hP;
   L.ldhp = ldhp;
-  const int kp = (prec == CHFSI_BF16) ? CHFSI_F32 : prec;
+  L.Abf = op->Abf;
+  const int kp = prec;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+  }
   HIP_TRY(ctx, launch_cell_hx(L, kp, ctx->stream));
+  if (ctx->timing) {
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    ctx->pending.emplace_back(e0, e1);
+    // algorithmic flops: dense cell products (padding excluded) and the
+    // nonlocal cell products of the (cell, atom) pairs; x4 for complex
+    const double cfl = t.cplx ? 4.0 : 1.0;
+    double fl = 2.0 * t.mcell * static_cast<double>(t.mcell) * static_cast<double>(ncols) * t.E * cfl;
+    if (t.has_proj) fl += 2.0 * 2.0 * t.mcell * 4.0 * static_cast<double>(ncols) * op->npairs * cfl;
+    ctx->pending_flops.push_back(fl);
+  }
   return 0;
 }
 
@@ -621,6 +645,10 @@ int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
 int chfsi_ctx_destroy(chfsi_ctx* ctx) {
   if (!ctx) return 0;
   (void)hipStreamSynchronize(ctx->stream);
+  for (auto& pr : ctx->pending) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -669,6 +697,14 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
     if ((rc = upload(op.get(), sw, &d)) < 0) break;
     op->A64 = d;
     if ((rc = upload_f32(op.get(), sw, &op->A32)) < 0) break;
+    if (!t.cplx) {
+      const int mp32 = mpad32_of(t.p);
+      std::vector<uint16_t> bf(static_cast<size_t>(mp32 / 16) * (mp32 / 32) * 64 * 8);
+      swizzle_cell_matrix_bf16(t.cell_re.data(), t.mcell, bf.data());
+      uint16_t* db;
+      if ((rc = upload(op.get(), bf, &db)) < 0) break;
+      op->Abf = db;
+    }
     if (t.cplx) {
       swizzle_cell_matrix(t.cell_im.data(), t.mcell, t.mpad, sw.data());
       if ((rc = upload(op.get(), sw, &d)) < 0) break;
@@ -791,7 +827,6 @@ int chfsi_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int32_t m, do
   if (m < 1) return fail(op->ctx, CHFSI_EINVAL, "degree m must be >= 1");
   if (!(aL < a && a < b) || !std::isfinite(aL) || !std::isfinite(b))
     return fail(op->ctx, CHFSI_EINVAL, "need aL < a < b");
-  if (prec == CHFSI_BF16) return fail(op->ctx, CHFSI_EINVAL, "bf16 filter not available in this build");
   return do_filter(op, X, ncols, ld, m, a, b, aL, prec, block);
 }
 
@@ -822,6 +857,63 @@ int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double
   return 0;
 }
 
+int chfsi_pass(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, double a, double b, double aL,
+               double* theta, double* resid) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  if (!prm || !theta) return fail(ctx, CHFSI_EINVAL, "null argument");
+  const int64_t N = static_cast<int64_t>(prm->nwanted) + prm->n_buf;
+  if (prm->nwanted < 1 || prm->n_buf < 0) return fail(ctx, CHFSI_EINVAL, "nwanted >= 1, n_buf >= 0");
+  CHECK(check_block(op, Xv, N, ld));
+  if (prm->m < 1) return fail(ctx, CHFSI_EINVAL, "degree m must be >= 1");
+  if (!prec_valid_for(op, prm->filter_prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
+  if (!(aL < a && a < b)) return fail(ctx, CHFSI_EINVAL, "need aL < a < b");
+  const int cf = op->t.cplx ? 2 : 1;
+  double* X = static_cast<double*>(Xv);
+  void* X2v;
+  CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * N * 8 * cf, &X2v));
+  CHECK(do_filter(op, X, N, ld, prm->m, a, b, aL, prm->filter_prec, prm->block));
+  CHECK(cholgs(op, X, ld, static_cast<double*>(X2v), N, N, nullptr));
+  std::vector<double> r(N);
+  CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N, X, ld, N, theta, r.data()));
+  if (resid) std::memcpy(resid, r.data(), N * 8);
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(theta[i]) || !std::isfinite(r[i]))
+      return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
+  return 0;
+}
+
+int chfsi_set_timing(chfsi_ctx* ctx, int32_t enable) {
+  if (!ctx) return CHFSI_EINVAL;
+  ctx->timing = enable != 0;
+  return 0;
+}
+
+int chfsi_kernel_time(chfsi_ctx* ctx, double* total_ms, int64_t* launches, double* flops, int32_t reset) {
+  if (!ctx) return CHFSI_EINVAL;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i < ctx->pending.size(); ++i) {
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->pending[i].first, ctx->pending[i].second));
+    ctx->t_ms += ms;
+    ctx->t_flops += ctx->pending_flops[i];
+    ctx->t_launches += 1;
+    (void)hipEventDestroy(ctx->pending[i].first);
+    (void)hipEventDestroy(ctx->pending[i].second);
+  }
+  ctx->pending.clear();
+  ctx->pending_flops.clear();
+  if (total_ms) *total_ms = ctx->t_ms;
+  if (launches) *launches = ctx->t_launches;
+  if (flops) *flops = ctx->t_flops;
+  if (reset) {
+    ctx->t_ms = 0.0;
+    ctx->t_flops = 0.0;
+    ctx->t_launches = 0;
+  }
+  return 0;
+}
+
 int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, double* theta, double* resid,
                 chfsi_stats* stats) {
   if (!op) return CHFSI_EINVAL;
@@ -833,7 +925,6 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
   CHECK(check_block(op, Xv, N, ld));
   if (prm->m < 1) return fail(ctx, CHFSI_EINVAL, "degree m must be >= 1");
   if (!prec_valid_for(op, prm->filter_prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
-  if (prm->filter_prec == CHFSI_BF16) return fail(ctx, CHFSI_EINVAL, "bf16 filter not available in this build");
   if (prm->fixed_passes <= 0 && !(prm->tol > 0.0)) return fail(ctx, CHFSI_EINVAL, "need fixed_passes or tol");
   const int cf = t.cplx ? 2 : 1;
   hipEvent_t ev[8];

@@ -55,6 +55,12 @@ std::string build_tables(const chfsi_system& sys, HostTables& t);
 // Swizzles a row-major mcell x mcell matrix into MFMA A-operand layout:
 // out[(rt * ks_count + ks) * 64 + lane] = A[rt*16 + lane%16][ks*4 + lane/16].
 void swizzle_cell_matrix(const double* A, int mcell, int mpad, double* out);
+// bf16 (round to nearest even) operand order of v_mfma_f32_16x16x32_bf16, rows
+// and k padded to a multiple of 32:
+// out[((rt * ks_count + ks) * 64 + lane) * 8 + j] = A[rt*16 + lane%16][ks*32 + 8*(lane/16) + j]
+int mpad32_of(int p);
+void swizzle_cell_matrix_bf16(const double* A, int mcell, uint16_t* out);
+uint16_t bf16_rne(float x);
 
 // ---- kernel launchers (kernels_hx.hip, kernels_dense.hip) -----------------
 
@@ -74,6 +80,7 @@ struct HxLaunch {
   const int32_t* pair_ptr; const int32_t* pair_atom;
   const void* pair_re; const void* pair_im;
   const void* hP; int64_t ldhp;    // scaled projector coefficients (real view)
+  const void* Abf = nullptr;       // bf16 cell matrix in 16x16x32 operand order
 };
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).

@@ -85,7 +85,13 @@ struct HxArgs {
   int64_t ldhp;
 };
 
-template <int P, typename T, bool CPLX, int WAVES>
+// Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
+// number of 16-row tiles is even for every order p in [2, 7], so each wave
+// owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
+// A fragments of the next LDS chunk are loaded into registers before the
+// gather of that chunk is issued: vector-memory counters retire in order, so
+// the MFMAs of a chunk never wait for the (HBM-latency) gather loads.
+template <int P, typename T, bool CPLX, int WAVES, int KPC>
 __global__ void __launch_bounds__(64 * WAVES)
 cell_hx_kernel(const HxArgs<T> a) {
   constexpr int Q = P + 1;
@@ -93,14 +99,21 @@ cell_hx_kernel(const HxArgs<T> a) {
   constexpr int MP = (MC + 15) / 16 * 16;
   constexpr int RT = MP / 16;           // row tiles
   constexpr int KS = MP / 4;            // 4-wide k steps
-  constexpr int NCH = MP / kKC;         // LDS chunks
-  constexpr int RW = (RT + WAVES - 1) / WAVES;  // row tiles per wave
+  constexpr int KC = 4 * KPC;           // cell rows per LDS chunk
+  constexpr int NCH = MP / KC;          // LDS chunks
+  constexpr int RG = WAVES / 2;         // row groups
+  constexpr int RPW = RT / RG;          // row tiles per wave
+  constexpr int CPW = 2;                // column tiles per wave
+  constexpr int GR = KC / WAVES;        // gathered rows per thread and chunk
+  static_assert(MP % KC == 0 && RT % RG == 0 && KC % WAVES == 0, "tiling");
   using acc_t = typename Mma<T>::acc_t;
 
-  __shared__ T xs[2][kKC][kNT];
+  __shared__ T xs[2][KC][kNT];
 
   const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int lane = tid % 64;
+  const int rt0 = (wave / 2) * RPW, ct0 = (wave % 2) * CPW;
   const int nc = a.nc, n = nc * P;
   const int E = nc * nc * nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -117,109 +130,126 @@ cell_hx_kernel(const HxArgs<T> a) {
   };
 
   // gather: thread owns column `lane` of rows wave, wave + WAVES, ...
-  T g[kKC / WAVES];
   const bool col_ok = (col0 + lane) < a.ncols;
-  auto load_chunk = [&](int ch) {
+  auto load_chunk = [&](T (&g)[GR], int ch) {
 #pragma unroll
-    for (int i = 0; i < kKC / WAVES; ++i) {
-      const int l = ch * kKC + wave + WAVES * i;
+    for (int i = 0; i < GR; ++i) {
+      const int l = ch * KC + wave + WAVES * i;
       T v = T(0);
       if (l < MC && col_ok) v = a.Xk[gnode(l) * a.ldx + col0 + lane];
       g[i] = v;
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](const T (&g)[GR], int buf) {
 #pragma unroll
-    for (int i = 0; i < kKC / WAVES; ++i) xs[buf][wave + WAVES * i][lane] = g[i];
+    for (int i = 0; i < GR; ++i) xs[buf][wave + WAVES * i][lane] = g[i];
   };
 
-  acc_t acc[RW][4];
+  // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
+  const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
+  const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
+  constexpr int NI = CPLX ? KPC : 1;
+  constexpr int RI = CPLX ? RPW : 1;
+  auto load_a = [&](T (&dst)[KPC][RPW], T (&dsti)[NI][RI], int ch) {
 #pragma unroll
-  for (int r = 0; r < RW; ++r)
+    for (int s = 0; s < KPC; ++s)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = acc_t{0, 0, 0, 0};
+      for (int r = 0; r < RPW; ++r) {
+        dst[s][r] = Aw[(static_cast<int64_t>(r) * KS + ch * KPC + s) * 64];
+        if constexpr (CPLX) dsti[s][r] = Aiw[(static_cast<int64_t>(r) * KS + ch * KPC + s) * 64];
+      }
+  };
 
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
+  acc_t acc[RPW][CPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
 
-  for (int ch = 0; ch < NCH; ++ch) {
+  // One chunk: issue A of chunk ch+1 and the gather of chunk ch+2 (in that
+  // order), multiply with A of chunk ch and the LDS copy of chunk ch, then
+  // store the gather of chunk ch+1 (issued one chunk earlier) to LDS.
+  auto chunk_step = [&](int ch, T (&acur)[KPC][RPW], T (&aicur)[NI][RI], T (&anext)[KPC][RPW],
+                        T (&ainext)[NI][RI], T (&gstore)[GR], T (&gload)[GR]) {
     const int buf = ch & 1;
-    if (ch + 1 < NCH) load_chunk(ch + 1);
+    if (ch + 1 < NCH) load_a(anext, ainext, ch + 1);
+    if (ch + 2 < NCH) load_chunk(gload, ch + 2);
 #pragma unroll
-    for (int ks = 0; ks < kKC / 4; ++ks) {
-      const int krow = ks * 4 + lane / 16;
-      T b[4], bs[4];
+    for (int s = 0; s < KPC; ++s) {
+      const int krow = s * 4 + lane / 16;
+      T b[CPW], bs[CPW];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int cc = ct * 16 + lane % 16;
-        b[ct] = xs[buf][krow][cc];
+      for (int c = 0; c < CPW; ++c) {
+        const int cc = (ct0 + c) * 16 + lane % 16;
+        b[c] = xs[buf][krow][cc];
         if constexpr (CPLX) {
           const T o = xs[buf][krow][cc ^ 1];
-          bs[ct] = (cc & 1) ? o : -o;
+          bs[c] = (cc & 1) ? o : -o;
         }
       }
-      const int kg = ch * (kKC / 4) + ks;
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const int rt = wave + WAVES * r;
-        if (rt < RT) {
-          const T av = a.A[(static_cast<int64_t>(rt) * KS + kg) * 64 + lane];
+      for (int r = 0; r < RPW; ++r)
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(av, b[ct], acc[r][ct]);
-          if constexpr (CPLX) {
-            const T ai = a.Ai[(static_cast<int64_t>(rt) * KS + kg) * 64 + lane];
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(ai, bs[ct], acc[r][ct]);
-          }
+        for (int c = 0; c < CPW; ++c) {
+          acc[r][c] = Mma<T>::run(acur[s][r], b[c], acc[r][c]);
+          if constexpr (CPLX) acc[r][c] = Mma<T>::run(aicur[s][r], bs[c], acc[r][c]);
         }
-      }
     }
-    if (ch + 1 < NCH) store_chunk(buf ^ 1);
+    if (ch + 1 < NCH) store_chunk(gstore, buf ^ 1);
     __syncthreads();
+  };
+
+  T a0[KPC][RPW], a1[KPC][RPW];
+  T ai0[NI][RI], ai1[NI][RI];
+  T g0[GR], g1[GR];
+  load_a(a0, ai0, 0);
+  load_chunk(g0, 0);
+  store_chunk(g0, 0);
+  if (NCH > 1) load_chunk(g0, 1);
+  __syncthreads();
+  for (int ch = 0; ch < NCH; ch += 2) {
+    chunk_step(ch, a0, ai0, a1, ai1, g0, g1);
+    if (ch + 1 < NCH) chunk_step(ch + 1, a1, ai1, a0, ai0, g1, g0);
   }
 
-  // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell
+  // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell, one
+  // 4-wide k step per (cell, atom) pair
   if (a.pair_ptr != nullptr) {
     const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
     for (int pr = p0; pr < p1; ++pr) {
       const int at = a.pair_atom[pr];
-      T b[4], bs[4];
+      const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
+      T b[CPW], bs[CPW], cv[RPW], ci[CPLX ? RPW : 1];
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int cc = ct * 16 + lane % 16;
-        const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
-        b[ct] = hrow[cc];
+      for (int c = 0; c < CPW; ++c) {
+        const int cc = (ct0 + c) * 16 + lane % 16;
+        b[c] = hrow[cc];
         if constexpr (CPLX) {
           const T o = hrow[cc ^ 1];
-          bs[ct] = (cc & 1) ? o : -o;
+          bs[c] = (cc & 1) ? o : -o;
         }
       }
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const int rt = wave + WAVES * r;
-        if (rt < RT) {
-          const T cv = a.pair_re[(static_cast<int64_t>(pr) * RT + rt) * 64 + lane];
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(cv, b[ct], acc[r][ct]);
-          if constexpr (CPLX) {
-            const T ci = a.pair_im[(static_cast<int64_t>(pr) * RT + rt) * 64 + lane];
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<T>::run(ci, bs[ct], acc[r][ct]);
-          }
-        }
+      for (int r = 0; r < RPW; ++r) {
+        cv[r] = a.pair_re[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
+        if constexpr (CPLX) ci[r] = a.pair_im[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
       }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          acc[r][c] = Mma<T>::run(cv[r], b[c], acc[r][c]);
+          if constexpr (CPLX) acc[r][c] = Mma<T>::run(ci[r], bs[c], acc[r][c]);
+        }
     }
   }
 
   // epilogue: scale, owner terms, atomic assembly
 #pragma unroll
-  for (int r = 0; r < RW; ++r) {
-    const int rt = wave + WAVES * r;
-    if (rt >= RT) continue;
+  for (int r = 0; r < RPW; ++r) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = rt * 16 + Mma<T>::row(lane, i);
+      const int row = (rt0 + r) * 16 + Mma<T>::row(lane, i);
       if (row >= MC) continue;
       const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
       const bool owner = (la < P) && (lb < P) && (lc < P);
@@ -227,10 +257,10 @@ cell_hx_kernel(const HxArgs<T> a) {
       T vc = T(0);
       if (owner) vc = a.alpha * (static_cast<T>(a.vdiag[gn]) - a.c);
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int col = col0 + ct * 16 + lane % 16;
+      for (int c = 0; c < CPW; ++c) {
+        const int col = col0 + (ct0 + c) * 16 + lane % 16;
         if (col >= a.ncols) continue;
-        T v = a.alpha * acc[r][ct][i];
+        T v = a.alpha * acc[r][c][i];
         if (owner) {
           v += vc * a.Xk[gn * a.ldx + col];
           if (a.Xp != nullptr) {
@@ -276,7 +306,10 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
   constexpr int WAVES = RT > 24 ? 8 : 4;
-  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES>), dim3(static_cast<unsigned>(nblk)),
+  // k steps per LDS chunk, sized so that the A fragments of two chunks
+  // (one being used, one in flight) fit in registers next to the accumulators
+  constexpr int KPC = sizeof(T) == 8 ? ((CPLX && WAVES == 4) ? 1 : 2) : (CPLX ? 2 : 4);
+  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, KPC>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
 }
@@ -292,6 +325,195 @@ hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
     case 7: return launch_p<7, T, CPLX>(L, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---- BF16 variant ------------------------------------------------------------
+// Same structure as cell_hx_kernel with FP32 iterates: the cell products take
+// bf16-rounded inputs (round to nearest even) on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation; the potential, recurrence and nonlocal terms stay FP32
+// (the nonlocal k steps use the f32 16x16x4 MFMA into the same accumulators,
+// whose layout is shared by all 16x16 f32-output MFMAs).  Operand layout of
+// the bf16 MFMA: lane l supplies A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16] for j = 0..7.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+constexpr int kKB = 32;        // cell rows per LDS chunk (one bf16 k step)
+constexpr int kXR = kKB + 8;   // padded row length of the transposed chunk
+
+template <int P, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES)
+cell_hx_bf16_kernel(const HxArgs<float> a, const bf8* __restrict__ Abf) {
+  constexpr int Q = P + 1;
+  constexpr int MC = Q * Q * Q;
+  constexpr int MP = (MC + kKB - 1) / kKB * kKB;   // rows/k padded to 32
+  constexpr int RT = MP / 16;
+  constexpr int KS = MP / kKB;                     // 32-wide k steps
+  constexpr int RW = (RT + WAVES - 1) / WAVES;
+  constexpr int RT4 = (MC + 15) / 16;              // row tiles of the f32 pair tables
+  static_assert(kKB % (2 * WAVES) == 0, "chunk rows must split evenly");
+
+  // transposed chunk: xs[buf][col][row] as bf16
+  __shared__ __attribute__((aligned(16))) __bf16 xs[2][kNT][kXR];
+
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int nc = a.nc, n = nc * P;
+  const int E = nc * nc * nc;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int cell = bid % E;
+  const int col0 = (bid / E) * kNT;
+  const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
+
+  auto gnode = [&](int l) -> int64_t {
+    const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
+    int gx = cx * P + la; if (gx >= n) gx -= n;
+    int gy = cy * P + lb; if (gy >= n) gy -= n;
+    int gz = cz * P + lc; if (gz >= n) gz -= n;
+    return gx + static_cast<int64_t>(n) * (gy + static_cast<int64_t>(n) * gz);
+  };
+
+  // gather: thread owns column `lane`, row pairs (2 wave + 2 WAVES i, +1)
+  constexpr int NPAIR = kKB / (2 * WAVES);
+  float g[2 * NPAIR];
+  const bool col_ok = (col0 + lane) < a.ncols;
+  auto load_chunk = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < NPAIR; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int l = ch * kKB + 2 * wave + 2 * WAVES * i + h;
+        float v = 0.f;
+        if (l < MC && col_ok) v = a.Xk[gnode(l) * a.ldx + col0 + lane];
+        g[2 * i + h] = v;
+      }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NPAIR; ++i) {
+      bf2 v;
+      v[0] = static_cast<__bf16>(g[2 * i]);
+      v[1] = static_cast<__bf16>(g[2 * i + 1]);
+      *reinterpret_cast<bf2*>(&xs[buf][lane][2 * wave + 2 * WAVES * i]) = v;
+    }
+  };
+
+  f4 acc[RW][4];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int ch = 0; ch < KS; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < KS) load_chunk(ch + 1);
+    bf8 b[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+      b[ct] = *reinterpret_cast<const bf8*>(&xs[buf][ct * 16 + lane % 16][8 * (lane / 16)]);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int rt = wave + WAVES * r;
+      if (rt < RT) {
+        const bf8 av = Abf[(static_cast<int64_t>(rt) * KS + ch) * 64 + lane];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[ct], acc[r][ct], 0, 0, 0);
+      }
+    }
+    if (ch + 1 < KS) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+
+  // nonlocal in FP32
+  if (a.pair_ptr != nullptr) {
+    const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
+    for (int pr = p0; pr < p1; ++pr) {
+      const int at = a.pair_atom[pr];
+      float b[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        b[ct] = a.hP[(static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0 + ct * 16 + lane % 16];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int rt = wave + WAVES * r;
+        if (rt < RT4) {
+          const float cv = a.pair_re[(static_cast<int64_t>(pr) * RT4 + rt) * 64 + lane];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<float>::run(cv, b[ct], acc[r][ct]);
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    const int rt = wave + WAVES * r;
+    if (rt >= RT) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rt * 16 + Mma<float>::row(lane, i);
+      if (row >= MC) continue;
+      const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
+      const bool owner = (la < P) && (lb < P) && (lc < P);
+      const int64_t gn = gnode(row);
+      float vc = 0.f;
+      if (owner) vc = a.alpha * (static_cast<float>(a.vdiag[gn]) - a.c);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int col = col0 + ct * 16 + lane % 16;
+        if (col >= a.ncols) continue;
+        float v = a.alpha * acc[r][ct][i];
+        if (owner) {
+          v += vc * a.Xk[gn * a.ldx + col];
+          if (a.Xp != nullptr) {
+            float* xp = const_cast<float*>(a.Xp) + gn * a.ldp + col;
+            v -= a.beta * (*xp);
+            if (a.zero_prev) *xp = 0.f;
+          }
+        }
+        atomic_add(a.Tg + gn * a.ldt + col, v);
+      }
+    }
+  }
+}
+
+template <int P>
+hipError_t launch_bf16_p(const HxLaunch& L, hipStream_t s) {
+  HxArgs<float> a;
+  a.A = nullptr;
+  a.Ai = nullptr;
+  a.vdiag = L.vdiag;
+  a.Xk = static_cast<const float*>(L.Xk);
+  a.Xp = static_cast<const float*>(L.Xp);
+  a.Tg = static_cast<float*>(L.T);
+  a.ldx = L.ldx;
+  a.ldp = L.ldp;
+  a.ldt = L.ldt;
+  a.ncols = L.ncols;
+  a.nc = L.nc;
+  a.zero_prev = L.zero_prev ? 1 : 0;
+  a.alpha = static_cast<float>(L.alpha);
+  a.c = static_cast<float>(L.c);
+  a.beta = static_cast<float>(L.beta);
+  a.pair_ptr = L.pair_ptr;
+  a.pair_atom = L.pair_atom;
+  a.pair_re = static_cast<const float*>(L.pair_re);
+  a.pair_im = nullptr;
+  a.hP = static_cast<const float*>(L.hP);
+  a.ldhp = L.ldhp;
+  const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
+  const int64_t nblk = E * ((L.ncols + kNT - 1) / kNT);
+  if (nblk <= 0) return hipSuccess;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + kKB - 1) / kKB * kKB / 16;
+  constexpr int WAVES = RT > 24 ? 8 : 4;
+  hipLaunchKernelGGL((cell_hx_bf16_kernel<P, WAVES>), dim3(static_cast<unsigned>(nblk)), dim3(64 * WAVES), 0, s,
+                     a, static_cast<const bf8*>(L.Abf));
+  return hipGetLastError();
 }
 
 // ---- node-level projector contraction (Algorithm 4 steps 1-4) -------------
@@ -419,6 +641,18 @@ unsigned grid_for(int64_t total) {
 
 hipError_t launch_cell_hx(const HxLaunch& L, int prec, hipStream_t s) {
   if (L.p < kMinOrder || L.p > kMaxOrder) return hipErrorInvalidValue;
+  if (prec == CHFSI_BF16) {
+    if (L.cplx || L.Abf == nullptr) return hipErrorInvalidValue;
+    switch (L.p) {
+      case 2: return launch_bf16_p<2>(L, s);
+      case 3: return launch_bf16_p<3>(L, s);
+      case 4: return launch_bf16_p<4>(L, s);
+      case 5: return launch_bf16_p<5>(L, s);
+      case 6: return launch_bf16_p<6>(L, s);
+      case 7: return launch_bf16_p<7>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (prec) {
     case CHFSI_F64: return launch_t<double, false>(L, s);
     case CHFSI_F32: return launch_t<float, false>(L, s);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <unordered_map>
 
 #include "internal.h"
@@ -121,6 +122,32 @@ void swizzle_cell_matrix(const double* A, int mcell, int mpad, double* out) {
         out[(static_cast<size_t>(rt) * kss + ks) * 64 + lane] =
             (r < mcell && k < mcell) ? A[static_cast<size_t>(r) * mcell + k] : 0.0;
       }
+}
+
+int mpad32_of(int p) { return (mcell_of(p) + 31) / 32 * 32; }
+
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return static_cast<uint16_t>(u >> 16);
+}
+
+void swizzle_cell_matrix_bf16(const double* A, int mcell, uint16_t* out) {
+  int p = 1;
+  while (mcell_of(p) < mcell) ++p;
+  const int mp = mpad32_of(p);
+  const int rts = mp / 16, kss = mp / 32;
+  for (int rt = 0; rt < rts; ++rt)
+    for (int ks = 0; ks < kss; ++ks)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int j = 0; j < 8; ++j) {
+          const int r = rt * 16 + lane % 16, k = ks * 32 + 8 * (lane / 16) + j;
+          const float v = (r < mcell && k < mcell) ? static_cast<float>(A[static_cast<size_t>(r) * mcell + k]) : 0.f;
+          out[((static_cast<size_t>(rt) * kss + ks) * 64 + lane) * 8 + j] = bf16_rne(v);
+        }
 }
 
 std::string build_tables(const chfsi_system& sys, HostTables& t) {
