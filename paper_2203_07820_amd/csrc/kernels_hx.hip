@@ -91,8 +91,8 @@ struct HxArgs {
 // A fragments of the next LDS chunk are loaded into registers before the
 // gather of that chunk is issued: vector-memory counters retire in order, so
 // the MFMAs of a chunk never wait for the (HBM-latency) gather loads.
-template <int P, typename T, bool CPLX, int WAVES, int KPC>
-__global__ void __launch_bounds__(64 * WAVES)
+template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
@@ -244,32 +244,43 @@ cell_hx_kernel(const HxArgs<T> a) {
     }
   }
 
-  // epilogue: scale, owner terms, atomic assembly
+  // epilogue: scale, owner terms, atomic assembly.  Per row tile, the owner
+  // operands (potential, X_k, X_{k-1}) are loaded for all rows of the lane
+  // before any atomic is issued, so their latencies overlap.
+  const T* __restrict__ Xk = a.Xk;
+  T* __restrict__ Xp = const_cast<T*>(a.Xp);
+  T* __restrict__ Tg = a.Tg;
+  const double* __restrict__ vd = a.vdiag;
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
+    int64_t gn[4];
+    bool valid[4], own[4];
+    T vc[4], xk[4][CPW], xp[4][CPW];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = (rt0 + r) * 16 + Mma<T>::row(lane, i);
-      if (row >= MC) continue;
+      valid[i] = row < MC;
       const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
-      const bool owner = (la < P) && (lb < P) && (lc < P);
-      const int64_t gn = gnode(row);
-      T vc = T(0);
-      if (owner) vc = a.alpha * (static_cast<T>(a.vdiag[gn]) - a.c);
+      own[i] = valid[i] && (la < P) && (lb < P) && (lc < P);
+      gn[i] = valid[i] ? gnode(row) : 0;
+      vc[i] = own[i] ? a.alpha * (static_cast<T>(vd[gn[i]]) - a.c) : T(0);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int col = col0 + (ct0 + c) * 16 + lane % 16;
-        if (col >= a.ncols) continue;
-        T v = a.alpha * acc[r][c][i];
-        if (owner) {
-          v += vc * a.Xk[gn * a.ldx + col];
-          if (a.Xp != nullptr) {
-            T* xp = const_cast<T*>(a.Xp) + gn * a.ldp + col;
-            v -= a.beta * (*xp);
-            if (a.zero_prev) *xp = T(0);
-          }
-        }
-        atomic_add(a.Tg + gn * a.ldt + col, v);
+        const bool ok = own[i] && col < a.ncols;
+        xk[i][c] = ok ? Xk[gn[i] * a.ldx + col] : T(0);
+        xp[i][c] = (ok && Xp != nullptr) ? Xp[gn[i] * a.ldp + col] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = col0 + (ct0 + c) * 16 + lane % 16;
+        if (!valid[i] || col >= a.ncols) continue;
+        const T v = a.alpha * acc[r][c][i] + vc[i] * xk[i][c] - a.beta * xp[i][c];
+        if (own[i] && Xp != nullptr && a.zero_prev) Xp[gn[i] * a.ldp + col] = T(0);
+        atomic_add(Tg + gn[i] * a.ldt + col, v);
       }
     }
   }
@@ -306,10 +317,14 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
   constexpr int WAVES = RT > 24 ? 8 : 4;
-  // k steps per LDS chunk, sized so that the A fragments of two chunks
-  // (one being used, one in flight) fit in registers next to the accumulators
-  constexpr int KPC = sizeof(T) == 8 ? ((CPLX && WAVES == 4) ? 1 : 2) : (CPLX ? 2 : 4);
-  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, KPC>), dim3(static_cast<unsigned>(nblk)),
+  // k steps per LDS chunk, sized so that the A fragments of two chunks (one
+  // being used, one in flight) fit in registers next to the accumulators with
+  // two waves per SIMD (two workgroups per CU: one's gather and epilogue
+  // overlap the other's MFMAs).  Complex FP64 needs twice the A registers and
+  // runs one wave per SIMD.
+  constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
+  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : 2;
+  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
 }
