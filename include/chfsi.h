@@ -69,6 +69,7 @@ typedef enum {
 
 typedef struct chfsi_ctx chfsi_ctx;
 typedef struct chfsi_op chfsi_op;
+typedef struct chfsi_mlp chfsi_mlp;
 
 /* A periodic cube [0, L)^3 of ncell^3 hexahedral cells of order p, with
  * Gaussian atoms (Section 2.3 discretisation; synthetic stand-ins for the
@@ -243,6 +244,96 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, d
  * read; the stopping fields are ignored.  Synchronous. */
 int chfsi_pass(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double a, double b, double aL,
                double* theta, double* resid);
+
+/* ---- batched filter (many operators, one persistent launch per step) -------
+ * Applies the filter of chfsi_filter() to n independent blocks at once:
+ * block q is X[q] (device, double / complex double, ncols[q] columns, ld[q])
+ * of operator ops[q] with interval a[q], b[q], aL[q] (aL < a < b).  All
+ * operators must share the context, the order p and the real/complex type;
+ * prec is F64, F32 (real) or C128, C64 (complex).  Column blocks of `block`
+ * columns (<= 0: all) of every problem are filtered together: each
+ * Chebyshev step of a round is ONE launch of a persistent kernel whose work
+ * list concatenates every problem's (cell, column tile) items; the per-problem
+ * arguments and recurrence scalars come from device tables.  use_graph != 0
+ * captures the whole sequence into a hipGraph (kept in the context and
+ * replayed while the operators, buffers and shapes stay the same).  Grid
+ * shape from chfsi_autotune() when tuned, else 1 (C128) or 2 workgroups per
+ * CU.  Results equal chfsi_filter() on each block up to the order of the
+ * atomic assembly.  Asynchronous. */
+int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* const* X, const int64_t* ncols,
+                         const int64_t* ld, int32_t m, const double* a, const double* b, const double* aL,
+                         int32_t prec, int32_t block, int32_t use_graph);
+
+/* ---- batched solve ----------------------------------------------------------
+ * chfsi_solve() for n independent problems (systems and/or k-points) that
+ * advance pass by pass together: the filters of all unconverged problems run
+ * through chfsi_filter_batched() (with use_graph: one graph replay per pass),
+ * then each problem's CholGS and Rayleigh-Ritz run in turn.  params, X, ld,
+ * theta, resid, stats are arrays of n entries (resid, stats and their entries
+ * nullable); m, block and filter_prec must be equal across params.  A problem
+ * stops when its own criterion is met; the others continue.  Returns
+ * CHFSI_NOTCONV if any tolerance was not met.  Synchronous. */
+int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const chfsi_params* params,
+                        void* const* X, const int64_t* ld, double* const* theta, double* const* resid,
+                        chfsi_stats* stats, int32_t use_graph);
+
+/* ---- autotuner of the batched launch ----------------------------------------
+ * Times the batched filter on a synthetic batch of four uneven boxes of order
+ * p with `block` columns over persistent-grid shapes (1..4 workgroups per CU,
+ * contiguous or strided item assignment), keeps the fastest for the key
+ * (gfx950, p, prec, block) in the context and, when cache_json is not NULL,
+ * merges it into that JSON file (read first, then rewritten).  Synchronous.
+ * chfsi_load_tuning() reads such a file into the context; chfsi_get_tuning()
+ * returns the shape the batched launch will use (tuned or default). */
+int chfsi_autotune(chfsi_ctx* ctx, const char* cache_json, int32_t p, int32_t prec, int32_t block);
+int chfsi_load_tuning(chfsi_ctx* ctx, const char* cache_json);
+int chfsi_get_tuning(chfsi_ctx* ctx, int32_t p, int32_t prec, int32_t block, int32_t* grid_per_cu,
+                     int32_t* contiguous, double* ms);
+
+/* ---- learned warm start -------------------------------------------------------
+ * A small network maps per-node features to an initial block (an extension
+ * around the paper's method; the paper starts ChFSI from the previous SCF
+ * step's subspace).
+ *
+ * chfsi_features: F (device, float, M x 32 row-major) receives the radial
+ *   features of every node: F[j][8q + k] = sum_a sum_images phi_q(a)
+ *   exp(-(r - k)^2 / (2 * 0.5^2)), r = |x_j - R_a - nL| <= 10 bohr, k = 0..7,
+ *   phi = (Z_a, s_a, h_s,a, h_p,a).  Asynchronous.
+ * chfsi_mlp_create: network din -> hidden (tanh) -> hidden (tanh) -> dout
+ *   (linear), all widths <= 128, FP32, Xavier-uniform weights drawn from
+ *   `seed` (splitmix64), zero biases, Adam state zero, input normalisation
+ *   mean 0 / scale 1.  The network keeps a pointer to ctx.
+ * chfsi_mlp_params: flat parameter vector (host, chfsi_mlp_info nparams
+ *   floats) in the order W1 (din x hidden, row-major), b1, W2, b2, W3, b3;
+ *   get != 0 copies out, 0 copies in.  Synchronous.
+ * chfsi_mlp_set_norm: input standardisation (F - mean) / scale (host arrays
+ *   of din; scales > 0).
+ * chfsi_mlp_forward: Y (device, rows x dout) = network(F (device, rows x din)).
+ * chfsi_mlp_loss_grad: loss = ||Y - Q Q^T Y||^2 / ||Y||^2
+ *   + 0.1 ||dout Y^T Y / ||Y||^2 - I||^2 / dout^2 for Y = network(F) and the
+ *   orthonormal block Q (device, rows x nq, nq = dout); grads_host (nullable,
+ *   nparams floats) receives d loss / d parameters.  Synchronous.
+ * chfsi_mlp_train_step: loss_grad followed by one Adam step (lr, 0.9, 0.999,
+ *   1e-8).  Synchronous (returns the loss before the step).
+ * chfsi_initial_block: X (device, double, M x ld, ncols columns) receives the
+ *   network's block (features of op, forward, widened to FP64; columns beyond
+ *   dout drawn from `seed`), or a random N(0,1) block from `seed` when net is
+ *   NULL, the operator is complex, or the network's block is non-finite or
+ *   has a non-positive-definite overlap; *used_fallback says which.
+ *   Synchronous. */
+int chfsi_features(chfsi_op* op, float* F);
+int chfsi_mlp_create(chfsi_ctx* ctx, int32_t din, int32_t hidden, int32_t dout, uint64_t seed, chfsi_mlp** out);
+int chfsi_mlp_destroy(chfsi_mlp* net);
+int chfsi_mlp_info(const chfsi_mlp* net, int32_t* din, int32_t* hidden, int32_t* dout, int64_t* nparams);
+int chfsi_mlp_params(chfsi_mlp* net, float* host, int32_t get);
+int chfsi_mlp_set_norm(chfsi_mlp* net, const float* mean, const float* scale);
+int chfsi_mlp_forward(chfsi_mlp* net, const float* F, int64_t rows, float* Y);
+int chfsi_mlp_loss_grad(chfsi_mlp* net, const float* F, int64_t rows, const float* Q, int32_t nq, double* loss,
+                        float* grads_host);
+int chfsi_mlp_train_step(chfsi_mlp* net, const float* F, int64_t rows, const float* Q, int32_t nq, float lr,
+                         double* loss);
+int chfsi_initial_block(chfsi_op* op, chfsi_mlp* net, uint64_t seed, void* X, int64_t ncols, int64_t ld,
+                        int32_t* used_fallback);
 
 /* ---- kernel timing ---------------------------------------------------------
  * When enabled, the library brackets every launch of the cell H~.X kernel

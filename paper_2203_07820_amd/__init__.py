@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BF16, C64, C128, F32, F64  # noqa: F401
 
-__all__ = ["ChfsiError", "Context", "Operator", "F64", "F32", "BF16", "C128", "C64", "load"]
+__all__ = ["ChfsiError", "Context", "Operator", "Network", "features", "initial_block", "F64", "F32", "BF16",
+           "C128", "C64", "load"]
 
 
 class ChfsiError(RuntimeError):
@@ -89,6 +90,69 @@ class Context:
         ms, n, fl = C.c_double(), C.c_int64(), C.c_double()
         self.check(self.lib.chfsi_kernel_time(self.h, C.byref(ms), C.byref(n), C.byref(fl), 1 if reset else 0))
         return ms.value, n.value, fl.value
+
+    # -- batched ----------------------------------------------------------
+    def filter_batched(self, ops, Xs, m: int, a, b, aL, prec: int, block: int = 0, use_graph: bool = False):
+        n = len(ops)
+        VP = C.c_void_p * n
+        I64 = C.c_int64 * n
+        D = C.c_double * n
+        cols = [_ld_cols(X) for X in Xs]
+        self.check(self.lib.chfsi_filter_batched(
+            self.h, n, VP(*[o.h for o in ops]), VP(*[_tptr(X) for X in Xs]), I64(*[c[0] for c in cols]),
+            I64(*[c[1] for c in cols]), int(m), D(*a), D(*b), D(*aL), int(prec), int(block), 1 if use_graph else 0))
+
+    def solve_batched(self, ops, Xs, nwanted, m: int, block: int, filter_prec: int, n_buf=0, fixed_passes: int = 0,
+                      tol: float = 0.0, max_passes: int = 100, lanczos_v0=None, b_upper=None, use_graph: bool = True):
+        """chfsi_solve_batched; nwanted / n_buf / lanczos_v0 / b_upper may be per-problem lists."""
+        n = len(ops)
+
+        def per(x):
+            return list(x) if isinstance(x, (list, tuple)) else [x] * n
+
+        nw, nb, v0s, bs = per(nwanted), per(n_buf), per(lanczos_v0), per(b_upper)
+        P = (_lib.Params * n)()
+        keep = []
+        for q in range(n):
+            p = P[q]
+            p.nwanted, p.n_buf, p.m, p.block = nw[q], nb[q], m, block
+            p.fixed_passes, p.max_passes, p.tol = fixed_passes, max_passes, tol
+            p.filter_prec, p.lanczos_steps = int(filter_prec), 20
+            p.b_upper = float(bs[q]) if bs[q] is not None else 0.0
+            if v0s[q] is not None:
+                v = np.ascontiguousarray(v0s[q])
+                v = np.ascontiguousarray(v.view(np.float64) if np.iscomplexobj(v) else v, dtype=np.float64)
+                keep.append(v)
+                p.lanczos_v0 = _dptr(v)
+        cols = [_ld_cols(X) for X in Xs]
+        for q in range(n):
+            if cols[q][0] != nw[q] + nb[q]:
+                raise ValueError("X must have nwanted + n_buf columns")
+        th = [np.zeros(cols[q][0]) for q in range(n)]
+        rs = [np.zeros(cols[q][0]) for q in range(n)]
+        PD = C.POINTER(C.c_double) * n
+        st = (_lib.Stats * n)()
+        VP = C.c_void_p * n
+        rc = self.lib.chfsi_solve_batched(self.h, n, VP(*[o.h for o in ops]), P, VP(*[_tptr(X) for X in Xs]),
+                                          (C.c_int64 * n)(*[c[1] for c in cols]), PD(*[_dptr(t) for t in th]),
+                                          PD(*[_dptr(r) for r in rs]), st, 1 if use_graph else 0)
+        self.check(rc, allow=(0, 1))
+        stats = [{f: getattr(st[q], f) for f, _ in _lib.Stats._fields_} for q in range(n)]
+        return th, rs, stats
+
+    def autotune(self, p: int, prec: int, block: int, cache_json: Optional[str] = None):
+        self.check(self.lib.chfsi_autotune(self.h, cache_json.encode() if cache_json else None, int(p), int(prec),
+                                           int(block)))
+        return self.get_tuning(p, prec, block)
+
+    def load_tuning(self, cache_json: str):
+        self.check(self.lib.chfsi_load_tuning(self.h, cache_json.encode()))
+
+    def get_tuning(self, p: int, prec: int, block: int):
+        g, c, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self.check(self.lib.chfsi_get_tuning(self.h, int(p), int(prec), int(block), C.byref(g), C.byref(c),
+                                             C.byref(ms)))
+        return {"grid_per_cu": g.value, "contiguous": c.value, "ms": ms.value}
 
     def close(self):
         if getattr(self, "h", None):
@@ -260,3 +324,76 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+class Network:
+    """The warm-start network (chfsi_mlp_*): device features in, device block out."""
+
+    def __init__(self, ctx: Context, din: int = 32, hidden: int = 128, dout: int = 128, seed: int = 0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(ctx.lib.chfsi_mlp_create(ctx.h, int(din), int(hidden), int(dout), C.c_uint64(seed), C.byref(h)))
+        self.h = h
+        ctx._ops.add(self)
+        a, b, c, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        ctx.check(ctx.lib.chfsi_mlp_info(h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)))
+        self.din, self.hidden, self.dout, self.nparams = a.value, b.value, c.value, n.value
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        self.ctx.check(self.ctx.lib.chfsi_mlp_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), 1))
+        return out
+
+    def set_params(self, vec) -> None:
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        if v.size != self.nparams:
+            raise ValueError("wrong parameter count")
+        self.ctx.check(self.ctx.lib.chfsi_mlp_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float)), 0))
+
+    def set_norm(self, mean, scale) -> None:
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(scale, dtype=np.float32)
+        self.ctx.check(self.ctx.lib.chfsi_mlp_set_norm(self.h, m.ctypes.data_as(C.POINTER(C.c_float)),
+                                                       s.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def forward(self, F, Y) -> None:
+        self.ctx.check(self.ctx.lib.chfsi_mlp_forward(self.h, _tptr(F), F.shape[0], _tptr(Y)))
+
+    def loss_grad(self, F, Q, want_grads: bool = True):
+        loss = C.c_double()
+        g = np.zeros(self.nparams, dtype=np.float32) if want_grads else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grads else C.POINTER(C.c_float)()
+        self.ctx.check(self.ctx.lib.chfsi_mlp_loss_grad(self.h, _tptr(F), F.shape[0], _tptr(Q), Q.shape[1],
+                                                        C.byref(loss), gp))
+        return loss.value, g
+
+    def train_step(self, F, Q, lr: float = 1e-3) -> float:
+        loss = C.c_double()
+        self.ctx.check(self.ctx.lib.chfsi_mlp_train_step(self.h, _tptr(F), F.shape[0], _tptr(Q), Q.shape[1],
+                                                         C.c_float(lr), C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.chfsi_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(op: Operator, F) -> None:
+    """F (device float32, M x 32) <- radial features of the operator's atoms."""
+    op.ctx.check(op.ctx.lib.chfsi_features(op.h, _tptr(F)))
+
+
+def initial_block(op: Operator, X, net: Optional[Network] = None, seed: int = 0) -> bool:
+    """X (device float64, M x ld) <- warm start (or random); returns True if the fallback was used."""
+    ncols, ld = _ld_cols(X)
+    fb = C.c_int32()
+    op.ctx.check(op.ctx.lib.chfsi_initial_block(op.h, net.h if net is not None else None, C.c_uint64(seed),
+                                                _tptr(X), ncols, ld, C.byref(fb)))
+    return bool(fb.value)

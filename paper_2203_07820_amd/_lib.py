@@ -17,6 +17,10 @@ EXPORTS = [
     "chfsi_op_build", "chfsi_op_destroy", "chfsi_op_info", "chfsi_op_tables",
     "chfsi_apply", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_kernel_time",
+    "chfsi_filter_batched", "chfsi_solve_batched", "chfsi_autotune", "chfsi_load_tuning", "chfsi_get_tuning",
+    "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
+    "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
+    "chfsi_initial_block",
 ]
 
 
@@ -82,6 +86,23 @@ def load() -> C.CDLL:
         "chfsi_pass": (C.c_int, [vp, C.POINTER(Params), vp, i64, dbl, dbl, dbl, pd, pd]),
         "chfsi_set_timing": (C.c_int, [vp, i32]),
         "chfsi_kernel_time": (C.c_int, [vp, pd, C.POINTER(i64), pd, i32]),
+        "chfsi_filter_batched": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), C.POINTER(i64),
+                                           i32, pd, pd, pd, i32, i32, i32]),
+        "chfsi_solve_batched": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(Params), C.POINTER(vp),
+                                          C.POINTER(i64), C.POINTER(pd), C.POINTER(pd), C.POINTER(Stats), i32]),
+        "chfsi_autotune": (C.c_int, [vp, C.c_char_p, i32, i32, i32]),
+        "chfsi_load_tuning": (C.c_int, [vp, C.c_char_p]),
+        "chfsi_get_tuning": (C.c_int, [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), pd]),
+        "chfsi_features": (C.c_int, [vp, vp]),
+        "chfsi_mlp_create": (C.c_int, [vp, i32, i32, i32, u64, C.POINTER(vp)]),
+        "chfsi_mlp_destroy": (C.c_int, [vp]),
+        "chfsi_mlp_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]),
+        "chfsi_mlp_params": (C.c_int, [vp, C.POINTER(C.c_float), i32]),
+        "chfsi_mlp_set_norm": (C.c_int, [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+        "chfsi_mlp_forward": (C.c_int, [vp, vp, i64, vp]),
+        "chfsi_mlp_loss_grad": (C.c_int, [vp, vp, i64, vp, i32, pd, C.POINTER(C.c_float)]),
+        "chfsi_mlp_train_step": (C.c_int, [vp, vp, i64, vp, i32, C.c_float, pd]),
+        "chfsi_initial_block": (C.c_int, [vp, vp, u64, vp, i64, i64, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

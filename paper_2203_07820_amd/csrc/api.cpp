@@ -14,6 +14,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,114 +24,13 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
+#include "context.h"
 
 using namespace chfsi;
 
-namespace {
-
-enum Slot {
-  WS_R0, WS_R1, WS_R2, WS_R3,      // filter buffers
-  WS_NLPART, WS_HP,                // projector partials / scaled coefficients
-  WS_GPART, WS_G, WS_S, WS_Z, WS_Z2,
-  WS_W, WS_X2, WS_HPSI,            // M x N work blocks
-  WS_RPART, WS_VEC, WS_SMALL, WS_EIG, WS_INFO,
-  WS_COUNT
-};
-
-}  // namespace
-
-struct chfsi_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  rocblas_handle blas = nullptr;
-  std::string err;
-  void* ws[WS_COUNT] = {};
-  size_t ws_size[WS_COUNT] = {};
-  // opt-in timing of the cell kernel: event pairs not yet read, totals
-  bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  std::vector<double> pending_flops;
-  double t_ms = 0.0, t_flops = 0.0;
-  int64_t t_launches = 0;
-};
-
-struct chfsi_op {
-  chfsi_ctx* ctx = nullptr;
-  HostTables t;                      // host copies (large projector arrays dropped)
-  int64_t npairs = 0;
-  // device tables
-  void* A64 = nullptr;  void* Ai64 = nullptr;   // swizzled cell matrix, double
-  void* A32 = nullptr;  void* Ai32 = nullptr;   // float
-  void* Abf = nullptr;                          // bf16, 16x16x32 operand order
-  double* vdiag = nullptr;
-  int64_t* atom_ptr = nullptr;
-  int32_t* atom_node = nullptr;
-  double* atom_val = nullptr;
-  int32_t* chunk_atom = nullptr;
-  int64_t* chunk_begin = nullptr;
-  int32_t* atom_chunk_ptr = nullptr;
-  int nchunks = 0;
-  double* hcoef = nullptr;
-  int32_t* pair_ptr = nullptr;
-  int32_t* pair_atom = nullptr;
-  void* pair_re64 = nullptr; void* pair_im64 = nullptr;
-  void* pair_re32 = nullptr; void* pair_im32 = nullptr;
-  std::vector<void*> allocs;
-};
+thread_local std::string chfsi_host::g_create_err;
 
 namespace {
-
-thread_local std::string g_create_err;
-
-int fail(chfsi_ctx* c, int code, const std::string& msg) {
-  if (c) c->err = msg;
-  else g_create_err = msg;
-  return code;
-}
-
-#define HIP_TRY(ctx, expr)                                                                \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(ctx, CHFSI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-  } while (0)
-
-#define RB_TRY(ctx, expr)                                                                 \
-  do {                                                                                    \
-    rocblas_status s_ = (expr);                                                           \
-    if (s_ != rocblas_status_success)                                                     \
-      return fail(ctx, CHFSI_EHIP, std::string(#expr) + ": rocblas status " +             \
-                                       std::to_string(static_cast<int>(s_)));             \
-  } while (0)
-
-#define CHECK(expr)            \
-  do {                         \
-    int r_ = (expr);           \
-    if (r_ < 0) return r_;     \
-  } while (0)
-
-// Grow-only scratch slot.
-int ws_get(chfsi_ctx* c, int slot, size_t bytes, void** out) {
-  if (bytes == 0) bytes = 256;
-  if (c->ws_size[slot] < bytes) {
-    if (c->ws[slot]) {
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      HIP_TRY(c, hipFree(c->ws[slot]));
-      c->ws[slot] = nullptr;
-      c->ws_size[slot] = 0;
-    }
-    const size_t b = (bytes + 4095) / 4096 * 4096;
-    hipError_t e = hipMalloc(&c->ws[slot], b);
-    if (e != hipSuccess) {
-      c->ws[slot] = nullptr;
-      return fail(c, CHFSI_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-    }
-    c->ws_size[slot] = b;
-  }
-  *out = c->ws[slot];
-  return 0;
-}
 
 template <typename T>
 int upload(chfsi_op* op, const std::vector<T>& v, T** out) {
@@ -171,41 +73,43 @@ size_t prec_bytes(int prec) {
 int storage_of(int prec) { return prec == CHFSI_BF16 ? CHFSI_F32 : prec; }
 bool is_single(int prec) { return prec == CHFSI_F32 || prec == CHFSI_BF16 || prec == CHFSI_C64; }
 
-// Y = alpha (H~ Xk - c Xk) - beta Xp  accumulated into T (which must hold 0
-// on entry).  Xk, Xp, T are in the storage type of prec, logical ld.
-int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp, int64_t ldp, void* T,
-            int64_t ldt, int64_t ncols, double alpha, double c, double beta, bool zero_prev) {
+// P = h * C^H Xk for the projectors of op (node-level lists, deterministic
+// two-phase sum) into hP (natoms*4 x ldhp, real view), using `part` as the
+// chunk partials (nchunks*4 x ldhp).
+int nl_project(chfsi_op* op, int prec, const void* Xk, int64_t ldx, int64_t ncols, void* part, void* hP,
+               int64_t ldhp) {
   chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  NlLaunch nl;
+  nl.natoms = t.natoms;
+  nl.cplx = t.cplx;
+  nl.ncols = static_cast<int>(ncols);
+  nl.atom_ptr = op->atom_ptr;
+  nl.atom_node = op->atom_node;
+  nl.atom_val = op->atom_val;
+  nl.chunk_atom = op->chunk_atom;
+  nl.chunk_begin = op->chunk_begin;
+  nl.nchunks = op->nchunks;
+  nl.atom_chunk_ptr = op->atom_chunk_ptr;
+  nl.hcoef = op->hcoef;
+  nl.X = Xk;
+  nl.ldx = ldx;
+  nl.partial = part;
+  nl.hP = hP;
+  nl.ldhp = ldhp;
+  HIP_TRY(ctx, launch_nl_project(nl, prec, ctx->stream));
+  return 0;
+}
+
+int64_t hp_ld(const chfsi_op* op, int64_t ncols) { return (ncols * (op->t.cplx ? 2 : 1) + 63) / 64 * 64; }
+
+// Kernel arguments of one step T += alpha (H~ Xk - c Xk) - beta Xp (logical lds).
+HxLaunch make_hx(const chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp, int64_t ldp, void* T,
+                 int64_t ldt, int64_t ncols, double alpha, double c, double beta, bool zero_prev, const void* hP,
+                 int64_t ldhp) {
   const HostTables& t = op->t;
   const int cf = t.cplx ? 2 : 1;
   const bool single = is_single(prec);
-  void* hP = nullptr;
-  int64_t ldhp = 0;
-  if (t.has_proj) {
-    ldhp = (ncols * cf + 63) / 64 * 64;
-    const size_t eb = single ? 4 : 8;
-    void* part = nullptr;
-    CHECK(ws_get(ctx, WS_NLPART, static_cast<size_t>(op->nchunks) * 4 * ldhp * eb, &part));
-    CHECK(ws_get(ctx, WS_HP, static_cast<size_t>(t.natoms) * 4 * ldhp * eb, &hP));
-    NlLaunch nl;
-    nl.natoms = t.natoms;
-    nl.cplx = t.cplx;
-    nl.ncols = static_cast<int>(ncols);
-    nl.atom_ptr = op->atom_ptr;
-    nl.atom_node = op->atom_node;
-    nl.atom_val = op->atom_val;
-    nl.chunk_atom = op->chunk_atom;
-    nl.chunk_begin = op->chunk_begin;
-    nl.nchunks = op->nchunks;
-    nl.atom_chunk_ptr = op->atom_chunk_ptr;
-    nl.hcoef = op->hcoef;
-    nl.X = Xk;
-    nl.ldx = ldx;
-    nl.partial = part;
-    nl.hP = hP;
-    nl.ldhp = ldhp;
-    HIP_TRY(ctx, launch_nl_project(nl, prec, ctx->stream));
-  }
   HxLaunch L;
   L.p = t.p;
   L.nc = t.ncell;
@@ -231,6 +135,36 @@ int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp,
   L.hP = hP;
   L.ldhp = ldhp;
   L.Abf = op->Abf;
+  return L;
+}
+
+// algorithmic flops of one step over ncols logical columns (padding excluded)
+double hx_flops(const chfsi_op* op, int64_t ncols) {
+  const HostTables& t = op->t;
+  const double cfl = t.cplx ? 4.0 : 1.0;
+  double fl = 2.0 * t.mcell * static_cast<double>(t.mcell) * static_cast<double>(ncols) * t.E * cfl;
+  if (t.has_proj) fl += 2.0 * 2.0 * t.mcell * 4.0 * static_cast<double>(ncols) * op->npairs * cfl;
+  return fl;
+}
+
+// Y = alpha (H~ Xk - c Xk) - beta Xp  accumulated into T (which must hold 0
+// on entry).  Xk, Xp, T are in the storage type of prec, logical ld.
+int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp, int64_t ldp, void* T,
+            int64_t ldt, int64_t ncols, double alpha, double c, double beta, bool zero_prev) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const bool single = is_single(prec);
+  void* hP = nullptr;
+  int64_t ldhp = 0;
+  if (t.has_proj) {
+    ldhp = hp_ld(op, ncols);
+    const size_t eb = single ? 4 : 8;
+    void* part = nullptr;
+    CHECK(ws_get(ctx, WS_NLPART, static_cast<size_t>(op->nchunks) * 4 * ldhp * eb, &part));
+    CHECK(ws_get(ctx, WS_HP, static_cast<size_t>(t.natoms) * 4 * ldhp * eb, &hP));
+    CHECK(nl_project(op, prec, Xk, ldx, ncols, part, hP, ldhp));
+  }
+  HxLaunch L = make_hx(op, prec, Xk, ldx, Xp, ldp, T, ldt, ncols, alpha, c, beta, zero_prev, hP, ldhp);
   const int kp = prec;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
@@ -242,12 +176,7 @@ int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp,
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     ctx->pending.emplace_back(e0, e1);
-    // algorithmic flops: dense cell products (padding excluded) and the
-    // nonlocal cell products of the (cell, atom) pairs; x4 for complex
-    const double cfl = t.cplx ? 4.0 : 1.0;
-    double fl = 2.0 * t.mcell * static_cast<double>(t.mcell) * static_cast<double>(ncols) * t.E * cfl;
-    if (t.has_proj) fl += 2.0 * 2.0 * t.mcell * 4.0 * static_cast<double>(ncols) * op->npairs * cfl;
-    ctx->pending_flops.push_back(fl);
+    ctx->pending_flops.push_back(hx_flops(op, ncols));
   }
   return 0;
 }
@@ -472,23 +401,6 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
   return 0;
 }
 
-// splitmix64 (Steele, Lea, Flood 2014) + Box-Muller: the library's own
-// generator for start vectors when the caller gives none.
-struct SplitMix {
-  uint64_t s;
-  uint64_t next() {
-    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-    return z ^ (z >> 31);
-  }
-  double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
-  double normal() {
-    const double u1 = uniform(), u2 = uniform();
-    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
-  }
-};
-
 // Eigenvalues of a small symmetric matrix by cyclic Jacobi rotations.
 std::vector<double> small_eigvals(std::vector<double> A, int n) {
   for (int sweep = 0; sweep < 100; ++sweep) {
@@ -614,6 +526,244 @@ double event_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+
+// ---- batched filter over many operators (one persistent launch per step) ----
+
+struct BItem {
+  chfsi_op* op;
+  double* X;       // subspace block (double / complex double)
+  int64_t ncols;   // logical columns
+  int64_t ld;
+  double a, b, aL;
+};
+
+std::string tune_key(int p, int prec, int64_t block) {
+  return "gfx950:p" + std::to_string(p) + ":prec" + std::to_string(prec) + ":B" + std::to_string(block);
+}
+
+chfsi_ctx::Tuning tuning_for(chfsi_ctx* ctx, int p, int prec, int64_t block) {
+  auto it = ctx->tuning.find(tune_key(p, prec, block));
+  if (it != ctx->tuning.end()) return it->second;
+  chfsi_ctx::Tuning t;
+  t.grid_per_cu = (prec == CHFSI_C128) ? 1 : 2;  // resident workgroups per CU
+  return t;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int pinned_get(chfsi_ctx* ctx, size_t bytes, void** out) {
+  if (ctx->pinned_size < bytes) {
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_size = 0;
+    HIP_TRY(ctx, hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+    ctx->pinned_size = bytes;
+  }
+  *out = ctx->pinned;
+  return 0;
+}
+
+void drop_graph(chfsi_ctx* ctx) {
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+  ctx->gkey.clear();
+}
+
+// Filters every item's block X (all columns, in rounds of `block` columns)
+// with degree m on its own [a, b], aL.  Each Chebyshev step of a round is one
+// persistent launch over all items (cell_hx_batched_kernel); the per-item
+// recurrence scalars live in device descriptor tables written before the
+// launch, so with use_graph the whole sequence is captured once into a
+// hipGraph and replayed while the tables change.
+int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int prec, int64_t block,
+                   bool use_graph, const chfsi_ctx::Tuning* force = nullptr) {
+  const int n = static_cast<int>(items.size());
+  if (n == 0) return 0;
+  const int p = items[0].op->t.p;
+  const bool cplx = items[0].op->t.cplx;
+  for (const BItem& it : items) {
+    if (it.op->ctx != ctx) return fail(ctx, CHFSI_EINVAL, "operators of a batch must share the context");
+    if (it.op->t.p != p || it.op->t.cplx != cplx)
+      return fail(ctx, CHFSI_EINVAL, "operators of a batch must share order p and real/complex type");
+    if (!prec_valid_for(it.op, prec)) return fail(ctx, CHFSI_EINVAL, "precision does not match the operators");
+    if (prec == CHFSI_BF16) return fail(ctx, CHFSI_EINVAL, "batched filter supports F64, F32, C128, C64");
+    if (!(it.aL < it.a && it.a < it.b)) return fail(ctx, CHFSI_EINVAL, "need aL < a < b for every item");
+  }
+  const int cf = cplx ? 2 : 1;
+  const int sp = storage_of(prec);
+  const int xprec = cplx ? CHFSI_C128 : CHFSI_F64;
+  const size_t ebl = prec_bytes(sp);           // bytes per logical entry
+  const size_t esc = is_single(prec) ? 4 : 8;  // bytes per real scalar
+  std::vector<int64_t> Bq(n);
+  int rounds = 0;
+  for (int q = 0; q < n; ++q) {
+    Bq[q] = (block <= 0 || block > items[q].ncols) ? items[q].ncols : block;
+    rounds = std::max<int>(rounds, static_cast<int>((items[q].ncols + Bq[q] - 1) / Bq[q]));
+  }
+  // workspace: per item R0..R3, projector partials and coefficients
+  std::vector<size_t> offR(n), offPart(n), offHP(n);
+  std::vector<int64_t> ldhp(n);
+  size_t total = 0;
+  for (int q = 0; q < n; ++q) {
+    const chfsi_op* op = items[q].op;
+    offR[q] = total;
+    total += align256(static_cast<size_t>(op->t.M) * Bq[q] * ebl) * 4;
+    ldhp[q] = hp_ld(op, Bq[q]);
+    offPart[q] = total;
+    if (op->t.has_proj) total += align256(static_cast<size_t>(op->nchunks) * 4 * ldhp[q] * esc);
+    offHP[q] = total;
+    if (op->t.has_proj) total += align256(static_cast<size_t>(op->t.natoms) * 4 * ldhp[q] * esc);
+  }
+  const size_t db = hx_desc_bytes(prec);
+  const size_t tab_desc = static_cast<size_t>(rounds) * m * n * db;
+  const size_t tab_off = static_cast<size_t>(rounds) * (n + 1) * sizeof(int64_t);
+  const size_t tab_bytes = align256(tab_desc) + tab_off;
+  void *wsb, *tab, *host;
+  CHECK(ws_get(ctx, WS_BATCH, total, &wsb));
+  CHECK(ws_get(ctx, WS_BTAB, tab_bytes, &tab));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the staging buffer is rewritten below
+  CHECK(pinned_get(ctx, tab_bytes, &host));
+  char* base = static_cast<char*>(wsb);
+  auto R = [&](int q, int i) { return static_cast<void*>(base + offR[q] + align256(static_cast<size_t>(items[q].op->t.M) * Bq[q] * ebl) * i); };
+  // host tables
+  std::memset(host, 0, tab_bytes);
+  char* hdesc = static_cast<char*>(host);
+  int64_t* hoff = reinterpret_cast<int64_t*>(static_cast<char*>(host) + align256(tab_desc));
+  std::vector<std::vector<int>> active(rounds);
+  std::vector<std::vector<int64_t>> width(rounds);
+  for (int r = 0; r < rounds; ++r) {
+    int64_t acc = 0;
+    for (int q = 0; q < n; ++q) {
+      const int64_t c0 = r * Bq[q];
+      if (c0 >= items[q].ncols) continue;
+      const int64_t nb = std::min<int64_t>(Bq[q], items[q].ncols - c0);
+      active[r].push_back(q);
+      width[r].push_back(nb);
+    }
+    const int na = static_cast<int>(active[r].size());
+    for (int k = 0; k < na; ++k) {
+      const int q = active[r][k];
+      const chfsi_op* op = items[q].op;
+      hoff[r * (n + 1) + k] = acc;
+      acc += op->t.E * ((width[r][k] * cf + 63) / 64);
+      double c;
+      std::vector<double> al, be;
+      cheb_coeffs(m, items[q].a, items[q].b, items[q].aL, &c, al, be);
+      const int64_t nb = width[r][k];
+      for (int st = 1; st <= m; ++st) {
+        HxLaunch L = make_hx(op, prec, R(q, (st - 1) % 4), nb, st >= 2 ? R(q, (st - 2) % 4) : nullptr, nb,
+                             R(q, st % 4), nb, nb, al[st - 1], c, st >= 2 ? be[st - 1] : 0.0, st >= 2,
+                             op->t.has_proj ? base + offHP[q] : nullptr, ldhp[q]);
+        pack_hx_desc(L, prec, hdesc + ((static_cast<size_t>(r) * m + (st - 1)) * n + k) * db);
+      }
+    }
+    for (int k = na; k <= n; ++k) hoff[r * (n + 1) + k] = acc;
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(tab, host, tab_bytes, hipMemcpyHostToDevice, ctx->stream));
+  const char* dtab = static_cast<const char*>(tab);
+  const int64_t* doff = reinterpret_cast<const int64_t*>(dtab + align256(tab_desc));
+  const chfsi_ctx::Tuning tu = force ? *force : tuning_for(ctx, p, prec, block);
+
+  auto enqueue = [&]() -> int {
+    for (int r = 0; r < rounds; ++r) {
+      const int na = static_cast<int>(active[r].size());
+      for (int k = 0; k < na; ++k) {
+        const int q = active[r][k];
+        const int64_t nb = width[r][k];
+        const int64_t M = items[q].op->t.M;
+        double* Xb = items[q].X + r * Bq[q] * cf;
+        HIP_TRY(ctx, launch_convert(R(q, 0), nb * cf, sp, Xb, items[q].ld * cf, xprec, M, nb * cf, ctx->stream));
+        for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R(q, i), M, nb * cf, nb * cf, sp, ctx->stream));
+      }
+      for (int st = 1; st <= m; ++st) {
+        for (int k = 0; k < na; ++k) {
+          const int q = active[r][k];
+          chfsi_op* op = items[q].op;
+          if (op->t.has_proj)
+            CHECK(nl_project(op, prec, R(q, (st - 1) % 4), width[r][k], width[r][k], base + offPart[q],
+                             base + offHP[q], ldhp[q]));
+        }
+        HxBatch hb;
+        hb.p = p;
+        hb.descs = dtab + (static_cast<size_t>(r) * m + (st - 1)) * n * db;
+        hb.item_off = doff + r * (n + 1);
+        hb.nprob = na;
+        hb.grid = std::max(1, ctx->ncu * tu.grid_per_cu);
+        hb.contiguous = tu.contiguous;
+        HIP_TRY(ctx, launch_cell_hx_batched(hb, prec, ctx->stream));
+      }
+      for (int k = 0; k < na; ++k) {
+        const int q = active[r][k];
+        const int64_t nb = width[r][k];
+        double* Xb = items[q].X + r * Bq[q] * cf;
+        HIP_TRY(ctx, launch_convert(Xb, items[q].ld * cf, xprec, R(q, m % 4), nb * cf, sp, items[q].op->t.M,
+                                    nb * cf, ctx->stream));
+      }
+    }
+    return 0;
+  };
+  if (!use_graph) return enqueue();
+  // the graph is keyed by everything its nodes point at
+  std::ostringstream key;
+  key << m << ":" << prec << ":" << block << ":" << wsb << ":" << tab << ":" << tu.grid_per_cu << ":" << tu.contiguous;
+  for (const BItem& it : items) key << ":" << it.op << "," << it.X << "," << it.ncols << "," << it.ld;
+  if (key.str() != ctx->gkey || !ctx->gexec) {
+    drop_graph(ctx);
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, CHFSI_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    ctx->graph = g;
+    HIP_TRY(ctx, hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+    ctx->gkey = key.str();
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+  return 0;
+}
+
+int load_tuning_file(chfsi_ctx* ctx, const std::string& path) {
+  std::ifstream f(path);
+  if (!f) return 0;
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t k0 = line.find("\"key\": \"");
+    if (k0 == std::string::npos) continue;
+    const size_t k1 = line.find('"', k0 + 8);
+    chfsi_ctx::Tuning t;
+    const size_t g = line.find("\"grid_per_cu\": ");
+    const size_t c = line.find("\"contiguous\": ");
+    const size_t ms = line.find("\"ms\": ");
+    if (k1 == std::string::npos || g == std::string::npos || c == std::string::npos) continue;
+    t.grid_per_cu = std::atoi(line.c_str() + g + 15);
+    t.contiguous = std::atoi(line.c_str() + c + 14);
+    if (ms != std::string::npos) t.ms = std::atof(line.c_str() + ms + 6);
+    if (t.grid_per_cu >= 1 && t.grid_per_cu <= 16) ctx->tuning[line.substr(k0 + 8, k1 - k0 - 8)] = t;
+  }
+  return 0;
+}
+
+int save_tuning_file(chfsi_ctx* ctx, const std::string& path) {
+  std::ofstream f(path);
+  if (!f) return fail(ctx, CHFSI_EINVAL, "cannot write tuning cache " + path);
+  f << "[\n";
+  size_t i = 0;
+  for (const auto& kv : ctx->tuning) {
+    f << "{\"key\": \"" << kv.first << "\", \"grid_per_cu\": " << kv.second.grid_per_cu
+      << ", \"contiguous\": " << kv.second.contiguous << ", \"ms\": " << kv.second.ms << "}"
+      << (++i < ctx->tuning.size() ? "," : "") << "\n";
+  }
+  f << "]\n";
+  return 0;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -634,6 +784,9 @@ int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
   std::unique_ptr<chfsi_ctx> c(new chfsi_ctx());
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, CHFSI_EHIP, "hipGetDeviceProperties failed");
+  c->ncu = prop.multiProcessorCount;
   if (rocblas_create_handle(&c->blas) != rocblas_status_success)
     return fail(nullptr, CHFSI_EHIP, "rocblas_create_handle failed");
   if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
@@ -649,6 +802,9 @@ int chfsi_ctx_destroy(chfsi_ctx* ctx) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -1001,6 +1157,224 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
     ctx->err = "tolerance not met";
     return CHFSI_NOTCONV;
   }
+  return 0;
+}
+
+int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* const* X, const int64_t* ncols,
+                         const int64_t* ld, int32_t m, const double* a, const double* b, const double* aL,
+                         int32_t prec, int32_t block, int32_t use_graph) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (n < 1 || !ops || !X || !ncols || !ld || !a || !b || !aL) return fail(ctx, CHFSI_EINVAL, "null argument");
+  if (m < 1) return fail(ctx, CHFSI_EINVAL, "degree m must be >= 1");
+  std::vector<BItem> items(n);
+  for (int q = 0; q < n; ++q) {
+    if (!ops[q]) return fail(ctx, CHFSI_EINVAL, "null operator");
+    CHECK(check_block(ops[q], X[q], ncols[q], ld[q]));
+    items[q] = BItem{ops[q], static_cast<double*>(X[q]), ncols[q], ld[q], a[q], b[q], aL[q]};
+  }
+  return batched_filter(ctx, items, m, prec, block, use_graph != 0);
+}
+
+int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const chfsi_params* params,
+                        void* const* Xv, const int64_t* ld, double* const* theta, double* const* resid,
+                        chfsi_stats* stats, int32_t use_graph) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (n < 1 || !ops || !params || !Xv || !ld || !theta) return fail(ctx, CHFSI_EINVAL, "null argument");
+  const int m = params[0].m;
+  const int prec = params[0].filter_prec;
+  const int64_t block = params[0].block;
+  std::vector<int64_t> N(n);
+  for (int q = 0; q < n; ++q) {
+    const chfsi_params& pr = params[q];
+    if (!ops[q] || !theta[q]) return fail(ctx, CHFSI_EINVAL, "null operator or output");
+    if (ops[q]->ctx != ctx) return fail(ctx, CHFSI_EINVAL, "operators must share the context");
+    if (pr.m != m || pr.filter_prec != prec || pr.block != block)
+      return fail(ctx, CHFSI_EINVAL, "m, block and filter_prec must be equal across the batch");
+    if (pr.nwanted < 1 || pr.n_buf < 0 || pr.m < 1) return fail(ctx, CHFSI_EINVAL, "bad parameters");
+    if (pr.fixed_passes <= 0 && !(pr.tol > 0.0)) return fail(ctx, CHFSI_EINVAL, "need fixed_passes or tol");
+    N[q] = static_cast<int64_t>(pr.nwanted) + pr.n_buf;
+    CHECK(check_block(ops[q], Xv[q], N[q], ld[q]));
+    if (!prec_valid_for(ops[q], prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  struct G2 { hipEvent_t a, b; ~G2() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } guard{e0, e1};
+  std::vector<double> bq(n), aq(n), aLq(n);
+  std::vector<std::vector<double>> th(n), r(n);
+  std::vector<int> passes(n, 0);
+  std::vector<char> done(n, 0);
+  std::vector<double> tfilt(n, 0.0), tcg(n, 0.0), trr(n, 0.0);
+  for (int q = 0; q < n; ++q) {
+    chfsi_op* op = ops[q];
+    const chfsi_params& pr = params[q];
+    double b = pr.b_upper;
+    if (!(b > 0.0)) {
+      double lmin;
+      CHECK(do_bounds(op, pr.lanczos_steps > 0 ? pr.lanczos_steps : 20, nullptr, pr.lanczos_v0, pr.seed, &b, &lmin));
+    }
+    bq[q] = b;
+    const int cf = op->t.cplx ? 2 : 1;
+    void* X2v;
+    CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * N[q] * 8 * cf, &X2v));
+    th[q].assign(N[q], 0.0);
+    r[q].assign(N[q], 0.0);
+    CHECK(cholgs(op, static_cast<double*>(Xv[q]), ld[q], static_cast<double*>(X2v), N[q], N[q], nullptr));
+    CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N[q], static_cast<double*>(Xv[q]), ld[q], N[q],
+                        th[q].data(), r[q].data()));
+  }
+  auto converged = [&](int q) {
+    const chfsi_params& pr = params[q];
+    const int limit = pr.fixed_passes > 0 ? pr.fixed_passes : (pr.max_passes > 0 ? pr.max_passes : 100);
+    if (passes[q] >= limit) return true;
+    if (pr.fixed_passes > 0) return false;
+    double mr = 0.0;
+    for (int i = 0; i < pr.nwanted; ++i) mr = std::max(mr, r[q][i]);
+    return mr <= pr.tol;
+  };
+  for (;;) {
+    std::vector<BItem> items;
+    std::vector<int> idx;
+    for (int q = 0; q < n; ++q) {
+      if (done[q] || converged(q)) { done[q] = 1; continue; }
+      aq[q] = th[q][N[q] - 1];
+      aLq[q] = th[q][0];
+      if (!(aLq[q] < aq[q] && aq[q] < bq[q])) return fail(ctx, CHFSI_EDIVERGE, "filter interval collapsed");
+      items.push_back(BItem{ops[q], static_cast<double*>(Xv[q]), N[q], ld[q], aq[q], bq[q], aLq[q]});
+      idx.push_back(q);
+    }
+    if (items.empty()) break;
+    HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+    CHECK(batched_filter(ctx, items, m, prec, block, use_graph != 0));
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(e1));
+    const double tf = event_ms(e0, e1);
+    for (int q : idx) {
+      chfsi_op* op = ops[q];
+      const int cf = op->t.cplx ? 2 : 1;
+      void* X2v;
+      CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * N[q] * 8 * cf, &X2v));
+      HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+      CHECK(cholgs(op, static_cast<double*>(Xv[q]), ld[q], static_cast<double*>(X2v), N[q], N[q], nullptr));
+      CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N[q], static_cast<double*>(Xv[q]), ld[q], N[q],
+                          th[q].data(), r[q].data()));
+      HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+      HIP_TRY(ctx, hipEventSynchronize(e1));
+      trr[q] += event_ms(e0, e1);
+      tfilt[q] += tf;
+      ++passes[q];
+      for (int64_t i = 0; i < N[q]; ++i)
+        if (!std::isfinite(th[q][i]) || !std::isfinite(r[q][i]))
+          return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values");
+    }
+  }
+  drop_graph(ctx);
+  int rc = 0;
+  for (int q = 0; q < n; ++q) {
+    std::memcpy(theta[q], th[q].data(), N[q] * 8);
+    if (resid && resid[q]) std::memcpy(resid[q], r[q].data(), N[q] * 8);
+    double mr = 0.0;
+    for (int i = 0; i < params[q].nwanted; ++i) mr = std::max(mr, r[q][i]);
+    if (stats) {
+      chfsi_stats& st = stats[q];
+      std::memset(&st, 0, sizeof(st));
+      st.passes = passes[q];
+      st.t_filter = tfilt[q];
+      st.t_rr = trr[q];
+      st.b_upper = bq[q];
+      st.a_last = aq[q];
+      st.aL_last = aLq[q];
+      st.max_resid = mr;
+      st.hx_columns = static_cast<int64_t>(passes[q]) * (N[q] * m + N[q]) + N[q];
+      st.hx_flops = static_cast<double>(passes[q]) * hx_flops(ops[q], N[q] * m + N[q]);
+    }
+    if (params[q].fixed_passes <= 0 && mr > params[q].tol) rc = CHFSI_NOTCONV;
+  }
+  if (rc == CHFSI_NOTCONV) ctx->err = "tolerance not met for at least one problem";
+  return rc;
+}
+
+int chfsi_autotune(chfsi_ctx* ctx, const char* cache_json, int32_t p, int32_t prec, int32_t block) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (p < kMinOrder || p > kMaxOrder) return fail(ctx, CHFSI_EINVAL, "order p must be in [2, 7]");
+  if (prec != CHFSI_F64 && prec != CHFSI_F32 && prec != CHFSI_C128 && prec != CHFSI_C64)
+    return fail(ctx, CHFSI_EINVAL, "autotune supports F64, F32, C128, C64");
+  if (block < 1 || block > 1024) return fail(ctx, CHFSI_EINVAL, "block must be in [1, 1024]");
+  if (cache_json) CHECK(load_tuning_file(ctx, cache_json));
+  // synthetic batch: 4 uneven empty periodic boxes of order p (h = 2 bohr)
+  const bool cplx = (prec == CHFSI_C128 || prec == CHFSI_C64);
+  const int ncs[4] = {6, 8, 9, 10};
+  std::vector<chfsi_op*> ops;
+  std::vector<void*> bufs;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto* o : ops) chfsi_op_destroy(o);
+    for (void* b : bufs) (void)hipFree(b);
+  };
+  int rc = 0;
+  std::vector<BItem> items;
+  for (int i = 0; i < 4 && rc == 0; ++i) {
+    chfsi_system sys;
+    std::memset(&sys, 0, sizeof(sys));
+    sys.L = 2.0 * ncs[i];
+    sys.ncell = ncs[i];
+    sys.p = p;
+    if (cplx) { sys.k[0] = 0.1; sys.k[1] = 0.05; sys.k[2] = -0.07; }
+    chfsi_op* op = nullptr;
+    rc = chfsi_op_build(ctx, &sys, &op);
+    if (rc < 0) break;
+    ops.push_back(op);
+    const int cf = cplx ? 2 : 1;
+    void* X = nullptr;
+    const size_t bytes = static_cast<size_t>(op->t.M) * block * 8 * cf;
+    if (hipMalloc(&X, bytes) != hipSuccess) { rc = fail(ctx, CHFSI_ENOMEM, "autotune allocation failed"); break; }
+    bufs.push_back(X);
+    if (hipMemsetAsync(X, 0, bytes, ctx->stream) != hipSuccess) { rc = fail(ctx, CHFSI_EHIP, "memset failed"); break; }
+    items.push_back(BItem{op, static_cast<double*>(X), block, block, 1.0, 4.0, -1.0});
+  }
+  if (rc < 0) { cleanup(); return rc; }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  chfsi_ctx::Tuning best;
+  best.ms = 1e300;
+  const int m = 4;
+  for (int g = 1; g <= 4 && rc == 0; ++g)
+    for (int cont = 1; cont >= 0 && rc == 0; --cont) {
+      chfsi_ctx::Tuning t;
+      t.grid_per_cu = g;
+      t.contiguous = cont;
+      rc = batched_filter(ctx, items, m, prec, block, false, &t);  // warm-up
+      if (rc < 0) break;
+      (void)hipEventRecord(e0, ctx->stream);
+      rc = batched_filter(ctx, items, m, prec, block, false, &t);
+      if (rc < 0) break;
+      (void)hipEventRecord(e1, ctx->stream);
+      (void)hipEventSynchronize(e1);
+      t.ms = event_ms(e0, e1);
+      if (t.ms < best.ms) best = t;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cleanup();
+  if (rc < 0) return rc;
+  ctx->tuning[tune_key(p, prec, block)] = best;
+  if (cache_json) CHECK(save_tuning_file(ctx, cache_json));
+  return 0;
+}
+
+int chfsi_load_tuning(chfsi_ctx* ctx, const char* cache_json) {
+  if (!ctx || !cache_json) return CHFSI_EINVAL;
+  return load_tuning_file(ctx, cache_json);
+}
+
+int chfsi_get_tuning(chfsi_ctx* ctx, int32_t p, int32_t prec, int32_t block, int32_t* grid_per_cu,
+                     int32_t* contiguous, double* ms) {
+  if (!ctx) return CHFSI_EINVAL;
+  const chfsi_ctx::Tuning t = tuning_for(ctx, p, prec, block);
+  if (grid_per_cu) *grid_per_cu = t.grid_per_cu;
+  if (contiguous) *contiguous = t.contiguous;
+  if (ms) *ms = t.ms;
   return 0;
 }
 

@@ -47,6 +47,7 @@ struct HostTables {
   std::vector<int32_t> pair_atom;   // npairs
   std::vector<double> pair_re;      // npairs * (mpad/16) * 64
   std::vector<double> pair_im;      // complex only
+  std::vector<double> atoms;        // natoms x 8: x, y, z, Z, s, h_s, h_p, 0
 };
 
 // Builds the tables on the host (op_build.cpp).  Returns "" or an error text.
@@ -85,6 +86,22 @@ struct HxLaunch {
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).
 hipError_t launch_cell_hx(const HxLaunch& a, int prec, hipStream_t s);
+
+// Many problems of the same order and precision in one persistent launch.
+// descs: device array of nprob packed kernel argument blocks (pack_hx_desc);
+// item_off: device array of nprob + 1 item offsets (items of problem q are
+// its E_q x ceil(ncols_q / 64) (cell, column tile) pairs).
+struct HxBatch {
+  int p;
+  const void* descs;
+  const int64_t* item_off;
+  int nprob;
+  int grid;        // persistent workgroups
+  int contiguous;  // 1: contiguous item range per workgroup, 0: strided
+};
+size_t hx_desc_bytes(int prec);
+void pack_hx_desc(const HxLaunch& L, int prec, void* out);
+hipError_t launch_cell_hx_batched(const HxBatch& b, int prec, hipStream_t s);
 
 struct NlLaunch {
   int natoms;
@@ -136,5 +153,28 @@ hipError_t launch_gram_combine_complex(const double* G2, int64_t ldg2, double* S
 // real 2n1 x 2n2 expansion of a complex matrix: mode 0 row-major Z, mode 1
 // column-major L^-1 -> Z = L^-H (upper), mode 2 column-major Q -> Z = Q
 hipError_t launch_expand_complex(const double* Z, int n1, int n2, int mode, double* Z2, hipStream_t s);
+
+// ---- warm-start network kernels (kernels_mlp.hip), FP32 -------------------
+// C = epi(A W) with A (M x K, lda), W read as W[k * swk + n * swn], N <= 128.
+// mode 0: + bias (nullable); 1: tanh(. + bias); 2: D0 - A W; 3: (A W) * (1 - D0^2).
+hipError_t mlp_gemm(const float* A, int64_t lda, const float* W, int64_t swk, int64_t swn, float* C, int64_t ldc,
+                    int64_t M, int K, int N, int mode, const float* bias, const float* D0, int64_t ldd, hipStream_t s);
+// G = A^T B (KA x KB <= 128 x 128, ldg) with a deterministic split over rows.
+size_t mlp_gram_partial_bytes(int64_t M);
+hipError_t mlp_gram(const float* A, int64_t lda, int KA, const float* B, int64_t ldb, int KB, int64_t M, float* part,
+                    float* G, int ldg, hipStream_t s);
+size_t mlp_colsum_partial_bytes(int64_t M, int N);
+hipError_t mlp_colsum(const float* A, int64_t lda, int N, int64_t M, double* part, float* out, hipStream_t s);
+int mlp_dot_blocks();
+hipError_t mlp_dot(const float* x, const float* y, int64_t n, double* part, hipStream_t s);
+hipError_t mlp_loss_small(const float* G, int n, double sY, float* D, double* out, hipStream_t s);
+hipError_t mlp_combine(float c1, const float* R, float c2, const float* Y, float c3, const float* YD, float* dY,
+                       int64_t n, hipStream_t s);
+hipError_t mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                    int t, hipStream_t s);
+hipError_t mlp_normalize(const float* F, const float* mean, const float* stdv, float* Fn, int64_t M, int din,
+                         hipStream_t s);
+hipError_t launch_features(const double* x1d, int n, double L, const double* atoms, int natoms, int kimg, double eta,
+                           double rcut, float* F, hipStream_t s);
 
 }  // namespace chfsi

@@ -23,6 +23,8 @@
 // ((cx p + a) mod n, ...).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "internal.h"
 
 namespace chfsi {
@@ -91,9 +93,18 @@ struct HxArgs {
 // A fragments of the next LDS chunk are loaded into registers before the
 // gather of that chunk is issued: vector-memory counters retire in order, so
 // the MFMAs of a chunk never wait for the (HBM-latency) gather loads.
-template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
-cell_hx_kernel(const HxArgs<T> a) {
+template <int P, int KPC> struct CellShape {
+  static constexpr int Q = P + 1;
+  static constexpr int MC = Q * Q * Q;
+  static constexpr int MP = (MC + 15) / 16 * 16;
+  static constexpr int KC = 4 * KPC;  // cell rows per LDS chunk
+};
+
+// One work item: cell `cell`, columns [col0, col0 + 64).  xs is the
+// workgroup's LDS staging buffer (2 x KC x 64).
+template <int P, typename T, bool CPLX, int WAVES, int KPC>
+__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
+                                          T (*xs)[4 * KPC][kNT]) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
   constexpr int MP = (MC + 15) / 16 * 16;
@@ -108,17 +119,11 @@ cell_hx_kernel(const HxArgs<T> a) {
   static_assert(MP % KC == 0 && RT % RG == 0 && KC % WAVES == 0, "tiling");
   using acc_t = typename Mma<T>::acc_t;
 
-  __shared__ T xs[2][KC][kNT];
-
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int lane = tid % 64;
   const int rt0 = (wave / 2) * RPW, ct0 = (wave % 2) * CPW;
   const int nc = a.nc, n = nc * P;
-  const int E = nc * nc * nc;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int cell = bid % E;
-  const int col0 = (bid / E) * kNT;
   const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
 
   auto gnode = [&](int l) -> int64_t {
@@ -283,6 +288,46 @@ cell_hx_kernel(const HxArgs<T> a) {
         atomic_add(Tg + gn[i] * a.ldt + col, v);
       }
     }
+  }
+}
+
+// Single problem: one workgroup per (cell, column tile), cells fastest.
+template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
+cell_hx_kernel(const HxArgs<T> a) {
+  __shared__ T xs[2][4 * KPC][kNT];
+  const int E = a.nc * a.nc * a.nc;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  cell_item<P, T, CPLX, WAVES, KPC>(a, bid % E, (bid / E) * kNT, xs);
+}
+
+// Many problems in one persistent launch: the work list is the concatenation
+// of every problem's (cell, column tile) items (item_off[q] = first item of
+// problem q, item_off[nprob] = total).  Each workgroup takes one contiguous
+// range of items, so a workgroup (and, through the XCD remap, an XCD) stays on
+// neighbouring cells of one problem.  Per-problem arguments, including the
+// recurrence scalars, are read from the device table `descs`, so a captured
+// graph stays valid when the host rewrites the table between replays.
+template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
+cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob,
+                       const int contiguous) {
+  __shared__ T xs[2][4 * KPC][kNT];
+  const int64_t nitems = item_off[nprob];
+  const int64_t G = gridDim.x;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t per = (nitems + G - 1) / G;
+  const int64_t i0 = contiguous ? w * per : w;
+  const int64_t i1 = contiguous ? ((w + 1) * per < nitems ? (w + 1) * per : nitems) : nitems;
+  const int64_t stride = contiguous ? 1 : G;
+  int q = 0;
+  for (int64_t it = i0; it < i1; it += stride) {
+    while (q + 1 < nprob && item_off[q + 1] <= it) ++q;
+    const HxArgs<T> d = descs[q];
+    const int64_t local = it - item_off[q];
+    const int E = d.nc * d.nc * d.nc;
+    __syncthreads();
+    cell_item<P, T, CPLX, WAVES, KPC>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, xs);
   }
 }
 
@@ -653,6 +698,84 @@ unsigned grid_for(int64_t total) {
 }
 
 }  // namespace
+
+template <typename T>
+HxArgs<T> pack_args(const HxLaunch& L) {
+  HxArgs<T> a;
+  a.A = static_cast<const T*>(L.A);
+  a.Ai = static_cast<const T*>(L.Ai);
+  a.vdiag = L.vdiag;
+  a.Xk = static_cast<const T*>(L.Xk);
+  a.Xp = static_cast<const T*>(L.Xp);
+  a.Tg = static_cast<T*>(L.T);
+  a.ldx = L.ldx;
+  a.ldp = L.ldp;
+  a.ldt = L.ldt;
+  a.ncols = L.ncols;
+  a.nc = L.nc;
+  a.zero_prev = L.zero_prev ? 1 : 0;
+  a.alpha = static_cast<T>(L.alpha);
+  a.c = static_cast<T>(L.c);
+  a.beta = static_cast<T>(L.beta);
+  a.pair_ptr = L.pair_ptr;
+  a.pair_atom = L.pair_atom;
+  a.pair_re = static_cast<const T*>(L.pair_re);
+  a.pair_im = static_cast<const T*>(L.pair_im);
+  a.hP = static_cast<const T*>(L.hP);
+  a.ldhp = L.ldhp;
+  return a;
+}
+
+template <int P, typename T, bool CPLX>
+hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
+  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
+  constexpr int WAVES = RT > 24 ? 8 : 4;
+  constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
+  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : 2;
+  if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
+                     static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);
+  return hipGetLastError();
+}
+
+template <typename T, bool CPLX>
+hipError_t launch_batched_t(const HxBatch& b, hipStream_t s) {
+  switch (b.p) {
+    case 2: return launch_batched_p<2, T, CPLX>(b, s);
+    case 3: return launch_batched_p<3, T, CPLX>(b, s);
+    case 4: return launch_batched_p<4, T, CPLX>(b, s);
+    case 5: return launch_batched_p<5, T, CPLX>(b, s);
+    case 6: return launch_batched_p<6, T, CPLX>(b, s);
+    case 7: return launch_batched_p<7, T, CPLX>(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+
+size_t hx_desc_bytes(int prec) {
+  return (prec == CHFSI_F64 || prec == CHFSI_C128) ? sizeof(HxArgs<double>) : sizeof(HxArgs<float>);
+}
+
+void pack_hx_desc(const HxLaunch& L, int prec, void* out) {
+  if (prec == CHFSI_F64 || prec == CHFSI_C128) {
+    HxArgs<double> a = pack_args<double>(L);
+    std::memcpy(out, &a, sizeof(a));
+  } else {
+    HxArgs<float> a = pack_args<float>(L);
+    std::memcpy(out, &a, sizeof(a));
+  }
+}
+
+hipError_t launch_cell_hx_batched(const HxBatch& b, int prec, hipStream_t s) {
+  if (b.p < kMinOrder || b.p > kMaxOrder) return hipErrorInvalidValue;
+  switch (prec) {
+    case CHFSI_F64: return launch_batched_t<double, false>(b, s);
+    case CHFSI_F32: return launch_batched_t<float, false>(b, s);
+    case CHFSI_C128: return launch_batched_t<double, true>(b, s);
+    case CHFSI_C64: return launch_batched_t<float, true>(b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_cell_hx(const HxLaunch& L, int prec, hipStream_t s) {
   if (L.p < kMinOrder || L.p > kMaxOrder) return hipErrorInvalidValue;

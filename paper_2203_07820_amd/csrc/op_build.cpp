@@ -263,6 +263,18 @@ std::string build_tables(const chfsi_system& sys, HostTables& t) {
         }
   }
 
+  t.atoms.assign(static_cast<size_t>(sys.natoms) * 8, 0.0);
+  for (int at = 0; at < sys.natoms; ++at) {
+    double* d = &t.atoms[static_cast<size_t>(at) * 8];
+    d[0] = sys.pos[3 * at];
+    d[1] = sys.pos[3 * at + 1];
+    d[2] = sys.pos[3 * at + 2];
+    d[3] = sys.Z[at];
+    d[4] = sys.s[at];
+    d[5] = (sys.has_proj && sys.h_s) ? sys.h_s[at] : 0.0;
+    d[6] = (sys.has_proj && sys.h_p) ? sys.h_p[at] : 0.0;
+  }
+
   // ---- projectors: c~_j = M_jj^(1/2) sum_images e^{-i k.(x_j - nL)} chi(x_j - R - nL)
   t.natoms = sys.natoms;
   t.has_proj = sys.has_proj != 0 && sys.natoms > 0;

@@ -1,0 +1,146 @@
+"""Batched path: many operators (uneven systems, k-points) in one persistent
+launch per Chebyshev step, optionally captured in a hipGraph.  Each batched
+result must equal the same problem solved alone (P14), and the batched
+filter must match the oracle's filter.  FP64: 1e-12 relative for one filter
+(only the order of the atomic assembly differs), 1e-10 Ha for Ritz values
+after several passes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import chfsi as ochfsi
+from oracle import fe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2203_07820_amd as lib  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _batch(k=(0.1, -0.2, 0.15)):
+    # uneven periodic systems of the same order p = 3 (two of them share a
+    # system at different k), complex Bloch operators
+    specs = [(2, 2, 11), (3, 3, 12), (4, 2, 13)]
+    out = []
+    for (nc, na, seed) in specs:
+        s = workloads.small_system(nc, 3, na, seed=seed, has_proj=True, k=k)
+        out.append(s)
+    out.append(out[0].with_k(np.array(k) * -0.5))
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("prec", ["c128", "f64"])
+def test_batched_filter_matches_individual_and_oracle(ctx, use_graph, prec):
+    k = (0.1, -0.2, 0.15) if prec == "c128" else (0.0, 0.0, 0.0)
+    systems = _batch(k)
+    ops = [lib.Operator(ctx, s) for s in systems]
+    cplx = ops[0].is_complex
+    ncols = [20, 37, 9, 33]
+    Xs, refs, params = [], [], []
+    for q, (s, op) in enumerate(zip(systems, ops)):
+        H = fe.assemble(fe.build_operator(s))
+        lam = np.linalg.eigvalsh(H.toarray())
+        a, b, aL = lam[ncols[q]], lam[-1] * 1.05, lam[0]
+        X = workloads.start_block(op.M, ncols[q], seed=50 + q, complex_=cplx)
+        refs.append(ochfsi.cheb_filter(lambda v: H @ v, X, 8, a, b, aL))
+        Xs.append(X)
+        params.append((a, b, aL))
+    P = lib.C128 if cplx else lib.F64
+    Xd = [dev(X) for X in Xs]
+    ctx.filter_batched(ops, Xd, 8, [p[0] for p in params], [p[1] for p in params], [p[2] for p in params], P,
+                       block=16, use_graph=use_graph)
+    for q in range(len(ops)):
+        got = host(Xd[q])
+        assert relerr(got, refs[q]) < 1e-11, q
+        # the same block filtered alone
+        Xi = dev(Xs[q])
+        ops[q].filter(Xi, 8, *params[q], prec=P, block=16)
+        assert relerr(got, host(Xi)) < 1e-12, q
+    if use_graph:
+        # replay the captured graph on fresh inputs with new intervals
+        Xd2 = [dev(X) for X in Xs]
+        ctx.filter_batched(ops, Xd2, 8, [p[0] * 1.01 for p in params], [p[1] for p in params],
+                           [p[2] for p in params], P, block=16, use_graph=True)
+        Xd3 = [dev(X) for X in Xs]
+        ctx.filter_batched(ops, Xd3, 8, [p[0] * 1.01 for p in params], [p[1] for p in params],
+                           [p[2] for p in params], P, block=16, use_graph=False)
+        for q in range(len(ops)):
+            assert relerr(host(Xd2[q]), host(Xd3[q])) < 1e-12
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_solve_batched_equals_individual_solves(ctx, use_graph):
+    systems = _batch()
+    ops = [lib.Operator(ctx, s) for s in systems]
+    nw = [12, 16, 10, 14]
+    X0 = [workloads.start_block(op.M, nw[q] + 4, seed=70 + q, complex_=True) for q, op in enumerate(ops)]
+    v0 = [workloads.lanczos_start(op.M, seed=80 + q, complex_=True) for q, op in enumerate(ops)]
+    Xb = [dev(X) for X in X0]
+    th, rs, st = ctx.solve_batched(ops, Xb, nw, m=10, block=8, filter_prec=lib.C128, n_buf=4, fixed_passes=4,
+                                   lanczos_v0=v0, use_graph=use_graph)
+    for q, op in enumerate(ops):
+        Xi = dev(X0[q])
+        thi, ri, sti = op.solve(Xi, nw[q], m=10, block=8, n_buf=4, fixed_passes=4, lanczos_v0=v0[q])
+        assert st[q]["passes"] == 4
+        assert np.max(np.abs(th[q] - thi)) < 1e-10
+        assert np.max(np.abs(rs[q] - ri)) < 1e-9
+        # and against the oracle iteration
+        H = fe.assemble(fe.build_operator(systems[q]))
+        ref = ochfsi.solve(lambda v: H @ v, X0[q], nw[q], m=10, block=8, v0=v0[q], passes=4)
+        assert np.max(np.abs(th[q][:nw[q]] - ref.theta)) < 1e-8
+
+
+def test_solve_batched_tolerance_retires_problems(ctx):
+    systems = _batch()[:3]
+    ops = [lib.Operator(ctx, s) for s in systems]
+    nw = [8, 8, 8]
+    X0 = [dev(workloads.start_block(op.M, 12, seed=90 + q, complex_=True)) for q, op in enumerate(ops)]
+    th, rs, st = ctx.solve_batched(ops, X0, nw, m=12, block=12, filter_prec=lib.C128, n_buf=4, tol=1e-8,
+                                   max_passes=40, use_graph=True)
+    for q in range(3):
+        assert np.max(rs[q][:8]) <= 1e-8
+        H = fe.assemble(fe.build_operator(systems[q]))
+        lam = np.linalg.eigvalsh(H.toarray())
+        assert np.max(np.abs(th[q][:8] - lam[:8])) < 1e-9
+
+
+def test_autotune_writes_cache_and_is_used(ctx, tmp_path):
+    path = str(tmp_path / "tune.json")
+    t = ctx.autotune(3, lib.C128, 16, cache_json=path)
+    assert 1 <= t["grid_per_cu"] <= 4 and t["contiguous"] in (0, 1) and t["ms"] > 0
+    data = json.loads(open(path).read())
+    assert any(e["key"] == "gfx950:p3:prec3:B16" for e in data)
+    c2 = lib.Context(0)
+    assert c2.get_tuning(3, lib.C128, 16)["ms"] == 0.0
+    c2.load_tuning(path)
+    t2 = c2.get_tuning(3, lib.C128, 16)
+    assert (t2["grid_per_cu"], t2["contiguous"]) == (t["grid_per_cu"], t["contiguous"])
+    assert abs(t2["ms"] - t["ms"]) <= 1e-4 * t["ms"]
+    c2.close()
