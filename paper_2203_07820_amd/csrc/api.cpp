@@ -712,10 +712,17 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   for (const BItem& it : items) key << ":" << it.op << "," << it.X << "," << it.ncols << "," << it.ld;
   if (key.str() != ctx->gkey || !ctx->gexec) {
     drop_graph(ctx);
-    HIP_TRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+    // Capture on the context's private stream (the caller's stream may be the
+    // legacy default stream, which cannot be captured); capturing records the
+    // sequence without running it, and the graph is launched on ctx->stream.
+    if (!ctx->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = ctx->stream;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    ctx->stream = ctx->cap_stream;
     const int rc = enqueue();
+    ctx->stream = user;
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (rc < 0) {
       if (g) (void)hipGraphDestroy(g);
       return rc;
@@ -804,6 +811,7 @@ int chfsi_ctx_destroy(chfsi_ctx* ctx) {
   }
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (int i = 0; i < WS_COUNT; ++i)
     if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);

@@ -45,6 +45,7 @@ struct chfsi_ctx {
   int ncu = 0;
   void* pinned = nullptr;           // host staging of descriptor tables
   size_t pinned_size = 0;
+  hipStream_t cap_stream = nullptr; // private stream that graphs are captured on
   hipGraph_t graph = nullptr;       // captured batched filter
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
