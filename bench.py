@@ -45,6 +45,25 @@ def pass_flops(M, E, mcell, npairs, N, m, cplx=False):
     return cell, nonlocal_, sub
 
 
+def profiled_traffic():
+    """HBM bytes per 128-column filter launch of the cell kernel, from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source (else None)."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "cell_hx_c1_fp64.md")
+    src = os.path.join(ROOT, "paper_2203_07820_amd", "csrc", "kernels_hx.hip")
+    try:
+        text = open(prof).read()
+        m = re.search(r"```json\s*(\{.*?\})\s*```", text, re.S)
+        rec = json.loads(m.group(1))
+        if rec["source_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(sys_, B, seed):
     """Oracle cell-wise H~.X of one B-column block at full size, timed."""
     import numpy as np
@@ -140,7 +159,8 @@ def main():
         "hx_kernel_ms_avg": kms / launches if launches else None,
         "hx_kernel_launches": launches,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None},
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
+                     "traffic": profiled_traffic(), "traffic_unit": "HBM bytes per 128-column launch"},
     }
     if not args.no_cpu_baseline:
         try:
