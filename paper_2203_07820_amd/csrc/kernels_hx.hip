@@ -31,6 +31,8 @@ namespace chfsi {
 namespace {
 
 constexpr int kNT = 64;     // columns per workgroup tile
+// B operands read directly from global memory (no LDS staging, no barriers)
+constexpr bool kDirect = true;
 constexpr int kKC = 16;     // cell rows (k values) per LDS chunk
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -102,7 +104,7 @@ template <int P, int KPC> struct CellShape {
 
 // One work item: cell `cell`, columns [col0, col0 + 64).  xs is the
 // workgroup's LDS staging buffer (2 x KC x 64).
-template <int P, typename T, bool CPLX, int WAVES, int KPC>
+template <int P, typename T, bool CPLX, int WAVES, int KPC, bool DIRECT>
 __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
                                           T (*xs)[4 * KPC][kNT]) {
   constexpr int Q = P + 1;
@@ -114,7 +116,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   constexpr int NCH = MP / KC;          // LDS chunks
   constexpr int RG = WAVES / 2;         // row groups
   constexpr int RPW = RT / RG;          // row tiles per wave
-  constexpr int CPW = 2;                // column tiles per wave
+  constexpr int CPW = kNT / 32;          // column tiles per wave (2 column groups)
   constexpr int GR = KC / WAVES;        // gathered rows per thread and chunk
   static_assert(MP % KC == 0 && RT % RG == 0 && KC % WAVES == 0, "tiling");
   using acc_t = typename Mma<T>::acc_t;
@@ -134,6 +136,79 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     return gx + static_cast<int64_t>(n) * (gy + static_cast<int64_t>(n) * gz);
   };
 
+  acc_t acc[RPW][CPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
+
+  if constexpr (DIRECT) {
+  // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
+  const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
+  const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
+  constexpr int RI = CPLX ? RPW : 1;
+  constexpr int CI = CPLX ? CPW : 1;
+  // k step kg: lanes 16 q .. 16 q + 15 hold cell row 4 kg + q, 16 consecutive
+  // columns of one node: one full cache line per 16 lanes, read straight into
+  // the B-operand registers (no LDS, no barrier).
+  const T* Xc = a.Xk + col0;
+  auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      av[r] = Aw[(static_cast<int64_t>(r) * KS + kg) * 64];
+      if constexpr (CPLX) avi[r] = Aiw[(static_cast<int64_t>(r) * KS + kg) * 64];
+    }
+  };
+  auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
+    const int l = kg * 4 + lane / 16;
+    const int64_t gn = l < MC ? gnode(l) : 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int cc = (ct0 + c) * 16 + lane % 16;
+      const bool ok = l < MC && col0 + cc < a.ncols;
+      bv[c] = ok ? Xc[gn * a.ldx + cc] : T(0);
+      if constexpr (CPLX) bo[c] = ok ? Xc[gn * a.ldx + (cc ^ 1)] : T(0);
+    }
+  };
+  auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bv)[CPW], const T (&bo)[CI]) {
+    T bs[CPW];
+    if constexpr (CPLX) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        acc[r][c] = Mma<T>::run(av[r], bv[c], acc[r][c]);
+        if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
+      }
+  };
+  // A one k step ahead, B (HBM latency) two k steps ahead; KS is even.
+  T a0[RPW], a1[RPW], ai0[RI], ai1[RI];
+  T b0[CPW], b1[CPW], b2[CPW], b3[CPW], o0[CI], o1[CI], o2[CI], o3[CI];
+  load_b(b0, o0, 0);
+  load_a(a0, ai0, 0);
+  load_b(b1, o1, 1);
+  for (int kg = 0; kg < KS; kg += 2) {
+    load_a(a1, ai1, kg + 1);
+    if (kg + 2 < KS) load_b(b2, o2, kg + 2);
+    compute(a0, ai0, b0, o0);
+    if (kg + 2 < KS) load_a(a0, ai0, kg + 2);
+    if (kg + 3 < KS) load_b(b3, o3, kg + 3);
+    compute(a1, ai1, b1, o1);
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      b0[c] = b2[c];
+      b1[c] = b3[c];
+      if constexpr (CPLX) {
+        o0[c] = o2[c];
+        o1[c] = o3[c];
+      }
+    }
+  }
+
+  } else {
   // gather: thread owns column `lane` of rows wave, wave + WAVES, ...
   const bool col_ok = (col0 + lane) < a.ncols;
   auto load_chunk = [&](T (&g)[GR], int ch) {
@@ -164,12 +239,6 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
         if constexpr (CPLX) dsti[s][r] = Aiw[(static_cast<int64_t>(r) * KS + ch * KPC + s) * 64];
       }
   };
-
-  acc_t acc[RPW][CPW];
-#pragma unroll
-  for (int r = 0; r < RPW; ++r)
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
 
   // One chunk: issue A of chunk ch+1 and the gather of chunk ch+2 (in that
   // order), multiply with A of chunk ch and the LDS copy of chunk ch, then
@@ -215,6 +284,8 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   for (int ch = 0; ch < NCH; ch += 2) {
     chunk_step(ch, a0, ai0, a1, ai1, g0, g1);
     if (ch + 1 < NCH) chunk_step(ch + 1, a1, ai1, a0, ai0, g1, g0);
+  }
+
   }
 
   // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell, one
@@ -298,7 +369,7 @@ cell_hx_kernel(const HxArgs<T> a) {
   __shared__ T xs[2][4 * KPC][kNT];
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, KPC>(a, bid % E, (bid / E) * kNT, xs);
+  cell_item<P, T, CPLX, WAVES, KPC, kDirect>(a, bid % E, (bid / E) * kNT, xs);
 }
 
 // Many problems in one persistent launch: the work list is the concatenation
@@ -327,7 +398,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
     __syncthreads();
-    cell_item<P, T, CPLX, WAVES, KPC>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, xs);
+    cell_item<P, T, CPLX, WAVES, KPC, kDirect>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, xs);
   }
 }
 
