@@ -114,7 +114,23 @@ typedef struct {
  *   lanczos_v0     optional host vector (M real or 2M interleaved complex
  *                  values) that starts Lanczos; NULL draws one from seed;
  *   seed           seed of the library's own generator (splitmix64 +
- *                  Box-Muller) when lanczos_v0 is NULL. */
+ *                  Box-Muller) when lanczos_v0 is NULL;
+ *   prec_switch    1: mixed-precision schedule.  After each pass the filter
+ *                  precision is raised one level (BF16 -> F32 -> F64,
+ *                  C64 -> C128) once r = max_{i<N} r_i has reached the
+ *                  level's rounding floor, r <= 16 u b (u = 2^-8 for BF16,
+ *                  2^-24 for F32 and C64; b the upper bound), or once r has
+ *                  grown in two passes in a row.  0: the precision stays;
+ *   hist_len       entries available in each non-NULL history array below;
+ *                  entry 0 describes the initial Rayleigh-Ritz, entry i the
+ *                  state after pass i; passes beyond hist_len - 1 are not
+ *                  recorded;
+ *   hist_time_ms   host, nullable: milliseconds from the start of the solve
+ *                  (bound included) to the end of that pass;
+ *   hist_max_resid host, nullable: max_{i<N} r_i after that pass;
+ *   hist_prec      host, nullable: filter precision of that pass (-1 for
+ *                  entry 0);
+ *   hist_theta     host, nullable: hist_len x (N + n_buf) Ritz values. */
 typedef struct {
   int32_t nwanted;
   int32_t n_buf;
@@ -128,6 +144,12 @@ typedef struct {
   double b_upper;
   const double* lanczos_v0;
   uint64_t seed;
+  int32_t prec_switch;
+  int32_t hist_len;
+  double* hist_time_ms;
+  double* hist_max_resid;
+  int32_t* hist_prec;
+  double* hist_theta;
 } chfsi_params;
 
 /* Timings (milliseconds, from HIP events on the context stream) and counts
@@ -144,6 +166,8 @@ typedef struct {
   double b_upper;           /* bound used                                 */
   double a_last, aL_last;   /* filter interval of the last pass           */
   double max_resid;         /* max_{i<N} r_i after the last pass          */
+  int32_t final_prec;       /* filter precision of the last pass          */
+  int32_t prec_changes;     /* passes after which the precision was raised */
 } chfsi_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -158,6 +182,10 @@ const char* chfsi_last_error(const chfsi_ctx* ctx);
 int chfsi_sync(chfsi_ctx* ctx);
 /* Library version string. */
 const char* chfsi_version(void);
+/* sizeof of chfsi_system, chfsi_params and chfsi_stats as this library was
+ * built, so that a binding can check its own struct layouts (any pointer may
+ * be NULL).  Needs no device. */
+int chfsi_abi_sizes(int64_t* system, int64_t* params, int64_t* stats);
 
 /* ---- operator build (Section 2.3; cell-level matrices of Section 4.2) ---
  * Builds on the host, in FP64: GLL nodes and weights, the (p+1)-point Gauss
@@ -234,6 +262,14 @@ int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double
 int chfsi_solve(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double* theta,
                 double* resid, chfsi_stats* stats);
 
+/* ---- mixed-precision schedule ----------------------------------------------
+ * The rule chfsi_solve() applies with params->prec_switch, for callers that
+ * drive the passes themselves (chfsi_pass): given the filter precision of the
+ * pass just done and max_resid[0..k] (k >= 1; entry 0 after the initial
+ * Rayleigh-Ritz, entry i after pass i), returns the precision of the next
+ * pass.  Host only; returns prec unchanged for k < 1 or a NULL history. */
+int32_t chfsi_next_prec(int32_t prec, const double* max_resid, int32_t k, double b_upper);
+
 /* ---- one ChFSI pass ---------------------------------------------------------
  * One pass of the loop of chfsi_solve() on the device block X (N + n_buf
  * columns, the current Ritz vectors): filter every column block of
@@ -270,9 +306,11 @@ int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* 
  * through chfsi_filter_batched() (with use_graph: one graph replay per pass),
  * then each problem's CholGS and Rayleigh-Ritz run in turn.  params, X, ld,
  * theta, resid, stats are arrays of n entries (resid, stats and their entries
- * nullable); m, block and filter_prec must be equal across params.  A problem
- * stops when its own criterion is met; the others continue.  Returns
- * CHFSI_NOTCONV if any tolerance was not met.  Synchronous. */
+ * nullable); m, block and filter_prec must be equal across params and
+ * prec_switch must be 0.  History arrays are filled per problem, with times
+ * measured from the start of the call.  A problem stops when its own
+ * criterion is met; the others continue.  Returns CHFSI_NOTCONV if any
+ * tolerance was not met.  Synchronous. */
 int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const chfsi_params* params,
                         void* const* X, const int64_t* ld, double* const* theta, double* const* resid,
                         chfsi_stats* stats, int32_t use_graph);

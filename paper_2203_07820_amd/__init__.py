@@ -55,6 +55,23 @@ def _ld_cols(t):
     return t.shape[1], t.stride(0)
 
 
+def _attach_history(p, ncols: int, fixed_passes: int, max_passes: int):
+    """Host arrays for the per-pass history of one solve, attached to Params p."""
+    n = (fixed_passes if fixed_passes > 0 else (max_passes if max_passes > 0 else 100)) + 1
+    h = {"time_ms": np.zeros(n), "max_resid": np.zeros(n), "prec": np.zeros(n, dtype=np.int32),
+         "theta": np.zeros((n, ncols))}
+    p.hist_len = n
+    p.hist_time_ms = _dptr(h["time_ms"])
+    p.hist_max_resid = _dptr(h["max_resid"])
+    p.hist_prec = h["prec"].ctypes.data_as(C.POINTER(C.c_int32))
+    p.hist_theta = _dptr(h["theta"])
+    return h
+
+
+def _trim_history(h, passes: int):
+    return {k: v[:passes + 1].copy() for k, v in h.items()}
+
+
 class Context:
     """A library context bound to one device and one HIP stream (torch's
     current stream by default)."""
@@ -103,8 +120,10 @@ class Context:
             I64(*[c[1] for c in cols]), int(m), D(*a), D(*b), D(*aL), int(prec), int(block), 1 if use_graph else 0))
 
     def solve_batched(self, ops, Xs, nwanted, m: int, block: int, filter_prec: int, n_buf=0, fixed_passes: int = 0,
-                      tol: float = 0.0, max_passes: int = 100, lanczos_v0=None, b_upper=None, use_graph: bool = True):
-        """chfsi_solve_batched; nwanted / n_buf / lanczos_v0 / b_upper may be per-problem lists."""
+                      tol: float = 0.0, max_passes: int = 100, lanczos_v0=None, b_upper=None, use_graph: bool = True,
+                      history: bool = False):
+        """chfsi_solve_batched; nwanted / n_buf / lanczos_v0 / b_upper may be per-problem lists.
+        With history=True each stats entry carries a per-pass "history" (see Operator.solve)."""
         n = len(ops)
 
         def per(x):
@@ -128,6 +147,8 @@ class Context:
         for q in range(n):
             if cols[q][0] != nw[q] + nb[q]:
                 raise ValueError("X must have nwanted + n_buf columns")
+        hists = [_attach_history(P[q], cols[q][0], fixed_passes, max_passes) if history else None
+                 for q in range(n)]
         th = [np.zeros(cols[q][0]) for q in range(n)]
         rs = [np.zeros(cols[q][0]) for q in range(n)]
         PD = C.POINTER(C.c_double) * n
@@ -138,6 +159,9 @@ class Context:
                                           PD(*[_dptr(r) for r in rs]), st, 1 if use_graph else 0)
         self.check(rc, allow=(0, 1))
         stats = [{f: getattr(st[q], f) for f, _ in _lib.Stats._fields_} for q in range(n)]
+        for q in range(n):
+            if hists[q] is not None:
+                stats[q]["history"] = _trim_history(hists[q], stats[q]["passes"])
         return th, rs, stats
 
     def autotune(self, p: int, prec: int, block: int, cache_json: Optional[str] = None):
@@ -271,7 +295,10 @@ class Operator:
 
     def solve(self, X, nwanted: int, m: int, block: int, n_buf: int = 0, fixed_passes: int = 0,
               tol: float = 0.0, max_passes: int = 100, filter_prec: Optional[int] = None,
-              lanczos_steps: int = 20, b_upper: float = 0.0, lanczos_v0=None, seed: int = 0):
+              lanczos_steps: int = 20, b_upper: float = 0.0, lanczos_v0=None, seed: int = 0,
+              prec_switch: bool = False, history: bool = False):
+        """chfsi_solve.  With history=True, stats["history"] holds per-pass
+        time_ms, max_resid, prec and theta (row 0: the initial Rayleigh-Ritz)."""
         if filter_prec is None:
             filter_prec = C128 if self.is_complex else F64
         ncols, ld = _ld_cols(X)
@@ -289,6 +316,8 @@ class Operator:
             v0 = np.ascontiguousarray(v0, dtype=np.float64)
             p.lanczos_v0 = _dptr(v0)
         p.seed = seed
+        p.prec_switch = 1 if prec_switch else 0
+        hist = _attach_history(p, ncols, fixed_passes, max_passes) if history else None
         th = np.zeros(ncols)
         r = np.zeros(ncols)
         st = _lib.Stats()
@@ -296,6 +325,8 @@ class Operator:
         self.ctx.check(rc, allow=(0, 1))
         stats = {f: getattr(st, f) for f, _ in _lib.Stats._fields_}
         stats["converged"] = rc == 0
+        if hist is not None:
+            stats["history"] = _trim_history(hist, stats["passes"])
         return th, r, stats
 
     def one_pass(self, X, nwanted: int, m: int, block: int, a: float, b: float, aL: float, n_buf: int = 0,
@@ -383,6 +414,13 @@ class Network:
             self.close()
         except Exception:
             pass
+
+
+def next_prec(prec: int, max_resid_history, b_upper: float) -> int:
+    """chfsi_next_prec: filter precision for the next pass of a caller-driven
+    solve, given max residuals after the initial Rayleigh-Ritz and each pass."""
+    h = np.ascontiguousarray(max_resid_history, dtype=np.float64)
+    return int(_lib.load().chfsi_next_prec(int(prec), _dptr(h), int(h.size - 1), float(b_upper)))
 
 
 def features(op: Operator, F) -> None:

@@ -13,14 +13,14 @@ F64, F32, BF16, C128, C64 = 0, 1, 2, 3, 4
 
 # every symbol include/chfsi.h declares
 EXPORTS = [
-    "chfsi_ctx_create", "chfsi_ctx_destroy", "chfsi_last_error", "chfsi_sync", "chfsi_version",
+    "chfsi_ctx_create", "chfsi_ctx_destroy", "chfsi_last_error", "chfsi_sync", "chfsi_version", "chfsi_abi_sizes",
     "chfsi_op_build", "chfsi_op_destroy", "chfsi_op_info", "chfsi_op_tables",
     "chfsi_apply", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_kernel_time",
     "chfsi_filter_batched", "chfsi_solve_batched", "chfsi_autotune", "chfsi_load_tuning", "chfsi_get_tuning",
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
-    "chfsi_initial_block",
+    "chfsi_initial_block", "chfsi_next_prec",
 ]
 
 
@@ -40,6 +40,9 @@ class Params(C.Structure):
         ("fixed_passes", C.c_int32), ("max_passes", C.c_int32), ("tol", C.c_double),
         ("filter_prec", C.c_int32), ("lanczos_steps", C.c_int32), ("b_upper", C.c_double),
         ("lanczos_v0", C.POINTER(C.c_double)), ("seed", C.c_uint64),
+        ("prec_switch", C.c_int32), ("hist_len", C.c_int32),
+        ("hist_time_ms", C.POINTER(C.c_double)), ("hist_max_resid", C.POINTER(C.c_double)),
+        ("hist_prec", C.POINTER(C.c_int32)), ("hist_theta", C.POINTER(C.c_double)),
     ]
 
 
@@ -49,6 +52,7 @@ class Stats(C.Structure):
         ("t_rr", C.c_double), ("t_total", C.c_double), ("passes", C.c_int32),
         ("hx_columns", C.c_int64), ("hx_flops", C.c_double), ("b_upper", C.c_double),
         ("a_last", C.c_double), ("aL_last", C.c_double), ("max_resid", C.c_double),
+        ("final_prec", C.c_int32), ("prec_changes", C.c_int32),
     ]
 
 
@@ -72,6 +76,7 @@ def load() -> C.CDLL:
         "chfsi_last_error": (C.c_char_p, [vp]),
         "chfsi_sync": (C.c_int, [vp]),
         "chfsi_version": (C.c_char_p, []),
+        "chfsi_abi_sizes": (C.c_int, [C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "chfsi_op_build": (C.c_int, [vp, C.POINTER(System), C.POINTER(vp)]),
         "chfsi_op_destroy": (C.c_int, [vp]),
         "chfsi_op_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
@@ -103,6 +108,7 @@ def load() -> C.CDLL:
         "chfsi_mlp_loss_grad": (C.c_int, [vp, vp, i64, vp, i32, pd, C.POINTER(C.c_float)]),
         "chfsi_mlp_train_step": (C.c_int, [vp, vp, i64, vp, i32, C.c_float, pd]),
         "chfsi_initial_block": (C.c_int, [vp, vp, u64, vp, i64, i64, C.POINTER(i32)]),
+        "chfsi_next_prec": (i32, [i32, pd, i32, dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -773,12 +773,50 @@ int save_tuning_file(chfsi_ctx* ctx, const std::string& path) {
 
 }  // namespace
 
+namespace {
+
+// Mixed-precision schedule: the next filter precision after a pass whose
+// residual history is r[0..k] (k >= 1), or prec itself.
+int next_prec(int prec, const double* r, int k, double b) {
+  int up = prec;
+  double u = 0.0;
+  if (prec == CHFSI_BF16) { up = CHFSI_F32; u = std::ldexp(1.0, -8); }
+  else if (prec == CHFSI_F32) { up = CHFSI_F64; u = std::ldexp(1.0, -24); }
+  else if (prec == CHFSI_C64) { up = CHFSI_C128; u = std::ldexp(1.0, -24); }
+  else return prec;
+  const bool floor_reached = r[k] <= 16.0 * u * b;
+  const bool growing = k >= 2 && r[k] > r[k - 1] && r[k - 1] > r[k - 2];
+  return (floor_reached || growing) ? up : prec;
+}
+
+void record_hist(const chfsi_params& p, int i, double t_ms, double maxr, int prec, const double* th, int64_t N) {
+  if (i < 0 || i >= p.hist_len) return;
+  if (p.hist_time_ms) p.hist_time_ms[i] = t_ms;
+  if (p.hist_max_resid) p.hist_max_resid[i] = maxr;
+  if (p.hist_prec) p.hist_prec[i] = prec;
+  if (p.hist_theta) std::memcpy(p.hist_theta + static_cast<int64_t>(i) * N, th, N * 8);
+}
+
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
 extern "C" {
 
 const char* chfsi_version(void) { return "chfsi 0.1 (gfx950)"; }
+
+int32_t chfsi_next_prec(int32_t prec, const double* max_resid, int32_t k, double b_upper) {
+  if (!max_resid || k < 1) return prec;
+  return next_prec(prec, max_resid, k, b_upper);
+}
+
+int chfsi_abi_sizes(int64_t* system, int64_t* params, int64_t* stats) {
+  if (system) *system = static_cast<int64_t>(sizeof(chfsi_system));
+  if (params) *params = static_cast<int64_t>(sizeof(chfsi_params));
+  if (stats) *stats = static_cast<int64_t>(sizeof(chfsi_stats));
+  return CHFSI_OK;
+}
 
 int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
   if (!out) return fail(nullptr, CHFSI_EINVAL, "null output pointer");
@@ -1090,6 +1128,7 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
   if (prm->m < 1) return fail(ctx, CHFSI_EINVAL, "degree m must be >= 1");
   if (!prec_valid_for(op, prm->filter_prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
   if (prm->fixed_passes <= 0 && !(prm->tol > 0.0)) return fail(ctx, CHFSI_EINVAL, "need fixed_passes or tol");
+  if (prm->hist_len < 0) return fail(ctx, CHFSI_EINVAL, "hist_len must be >= 0");
   const int cf = t.cplx ? 2 : 1;
   hipEvent_t ev[8];
   for (auto& e : ev) HIP_TRY(ctx, hipEventCreate(&e));
@@ -1099,6 +1138,7 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
   } guard{ev};
   chfsi_stats st;
   std::memset(&st, 0, sizeof(st));
+  st.final_prec = prm->filter_prec;
   HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
   double b = prm->b_upper;
   if (!(b > 0.0)) {
@@ -1123,8 +1163,15 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
     for (int i = 0; i < prm->nwanted; ++i) m = std::max(m, r[i]);
     return m;
   };
+  std::vector<double> rhist{max_r()};
+  if (prm->hist_len > 0) {
+    HIP_TRY(ctx, hipEventRecord(ev[5], ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(ev[5]));
+    record_hist(*prm, 0, event_ms(ev[0], ev[5]), rhist[0], -1, th.data(), N);
+  }
   const int limit = prm->fixed_passes > 0 ? prm->fixed_passes : (prm->max_passes > 0 ? prm->max_passes : 100);
   int passes = 0;
+  int fprec = prm->filter_prec;
   double a = th[N - 1], aL = th[0];
   while (passes < limit) {
     if (prm->fixed_passes <= 0 && max_r() <= prm->tol) break;
@@ -1132,7 +1179,7 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
     aL = th[0];
     if (!(aL < a && a < b)) return fail(ctx, CHFSI_EDIVERGE, "filter interval collapsed (b below the Ritz values?)");
     HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
-    CHECK(do_filter(op, X, N, ld, prm->m, a, b, aL, prm->filter_prec, prm->block));
+    CHECK(do_filter(op, X, N, ld, prm->m, a, b, aL, fprec, prm->block));
     HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
     CHECK(cholgs(op, X, ld, X2, N, N, nullptr));
     HIP_TRY(ctx, hipEventRecord(ev[4], ctx->stream));
@@ -1147,6 +1194,14 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
     for (int64_t i = 0; i < N; ++i)
       if (!std::isfinite(th[i]) || !std::isfinite(r[i]))
         return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
+    rhist.push_back(max_r());
+    record_hist(*prm, passes, event_ms(ev[0], ev[5]), rhist.back(), fprec, th.data(), N);
+    st.final_prec = fprec;
+    if (prm->prec_switch) {
+      const int np = next_prec(fprec, rhist.data(), static_cast<int>(rhist.size()) - 1, b);
+      if (np != fprec) ++st.prec_changes;
+      fprec = np;
+    }
   }
   HIP_TRY(ctx, hipEventRecord(ev[6], ctx->stream));
   HIP_TRY(ctx, hipEventSynchronize(ev[6]));
@@ -1200,19 +1255,31 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
       return fail(ctx, CHFSI_EINVAL, "m, block and filter_prec must be equal across the batch");
     if (pr.nwanted < 1 || pr.n_buf < 0 || pr.m < 1) return fail(ctx, CHFSI_EINVAL, "bad parameters");
     if (pr.fixed_passes <= 0 && !(pr.tol > 0.0)) return fail(ctx, CHFSI_EINVAL, "need fixed_passes or tol");
+    if (pr.prec_switch) return fail(ctx, CHFSI_EINVAL, "prec_switch is not available in the batched solve");
+    if (pr.hist_len < 0) return fail(ctx, CHFSI_EINVAL, "hist_len must be >= 0");
     N[q] = static_cast<int64_t>(pr.nwanted) + pr.n_buf;
     CHECK(check_block(ops[q], Xv[q], N[q], ld[q]));
     if (!prec_valid_for(ops[q], prec)) return fail(ctx, CHFSI_EINVAL, "filter precision does not match");
   }
-  hipEvent_t e0, e1;
+  hipEvent_t e0, e1, es;
   HIP_TRY(ctx, hipEventCreate(&e0));
   HIP_TRY(ctx, hipEventCreate(&e1));
-  struct G2 { hipEvent_t a, b; ~G2() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } guard{e0, e1};
+  HIP_TRY(ctx, hipEventCreate(&es));
+  struct G3 {
+    hipEvent_t a, b, c;
+    ~G3() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); (void)hipEventDestroy(c); }
+  } guard{e0, e1, es};
+  HIP_TRY(ctx, hipEventRecord(es, ctx->stream));
   std::vector<double> bq(n), aq(n), aLq(n);
   std::vector<std::vector<double>> th(n), r(n);
   std::vector<int> passes(n, 0);
   std::vector<char> done(n, 0);
   std::vector<double> tfilt(n, 0.0), tcg(n, 0.0), trr(n, 0.0);
+  auto maxr_of = [&](int q) {
+    double mr = 0.0;
+    for (int i = 0; i < params[q].nwanted; ++i) mr = std::max(mr, r[q][i]);
+    return mr;
+  };
   for (int q = 0; q < n; ++q) {
     chfsi_op* op = ops[q];
     const chfsi_params& pr = params[q];
@@ -1230,6 +1297,11 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
     CHECK(cholgs(op, static_cast<double*>(Xv[q]), ld[q], static_cast<double*>(X2v), N[q], N[q], nullptr));
     CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N[q], static_cast<double*>(Xv[q]), ld[q], N[q],
                         th[q].data(), r[q].data()));
+    if (pr.hist_len > 0) {
+      HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+      HIP_TRY(ctx, hipEventSynchronize(e1));
+      record_hist(pr, 0, event_ms(es, e1), maxr_of(q), -1, th[q].data(), N[q]);
+    }
   }
   auto converged = [&](int q) {
     const chfsi_params& pr = params[q];
@@ -1274,6 +1346,7 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
       for (int64_t i = 0; i < N[q]; ++i)
         if (!std::isfinite(th[q][i]) || !std::isfinite(r[q][i]))
           return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values");
+      record_hist(params[q], passes[q], event_ms(es, e1), maxr_of(q), prec, th[q].data(), N[q]);
     }
   }
   drop_graph(ctx);
@@ -1281,12 +1354,12 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
   for (int q = 0; q < n; ++q) {
     std::memcpy(theta[q], th[q].data(), N[q] * 8);
     if (resid && resid[q]) std::memcpy(resid[q], r[q].data(), N[q] * 8);
-    double mr = 0.0;
-    for (int i = 0; i < params[q].nwanted; ++i) mr = std::max(mr, r[q][i]);
+    const double mr = maxr_of(q);
     if (stats) {
       chfsi_stats& st = stats[q];
       std::memset(&st, 0, sizeof(st));
       st.passes = passes[q];
+      st.final_prec = prec;
       st.t_filter = tfilt[q];
       st.t_rr = trr[q];
       st.b_upper = bq[q];

@@ -433,13 +433,12 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
   constexpr int WAVES = RT > 24 ? 8 : 4;
-  // k steps per LDS chunk, sized so that the A fragments of two chunks (one
-  // being used, one in flight) fit in registers next to the accumulators with
-  // two waves per SIMD (two workgroups per CU: one's gather and epilogue
-  // overlap the other's MFMAs).  Complex FP64 needs twice the A registers and
-  // runs one wave per SIMD.
+  // Waves per SIMD: two for real FP64 and complex FP32 (one workgroup's
+  // epilogue overlaps the other's MFMAs), three for real FP32 (140 VGPRs at
+  // p = 6), one for complex FP64, whose A and B fragments double the
+  // register count.  KPC sizes the LDS chunk of the staged-gather variant.
   constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
-  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : 2;
+  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
   hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
@@ -802,7 +801,7 @@ hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
   constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
   constexpr int WAVES = RT > 24 ? 8 : 4;
   constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
-  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : 2;
+  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
   if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
                      static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);

@@ -37,3 +37,13 @@ def test_binding_declares_every_symbol():
     assert sorted(_lib.EXPORTS) == declared()
     lib = _lib.load()
     assert lib.chfsi_version().decode().startswith("chfsi")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_struct_layouts_match_the_library():
+    from paper_2203_07820_amd import _lib
+    lib = _lib.load()
+    sizes = [ctypes.c_int64() for _ in range(3)]
+    assert lib.chfsi_abi_sizes(*[ctypes.byref(x) for x in sizes]) == 0
+    assert [x.value for x in sizes] == [ctypes.sizeof(_lib.System), ctypes.sizeof(_lib.Params),
+                                        ctypes.sizeof(_lib.Stats)]
