@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--out", default=None, help="write per-pass histories (npz) here")
     ap.add_argument("--max-passes", type=int, default=0, help="c2: pass cap per run (0: default)")
     ap.add_argument("--c2-runs", default="f32,mixed,bf16", help="c2: runs beside the FP64 reference")
+    ap.add_argument("--c4-train", type=int, default=200, help="c4: training configurations solved")
+    ap.add_argument("--c4-test", type=int, default=40, help="c4: held-out configurations")
+    ap.add_argument("--c4-epochs", type=int, default=40, help="c4: passes over the training set")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -102,6 +105,10 @@ def main():
         sys.exit(2)
     if args.workload == "c2":
         return run_c2(args)
+    if args.workload == "c3":
+        return run_c3(args)
+    if args.workload == "c4":
+        return run_c4(args)
     return run_c1(args)
 
 
@@ -242,23 +249,24 @@ def run_c2(args):
     # refine the reference with higher-degree FP64 passes (not part of any timing)
     th_ref = ref["theta"][-1].copy()
     r_ref = ref["maxr"][-1]
-    for k in range(6):
+    for k in range(10):
         if r_ref <= ref_tol:
             break
-        th_ref, rr = op.one_pass(Xref, N, 2 * m, B, th_ref[-1], b, th_ref[0], n_buf=nb)
+        th_ref, rr = op.one_pass(Xref, N, 3 * m, B, th_ref[-1], b, th_ref[0], n_buf=nb)
         r_ref = float(np.max(rr[:N]))
-        log(f"# reference refinement {k + 1} (degree {2 * m}): max r={r_ref:.3e}")
+        log(f"# reference refinement {k + 1} (degree {3 * m}): max r={r_ref:.3e}")
     lam = th_ref[:N].copy()
     gaps = np.diff(th_ref)[:N]
-    kpre = int(np.nonzero(gaps[:N - 1] > 1e-6)[0].max()) + 1   # gap-separated prefix [0, kpre)
+    # gap-separated prefixes [0, k): the largest k <= N whose gap to state k exceeds the threshold
+    prefixes = {g: int(np.nonzero(gaps[:N - 1] > g)[0].max()) + 1 for g in (1e-6, 1e-4, 1e-3)}
 
     def dE(th):
         return float(np.max(np.abs(th[:N] - lam)))
 
-    def sin_angle(X):
-        C = Xref[:, :kpre].T @ X[:, :kpre]
-        R = X[:, :kpre].clone()
-        R.addmm_(Xref[:, :kpre], C, alpha=-1.0)
+    def sin_angle(X, k):
+        C = Xref[:, :k].T @ X[:, :k]
+        R = X[:, :k].clone()
+        R.addmm_(Xref[:, :k], C, alpha=-1.0)
         G = (R.T @ R).cpu().numpy()
         del R
         return float(np.sqrt(max(np.linalg.eigvalsh(G)[-1], 0.0)))
@@ -271,11 +279,13 @@ def run_c2(args):
                "final_dE": float(de[-1]), "min_dE": float(de.min()), "final_max_resid": float(rec["maxr"][-1]),
                "passes": int(len(rec["t"]) - 1), "sec_per_pass": float(np.median(np.diff(rec["t"]))),
                "hx_tflops": rec["hx_tflops"], "prec_per_pass": [int(p) for p in rec["prec"][1:]],
-               "sin_subspace": sin_angle(X)}
+               "sin_subspace": {f"gap>{g:g} (k={k})": sin_angle(X, k) for g, k in prefixes.items()}}
         rec["dE"] = de
         return out
 
     results = {"f64": summarize(ref, Xref)}
+    k64 = results["f64"]["passes_to_target"]
+    results["f64"]["max_resid_at_target"] = float(ref["maxr"][k64]) if k64 is not None else None
     hists = {"f64": ref}
     stop_target = lambda th, r: dE(th) <= target  # noqa: E731
     wanted = set(args.c2_runs.split(",")) if args.c2_runs else set()
@@ -300,7 +310,7 @@ def run_c2(args):
                                "+ 128 buffer columns, B=128, m=30, start N(0,1) seeded",
                    "N": N, "n_buf": nb, "block": B, "degree": m, "b_upper": b,
                    "reference": f"FP64 run (the f64 run, then up to 6 degree-{2 * m} passes) to max r <= {ref_tol:g}",
-                   "reference_max_resid": r_ref, "gap_prefix": kpre},
+                   "reference_max_resid": r_ref, "gap_prefixes": {f"{g:g}": k for g, k in prefixes.items()}},
         "speedup_vs_f64": {"f32": (t64 / t32) if (t64 and t32) else None,
                            "mixed": (t64 / tmix) if (t64 and tmix) else None},
         "runs": results,
@@ -313,6 +323,225 @@ def run_c2(args):
     if args.out:
         np.savez_compressed(args.out, **{f"{n}_{k}": v for n, h in hists.items() for k, v in h.items()
                                          if isinstance(v, np.ndarray)})
+    print(json.dumps(out), flush=True)
+
+
+def run_c3(args):
+    """Batched uneven k-point solves: 8 periodic p = 5 systems x 4 Monkhorst-Pack
+    k-points (32 complex Bloch operators).  Per pass: each problem solved on
+    its own (complex128) against one batched solve (persistent launch per
+    Chebyshev step, without and with the hipGraph) in complex128 and complex64,
+    tile shapes from the autotuner."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import paper_2203_07820_amd as lib
+    import workloads
+
+    m, B, K = 30, 128, max(1, args.steps)
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+    systems, Ns, tags = [], [], []
+    for i, (nc, na, nw) in enumerate(workloads.C3_SYSTEMS):
+        base = workloads.config("c3", i)
+        for j, kp in enumerate(workloads.kpoints_mp4(base.L)):
+            systems.append(base.with_k(kp))
+            Ns.append(nw)
+            tags.append((i, j))
+    t0 = time.perf_counter()
+    ops = [lib.Operator(ctx, s) for s in systems]
+    log(f"# c3: {len(ops)} operators built in {time.perf_counter() - t0:.1f}s; sum M={sum(o.M for o in ops)}")
+    bs = [ops[q].bounds(20, seed=3000 + tags[q][0] + 2_000_000 + 10 * tags[q][1])[0] for q in range(len(ops))]
+    cell = nl = sub = 0.0
+    for q, o in enumerate(ops):
+        c_, n_, s_ = pass_flops(o.M, o.E, o.mcell, o.npairs, Ns[q], m, cplx=True)
+        cell, nl, sub = cell + c_, nl + n_, sub + s_
+    total = cell + nl + sub
+
+    def fill():
+        Xs = []
+        for q, o in enumerate(ops):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(3000 + tags[q][0] + 1_000_000 + 10 * tags[q][1])
+            Xs.append(torch.randn(o.M, Ns[q], dtype=torch.complex128, device="cuda", generator=g))
+        torch.cuda.synchronize()
+        return Xs
+
+    def per_pass_ms(h):
+        return float(np.median(np.diff(h["time_ms"])))
+
+    tune_path = os.path.join(tempfile.gettempdir(), "chfsi_tuning_c3.json")
+    tuning = {}
+    for name, prec in (("c128", lib.C128), ("c64", lib.C64)):
+        t1 = time.perf_counter()
+        tuning[name] = ctx.autotune(5, prec, B, cache_json=tune_path)
+        log(f"# autotune {name}: {tuning[name]} ({time.perf_counter() - t1:.1f}s)")
+
+    modes = {}
+    # each problem on its own, complex128
+    Xs = fill()
+    seq_ms, seq_filter_ms, seq_theta = 0.0, 0.0, []
+    for q, o in enumerate(ops):
+        th, r, st = o.solve(Xs[q], Ns[q], m, B, fixed_passes=K, filter_prec=lib.C128, b_upper=bs[q], history=True)
+        seq_ms += per_pass_ms(st["history"])
+        seq_filter_ms += st["t_filter"] / K
+        seq_theta.append(th)
+        if q % 4 == 3:
+            log(f"# sequential: system {tags[q][0]} done, running pass time {seq_ms:.0f} ms")
+    modes["sequential_c128"] = {"pass_ms": seq_ms, "filter_ms_per_pass": seq_filter_ms,
+                                "tflops": total / (seq_ms * 1e-3) / 1e12}
+    del Xs
+    thetas = {}
+    for name, prec, graph in (("batched_c128", lib.C128, False), ("batched_graph_c128", lib.C128, True),
+                              ("batched_graph_c64", lib.C64, True)):
+        Xs = fill()
+        t1 = time.perf_counter()
+        th, rs, st = ctx.solve_batched(ops, Xs, Ns, m, B, prec, fixed_passes=K, b_upper=bs, use_graph=graph,
+                                       history=True)
+        big = int(np.argmax([o.M * Ns[q] for q, o in enumerate(ops)]))
+        pm = per_pass_ms(st[big]["history"])
+        modes[name] = {"pass_ms": pm, "filter_ms_per_pass": st[big]["t_filter"] / K,
+                       "tflops": total / (pm * 1e-3) / 1e12,
+                       "max_resid": float(max(np.max(rs[q][:Ns[q]]) for q in range(len(ops))))}
+        thetas[name] = th
+        log(f"# {name}: {pm:.0f} ms per pass ({time.perf_counter() - t1:.1f}s)")
+        del Xs
+    d_seq = max(float(np.max(np.abs(thetas["batched_graph_c128"][q] - seq_theta[q]))) for q in range(len(ops)))
+    d_c64 = max(float(np.max(np.abs(thetas["batched_graph_c64"][q][:Ns[q]] - thetas["batched_graph_c128"][q][:Ns[q]])))
+                for q in range(len(ops)))
+    pm = modes["batched_graph_c128"]["pass_ms"]
+    out = {
+        "metric": "batched k-point ChFSI pass (c3): algorithmic GFLOP/s of one pass over 32 problems",
+        "value": total / (pm * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": K, "warmup": 0,
+        "ms_per_step": pm, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128", "data": "synthetic",
+        "config": {"workload": "c3: 8 periodic p=5 systems (8^3..20^3 cells, 8..48 atoms with projectors, "
+                               "N=64..384) x 4 Monkhorst-Pack k-points, m=30, B=min(N,128)",
+                   "problems": len(ops), "sum_M": int(sum(o.M for o in ops)), "degree": m, "block": B,
+                   "pass_flops": total},
+        "modes": modes,
+        "speedup_batched_graph_vs_sequential": modes["sequential_c128"]["pass_ms"] / pm,
+        "speedup_c64_vs_c128": pm / modes["batched_graph_c64"]["pass_ms"],
+        "max_dtheta_batched_vs_sequential": d_seq,
+        "max_dtheta_c64_vs_c128_after_same_passes": d_c64,
+        "tuning": tuning,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c4(args):
+    """Learned warm start: seeded 16-atom configurations in a 12^3-cell p = 5
+    box solved by plain FP64 ChFSI from random starts to max r <= 1e-6; the
+    network (32 -> 128 -> 128 -> 128, tanh, FP32) is trained on their Ritz
+    blocks by the library's own kernels, then held-out configurations are
+    solved from the network's block and from a random block."""
+    import numpy as np
+    import torch
+
+    import paper_2203_07820_amd as lib
+    import workloads
+
+    N, nb, B, m, tol = 128, 32, 128, 30, 1e-6
+    n_train, n_test, epochs = args.c4_train, args.c4_test, args.c4_epochs
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+
+    def random_block(op, j):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(4000 + j + 1_000_000)
+        return torch.randn(op.M, N + nb, dtype=torch.float64, device="cuda", generator=g)
+
+    def solve(op, X, j):
+        return op.solve(X, N, m, B, n_buf=nb, tol=tol, max_passes=80, seed=4000 + j + 2_000_000)
+
+    def featurize(op):
+        F = torch.empty(op.M, 32, dtype=torch.float32, device="cuda")
+        lib.features(op, F)
+        return F
+
+    # 1. training data: converged Ritz blocks of the training configurations
+    t0 = time.perf_counter()
+    feats, targets, gen_passes = [], [], []
+    for j in range(n_train):
+        op = lib.Operator(ctx, workloads.config("c4", j))
+        X = random_block(op, j)
+        th, r, st = solve(op, X, j)
+        feats.append(featurize(op))
+        targets.append(X[:, :N].float().contiguous())
+        gen_passes.append(st["passes"])
+        del X
+        op.close()
+        if j % 10 == 9:
+            log(f"# c4 data: {j + 1}/{n_train} solved, mean passes {np.mean(gen_passes):.1f}, "
+                f"{time.perf_counter() - t0:.0f}s")
+    t_gen = time.perf_counter() - t0
+    # 2. standardisation from a host subsample of the training features
+    sample = np.concatenate([F[::64].cpu().numpy().astype(np.float64) for F in feats])
+    mean, scale = sample.mean(axis=0), sample.std(axis=0) + 1e-6
+    net = lib.Network(ctx, 32, 128, N, seed=4242)
+    net.set_norm(mean, scale)
+    # 3. training (Adam, one configuration per step)
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(7)
+    curve = []
+    for ep in range(epochs):
+        losses = [net.train_step(feats[j], targets[j], lr=1e-3) for j in rng.permutation(n_train)]
+        curve.append(float(np.mean(losses)))
+        if ep % 5 == 4 or ep == epochs - 1:
+            log(f"# c4 training epoch {ep + 1}: mean loss {curve[-1]:.4f} ({time.perf_counter() - t0:.0f}s)")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del feats, targets
+    # 4. held-out configurations: random start vs learned start
+    rows = []
+    for i in range(n_test):
+        j = 1800 + i
+        op = lib.Operator(ctx, workloads.config("c4", j))
+        X = random_block(op, j)
+        _, _, st_r = solve(op, X, j)
+        Q = X[:, :N].float().contiguous()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        F = featurize(op)
+        Xl = torch.empty(op.M, N + nb, dtype=torch.float64, device="cuda")
+        fallback = lib.initial_block(op, Xl, net, seed=4000 + j + 1_000_000)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t1
+        _, _, st_l = solve(op, Xl, j)
+        loss, _ = net.loss_grad(F, Q, want_grads=False)
+        rows.append({"passes_random": st_r["passes"], "passes_learned": st_l["passes"],
+                     "ms_random": st_r["t_total"], "ms_learned": st_l["t_total"] + 1e3 * t_init,
+                     "converged": bool(st_r["converged"] and st_l["converged"]), "fallback": fallback,
+                     "heldout_loss": loss})
+        del X, Xl, F, Q
+        op.close()
+        log(f"# c4 held-out {i + 1}/{n_test}: passes random {st_r['passes']} learned {st_l['passes']}"
+            f"{' (fallback)' if fallback else ''}")
+    pr = np.array([r_["passes_random"] for r_ in rows], dtype=float)
+    pl = np.array([r_["passes_learned"] for r_ in rows], dtype=float)
+    tr = np.array([r_["ms_random"] for r_ in rows])
+    tl = np.array([r_["ms_learned"] for r_ in rows])
+    out = {
+        "metric": "filter passes saved by the learned warm start at max r <= 1e-6 (c4)",
+        "value": float(np.mean(pr - pl)), "unit": "passes", "n_gpus": 1, "steps": n_test, "warmup": 0,
+        "ms_per_step": float(np.mean(tl)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 solve, f32 network", "data": "synthetic",
+        "config": {"workload": "c4: 16 Gaussian atoms with projectors in a 12^3-cell p=5 box (L=24, M=216000), "
+                               f"N=128 + {nb} buffer, B=128, m=30, tol 1e-6; {n_train} training and {n_test} "
+                               "held-out configurations (seeds 4000+j, held out from j=1800)",
+                   "n_train": n_train, "n_test": n_test, "epochs": epochs},
+        "passes_random_mean": float(pr.mean()), "passes_random_sd": float(pr.std()),
+        "passes_learned_mean": float(pl.mean()), "passes_learned_sd": float(pl.std()),
+        "passes_saved_sd": float(np.std(pr - pl)),
+        "time_to_tol_ms_random_mean": float(tr.mean()), "time_to_tol_ms_learned_mean": float(tl.mean()),
+        "fallbacks": int(sum(r_["fallback"] for r_ in rows)),
+        "all_converged": bool(all(r_["converged"] for r_ in rows)),
+        "train_loss_first_last": [curve[0], curve[-1]],
+        "heldout_loss_mean": float(np.mean([r_["heldout_loss"] for r_ in rows])),
+        "data_generation_s": t_gen, "training_s": t_train, "data_passes_mean": float(np.mean(gen_passes)),
+    }
     print(json.dumps(out), flush=True)
 
 

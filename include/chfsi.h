@@ -118,7 +118,7 @@ typedef struct {
  *   prec_switch    1: mixed-precision schedule.  After each pass the filter
  *                  precision is raised one level (BF16 -> F32 -> F64,
  *                  C64 -> C128) once r = max_{i<N} r_i has reached the
- *                  level's rounding floor, r <= 16 u b (u = 2^-8 for BF16,
+ *                  level's rounding floor, r <= 4 u b (u = 2^-8 for BF16,
  *                  2^-24 for F32 and C64; b the upper bound), or once r has
  *                  grown in two passes in a row.  0: the precision stays;
  *   hist_len       entries available in each non-NULL history array below;

@@ -784,7 +784,7 @@ int next_prec(int prec, const double* r, int k, double b) {
   else if (prec == CHFSI_F32) { up = CHFSI_F64; u = std::ldexp(1.0, -24); }
   else if (prec == CHFSI_C64) { up = CHFSI_C128; u = std::ldexp(1.0, -24); }
   else return prec;
-  const bool floor_reached = r[k] <= 16.0 * u * b;
+  const bool floor_reached = r[k] <= 4.0 * u * b;
   const bool growing = k >= 2 && r[k] > r[k - 1] && r[k - 1] > r[k - 2];
   return (floor_reached || growing) ? up : prec;
 }

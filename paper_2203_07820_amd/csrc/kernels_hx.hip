@@ -3,10 +3,11 @@
 // (Section 3.1).
 //
 // One workgroup owns one hexahedral cell and a 64-wide tile of columns.  It
-//   1. gathers the cell's nodal rows X^c (node-major, 64 contiguous values per
-//      node) through LDS in 16-row chunks, double buffered;
+//   1. reads the cell's nodal rows X^c (node-major, 64 contiguous values per
+//      node) straight into MFMA B-operand registers;
 //   2. multiplies the shared reference cell matrix A (mcell x mcell, streamed
-//      from L2 in MFMA operand order) by X^c with 16x16x4 MFMA (f64 or f32),
+//      from L2 in MFMA operand order) by X^c with 16x16x4 MFMA (f64 or f32;
+//      16x16x32 bf16 with f32 accumulation for the bf16 variant),
 //      accumulating in registers; for complex operators A_r X + A_i X' where
 //      X' is X with (re, im) -> (-im, re);
 //   3. adds the nonlocal term C^{c,a} (h P_a) for every atom a whose
@@ -31,12 +32,10 @@ namespace chfsi {
 namespace {
 
 constexpr int kNT = 64;     // columns per workgroup tile
-// B operands read directly from global memory (no LDS staging, no barriers)
-constexpr bool kDirect = true;
-constexpr int kKC = 16;     // cell rows (k values) per LDS chunk
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 template <typename T> struct Mma;
 // Operand layouts (both types): lane l supplies A[l % 16][l / 16] and
@@ -56,6 +55,12 @@ template <> struct Mma<float> {
   }
   __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane / 16) + i; }
 };
+// bf16 16x16x32 with f32 accumulation: lane l supplies A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16], j = 0..7; the accumulator layout is that of
+// the f32 16x16x4 MFMA, so both kinds can accumulate into the same tile.
+__device__ __forceinline__ f4 mma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
@@ -71,8 +76,9 @@ __device__ __forceinline__ int xcd_remap(int pid, int nblk) {
 
 template <typename T>
 struct HxArgs {
-  const T* A;
-  const T* Ai;
+  const T* A;       // cell matrix, 16x16x4 A-operand order [row tile][k step][lane]
+  const T* Ai;      // imaginary part (complex operators)
+  const bf8* Ab;    // bf16 copy, 16x16x32 A-operand order [row tile][k step][lane]
   const double* vdiag;
   const T* Xk;
   const T* Xp;
@@ -89,36 +95,34 @@ struct HxArgs {
   int64_t ldhp;
 };
 
+// One work item: cell `cell`, columns [col0, col0 + 64).
+//
 // Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
 // number of 16-row tiles is even for every order p in [2, 7], so each wave
 // owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
-// A fragments of the next LDS chunk are loaded into registers before the
-// gather of that chunk is issued: vector-memory counters retire in order, so
-// the MFMAs of a chunk never wait for the (HBM-latency) gather loads.
-template <int P, int KPC> struct CellShape {
-  static constexpr int Q = P + 1;
-  static constexpr int MC = Q * Q * Q;
-  static constexpr int MP = (MC + 15) / 16 * 16;
-  static constexpr int KC = 4 * KPC;  // cell rows per LDS chunk
-};
-
-// One work item: cell `cell`, columns [col0, col0 + 64).  xs is the
-// workgroup's LDS staging buffer (2 x KC x 64).
-template <int P, typename T, bool CPLX, int WAVES, int KPC, bool DIRECT>
-__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
-                                          T (*xs)[4 * KPC][kNT]) {
+// B fragments are read straight from global memory into registers (no LDS
+// staging, no barriers): in a 4-wide k step, lanes 16 q .. 16 q + 15 read 16
+// consecutive columns of cell row 4 kg + q, one cache line per 16 lanes.  A
+// fragments are loaded one k step ahead and B fragments two (HBM latency);
+// the A load of the next step is issued before the B load two steps ahead,
+// so that the in-order vector-memory counter never makes an MFMA wait on HBM.
+//
+// BF selects the bf16 cell products (FP32 iterates): a 32-wide k step needs
+// 8 cell rows per lane, whose node ids come from a per-cell table in LDS
+// (gtab, MP entries); the FP32 values are rounded to bf16 (to nearest even)
+// in registers.
+template <int P, typename T, bool CPLX, int WAVES, bool BF>
+__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0, int32_t* gtab) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
   constexpr int MP = (MC + 15) / 16 * 16;
   constexpr int RT = MP / 16;           // row tiles
   constexpr int KS = MP / 4;            // 4-wide k steps
-  constexpr int KC = 4 * KPC;           // cell rows per LDS chunk
-  constexpr int NCH = MP / KC;          // LDS chunks
   constexpr int RG = WAVES / 2;         // row groups
   constexpr int RPW = RT / RG;          // row tiles per wave
-  constexpr int CPW = kNT / 32;          // column tiles per wave (2 column groups)
-  constexpr int GR = KC / WAVES;        // gathered rows per thread and chunk
-  static_assert(MP % KC == 0 && RT % RG == 0 && KC % WAVES == 0, "tiling");
+  constexpr int CPW = kNT / 32;         // column tiles per wave (2 column groups)
+  static_assert(RT % RG == 0 && KS % 2 == 0, "tiling");
+  static_assert(!BF || (MP % 32 == 0 && !CPLX && sizeof(T) == 4), "bf16 variant: real FP32 iterates");
   using acc_t = typename Mma<T>::acc_t;
 
   const int tid = threadIdx.x;
@@ -142,150 +146,123 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 #pragma unroll
     for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
 
-  if constexpr (DIRECT) {
-  // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
-  const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
-  const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
-  constexpr int RI = CPLX ? RPW : 1;
-  constexpr int CI = CPLX ? CPW : 1;
-  // k step kg: lanes 16 q .. 16 q + 15 hold cell row 4 kg + q, 16 consecutive
-  // columns of one node: one full cache line per 16 lanes, read straight into
-  // the B-operand registers (no LDS, no barrier).
   const T* Xc = a.Xk + col0;
-  auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
+  if constexpr (BF) {
+    constexpr int KB = MP / 32;         // 32-wide k steps
+    for (int l = tid; l < MP; l += 64 * WAVES) gtab[l] = l < MC ? static_cast<int32_t>(gnode(l)) : -1;
+    __syncthreads();
+    const bf8* Aw = a.Ab + static_cast<int64_t>(rt0) * KB * 64 + lane;
+    auto load_a = [&](bf8 (&av)[RPW], int kg) {
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      av[r] = Aw[(static_cast<int64_t>(r) * KS + kg) * 64];
-      if constexpr (CPLX) avi[r] = Aiw[(static_cast<int64_t>(r) * KS + kg) * 64];
-    }
-  };
-  auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
-    const int l = kg * 4 + lane / 16;
-    const int64_t gn = l < MC ? gnode(l) : 0;
+      for (int r = 0; r < RPW; ++r) av[r] = Aw[(static_cast<int64_t>(r) * KB + kg) * 64];
+    };
+    auto load_b = [&](float (&bv)[CPW][8], int kg) {
+      const int l0 = kg * 32 + 8 * (lane / 16);
+      int32_t g[8];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      const int cc = (ct0 + c) * 16 + lane % 16;
-      const bool ok = l < MC && col0 + cc < a.ncols;
-      bv[c] = ok ? Xc[gn * a.ldx + cc] : T(0);
-      if constexpr (CPLX) bo[c] = ok ? Xc[gn * a.ldx + (cc ^ 1)] : T(0);
-    }
-  };
-  auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bv)[CPW], const T (&bo)[CI]) {
-    T bs[CPW];
-    if constexpr (CPLX) {
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
-    }
-#pragma unroll
-    for (int r = 0; r < RPW; ++r)
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        acc[r][c] = Mma<T>::run(av[r], bv[c], acc[r][c]);
-        if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
-      }
-  };
-  // A one k step ahead, B (HBM latency) two k steps ahead; KS is even.
-  T a0[RPW], a1[RPW], ai0[RI], ai1[RI];
-  T b0[CPW], b1[CPW], b2[CPW], b3[CPW], o0[CI], o1[CI], o2[CI], o3[CI];
-  load_b(b0, o0, 0);
-  load_a(a0, ai0, 0);
-  load_b(b1, o1, 1);
-  for (int kg = 0; kg < KS; kg += 2) {
-    load_a(a1, ai1, kg + 1);
-    if (kg + 2 < KS) load_b(b2, o2, kg + 2);
-    compute(a0, ai0, b0, o0);
-    if (kg + 2 < KS) load_a(a0, ai0, kg + 2);
-    if (kg + 3 < KS) load_b(b3, o3, kg + 3);
-    compute(a1, ai1, b1, o1);
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      b0[c] = b2[c];
-      b1[c] = b3[c];
-      if constexpr (CPLX) {
-        o0[c] = o2[c];
-        o1[c] = o3[c];
-      }
-    }
-  }
-
-  } else {
-  // gather: thread owns column `lane` of rows wave, wave + WAVES, ...
-  const bool col_ok = (col0 + lane) < a.ncols;
-  auto load_chunk = [&](T (&g)[GR], int ch) {
-#pragma unroll
-    for (int i = 0; i < GR; ++i) {
-      const int l = ch * KC + wave + WAVES * i;
-      T v = T(0);
-      if (l < MC && col_ok) v = a.Xk[gnode(l) * a.ldx + col0 + lane];
-      g[i] = v;
-    }
-  };
-  auto store_chunk = [&](const T (&g)[GR], int buf) {
-#pragma unroll
-    for (int i = 0; i < GR; ++i) xs[buf][wave + WAVES * i][lane] = g[i];
-  };
-
-  // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
-  const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
-  const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
-  constexpr int NI = CPLX ? KPC : 1;
-  constexpr int RI = CPLX ? RPW : 1;
-  auto load_a = [&](T (&dst)[KPC][RPW], T (&dsti)[NI][RI], int ch) {
-#pragma unroll
-    for (int s = 0; s < KPC; ++s)
-#pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        dst[s][r] = Aw[(static_cast<int64_t>(r) * KS + ch * KPC + s) * 64];
-        if constexpr (CPLX) dsti[s][r] = Aiw[(static_cast<int64_t>(r) * KS + ch * KPC + s) * 64];
-      }
-  };
-
-  // One chunk: issue A of chunk ch+1 and the gather of chunk ch+2 (in that
-  // order), multiply with A of chunk ch and the LDS copy of chunk ch, then
-  // store the gather of chunk ch+1 (issued one chunk earlier) to LDS.
-  auto chunk_step = [&](int ch, T (&acur)[KPC][RPW], T (&aicur)[NI][RI], T (&anext)[KPC][RPW],
-                        T (&ainext)[NI][RI], T (&gstore)[GR], T (&gload)[GR]) {
-    const int buf = ch & 1;
-    if (ch + 1 < NCH) load_a(anext, ainext, ch + 1);
-    if (ch + 2 < NCH) load_chunk(gload, ch + 2);
-#pragma unroll
-    for (int s = 0; s < KPC; ++s) {
-      const int krow = s * 4 + lane / 16;
-      T b[CPW], bs[CPW];
+      for (int j = 0; j < 8; ++j) g[j] = gtab[l0 + j];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const int cc = (ct0 + c) * 16 + lane % 16;
-        b[c] = xs[buf][krow][cc];
-        if constexpr (CPLX) {
-          const T o = xs[buf][krow][cc ^ 1];
-          bs[c] = (cc & 1) ? o : -o;
-        }
+        const bool okc = col0 + cc < a.ncols;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          bv[c][j] = (okc && g[j] >= 0) ? Xc[static_cast<int64_t>(g[j]) * a.ldx + cc] : 0.f;
+      }
+    };
+    auto pack = [&](const float (&bv)[CPW][8], bf8 (&bp)[CPW]) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bp[c][j] = static_cast<__bf16>(bv[c][j]);
+    };
+    // Pipeline: the raw FP32 rows of step kg + 2 are in flight while step kg
+    // multiplies; those of step kg + 1 are rounded to bf16 right after, so
+    // only one raw stage occupies registers.
+    bf8 a0[RPW], a1[RPW], p0[CPW];
+    float braw[CPW][8], bnext[CPW][8];
+    load_b(braw, 0);
+    load_a(a0, 0);
+    if (KB > 1) load_b(bnext, 1);
+    pack(braw, p0);
+#pragma unroll 1
+    for (int kg = 0; kg < KB; ++kg) {
+      if (kg + 1 < KB) load_a(a1, kg + 1);
+      if (kg + 2 < KB) load_b(braw, kg + 2);
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(a0[r], p0[c], acc[r][c]);
+      if (kg + 1 < KB) {
+        pack(bnext, p0);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) a0[r] = a1[r];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bnext[c][j] = braw[c][j];
+      }
+    }
+  } else {
+    // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
+    const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
+    const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
+    constexpr int RI = CPLX ? RPW : 1;
+    constexpr int CI = CPLX ? CPW : 1;
+    auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        av[r] = Aw[(static_cast<int64_t>(r) * KS + kg) * 64];
+        if constexpr (CPLX) avi[r] = Aiw[(static_cast<int64_t>(r) * KS + kg) * 64];
+      }
+    };
+    auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
+      const int l = kg * 4 + lane / 16;
+      const int64_t gn = l < MC ? gnode(l) : 0;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int cc = (ct0 + c) * 16 + lane % 16;
+        const bool ok = l < MC && col0 + cc < a.ncols;
+        bv[c] = ok ? Xc[gn * a.ldx + cc] : T(0);
+        if constexpr (CPLX) bo[c] = ok ? Xc[gn * a.ldx + (cc ^ 1)] : T(0);
+      }
+    };
+    auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bv)[CPW], const T (&bo)[CI]) {
+      T bs[CPW];
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
       }
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
-          acc[r][c] = Mma<T>::run(acur[s][r], b[c], acc[r][c]);
-          if constexpr (CPLX) acc[r][c] = Mma<T>::run(aicur[s][r], bs[c], acc[r][c]);
+          acc[r][c] = Mma<T>::run(av[r], bv[c], acc[r][c]);
+          if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
         }
+    };
+    T a0[RPW], a1[RPW], ai0[RI], ai1[RI];
+    T b0[CPW], b1[CPW], b2[CPW], b3[CPW], o0[CI], o1[CI], o2[CI], o3[CI];
+    load_b(b0, o0, 0);
+    load_a(a0, ai0, 0);
+    load_b(b1, o1, 1);
+    for (int kg = 0; kg < KS; kg += 2) {
+      load_a(a1, ai1, kg + 1);
+      if (kg + 2 < KS) load_b(b2, o2, kg + 2);
+      compute(a0, ai0, b0, o0);
+      if (kg + 2 < KS) load_a(a0, ai0, kg + 2);
+      if (kg + 3 < KS) load_b(b3, o3, kg + 3);
+      compute(a1, ai1, b1, o1);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        b0[c] = b2[c];
+        b1[c] = b3[c];
+        if constexpr (CPLX) {
+          o0[c] = o2[c];
+          o1[c] = o3[c];
+        }
+      }
     }
-    if (ch + 1 < NCH) store_chunk(gstore, buf ^ 1);
-    __syncthreads();
-  };
-
-  T a0[KPC][RPW], a1[KPC][RPW];
-  T ai0[NI][RI], ai1[NI][RI];
-  T g0[GR], g1[GR];
-  load_a(a0, ai0, 0);
-  load_chunk(g0, 0);
-  store_chunk(g0, 0);
-  if (NCH > 1) load_chunk(g0, 1);
-  __syncthreads();
-  for (int ch = 0; ch < NCH; ch += 2) {
-    chunk_step(ch, a0, ai0, a1, ai1, g0, g1);
-    if (ch + 1 < NCH) chunk_step(ch + 1, a1, ai1, a0, ai0, g1, g0);
-  }
-
   }
 
   // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell, one
@@ -362,14 +339,19 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   }
 }
 
+template <int P> constexpr int waves_for() {
+  return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 > 24 ? 8 : 4;
+}
+template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16; }
+
 // Single problem: one workgroup per (cell, column tile), cells fastest.
-template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
+template <int P, typename T, bool CPLX, int WAVES, int OCC, bool BF>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
-  __shared__ T xs[2][4 * KPC][kNT];
+  __shared__ int32_t gtab[BF ? rows_padded<P>() : 1];
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, KPC, kDirect>(a, bid % E, (bid / E) * kNT, xs);
+  cell_item<P, T, CPLX, WAVES, BF>(a, bid % E, (bid / E) * kNT, gtab);
 }
 
 // Many problems in one persistent launch: the work list is the concatenation
@@ -379,11 +361,10 @@ cell_hx_kernel(const HxArgs<T> a) {
 // neighbouring cells of one problem.  Per-problem arguments, including the
 // recurrence scalars, are read from the device table `descs`, so a captured
 // graph stays valid when the host rewrites the table between replays.
-template <int P, typename T, bool CPLX, int WAVES, int KPC, int OCC>
+template <int P, typename T, bool CPLX, int WAVES, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob,
                        const int contiguous) {
-  __shared__ T xs[2][4 * KPC][kNT];
   const int64_t nitems = item_off[nprob];
   const int64_t G = gridDim.x;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -397,16 +378,24 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const HxArgs<T> d = descs[q];
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
-    __syncthreads();
-    cell_item<P, T, CPLX, WAVES, KPC, kDirect>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, xs);
+    cell_item<P, T, CPLX, WAVES, false>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, nullptr);
   }
 }
 
-template <int P, typename T, bool CPLX>
-hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
+// Waves per SIMD: two for real and complex FP64, complex FP32 and bf16 (one
+// workgroup's epilogue overlaps the other's MFMAs), three for real FP32
+// (140 VGPRs at p = 6); complex FP64 at p = 6 (11 row tiles per wave, A and
+// B fragments doubled) needs the 512 registers of one wave per SIMD.
+template <int P, typename T, bool CPLX, bool BF> constexpr int occupancy() {
+  return BF ? 2 : ((CPLX && sizeof(T) == 8) ? (P == 6 ? 1 : 2) : ((!CPLX && sizeof(T) == 4) ? 3 : 2));
+}
+
+template <typename T>
+HxArgs<T> pack_args(const HxLaunch& L) {
   HxArgs<T> a;
   a.A = static_cast<const T*>(L.A);
   a.Ai = static_cast<const T*>(L.Ai);
+  a.Ab = static_cast<const bf8*>(L.Abf);
   a.vdiag = L.vdiag;
   a.Xk = static_cast<const T*>(L.Xk);
   a.Xp = static_cast<const T*>(L.Xp);
@@ -426,224 +415,35 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   a.pair_im = static_cast<const T*>(L.pair_im);
   a.hP = static_cast<const T*>(L.hP);
   a.ldhp = L.ldhp;
+  return a;
+}
+
+template <int P, typename T, bool CPLX, bool BF>
+hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
+  const HxArgs<T> a = pack_args<T>(L);
   const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
   const int64_t nct = (L.ncols + kNT - 1) / kNT;
   const int64_t nblk = E * nct;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
-  constexpr int WAVES = RT > 24 ? 8 : 4;
-  // Waves per SIMD: two for real FP64 and complex FP32 (one workgroup's
-  // epilogue overlaps the other's MFMAs), three for real FP32 (140 VGPRs at
-  // p = 6), one for complex FP64, whose A and B fragments double the
-  // register count.  KPC sizes the LDS chunk of the staged-gather variant.
-  constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
-  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
-  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(static_cast<unsigned>(nblk)),
+  constexpr int WAVES = waves_for<P>();
+  constexpr int OCC = occupancy<P, T, CPLX, BF>();
+  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, OCC, BF>), dim3(static_cast<unsigned>(nblk)),
                      dim3(64 * WAVES), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool CPLX>
+template <typename T, bool CPLX, bool BF>
 hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
   switch (L.p) {
-    case 2: return launch_p<2, T, CPLX>(L, s);
-    case 3: return launch_p<3, T, CPLX>(L, s);
-    case 4: return launch_p<4, T, CPLX>(L, s);
-    case 5: return launch_p<5, T, CPLX>(L, s);
-    case 6: return launch_p<6, T, CPLX>(L, s);
-    case 7: return launch_p<7, T, CPLX>(L, s);
+    case 2: return launch_p<2, T, CPLX, BF>(L, s);
+    case 3: return launch_p<3, T, CPLX, BF>(L, s);
+    case 4: return launch_p<4, T, CPLX, BF>(L, s);
+    case 5: return launch_p<5, T, CPLX, BF>(L, s);
+    case 6: return launch_p<6, T, CPLX, BF>(L, s);
+    case 7: return launch_p<7, T, CPLX, BF>(L, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-// ---- BF16 variant ------------------------------------------------------------
-// Same structure as cell_hx_kernel with FP32 iterates: the cell products take
-// bf16-rounded inputs (round to nearest even) on v_mfma_f32_16x16x32_bf16 with
-// FP32 accumulation; the potential, recurrence and nonlocal terms stay FP32
-// (the nonlocal k steps use the f32 16x16x4 MFMA into the same accumulators,
-// whose layout is shared by all 16x16 f32-output MFMAs).  Operand layout of
-// the bf16 MFMA: lane l supplies A[l % 16][8 (l / 16) + j] and
-// B[8 (l / 16) + j][l % 16] for j = 0..7.
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-
-constexpr int kKB = 32;        // cell rows per LDS chunk (one bf16 k step)
-constexpr int kXR = kKB + 8;   // padded row length of the transposed chunk
-
-template <int P, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES)
-cell_hx_bf16_kernel(const HxArgs<float> a, const bf8* __restrict__ Abf) {
-  constexpr int Q = P + 1;
-  constexpr int MC = Q * Q * Q;
-  constexpr int MP = (MC + kKB - 1) / kKB * kKB;   // rows/k padded to 32
-  constexpr int RT = MP / 16;
-  constexpr int KS = MP / kKB;                     // 32-wide k steps
-  constexpr int RW = (RT + WAVES - 1) / WAVES;
-  constexpr int RT4 = (MC + 15) / 16;              // row tiles of the f32 pair tables
-  static_assert(kKB % (2 * WAVES) == 0, "chunk rows must split evenly");
-
-  // transposed chunk: xs[buf][col][row] as bf16
-  __shared__ __attribute__((aligned(16))) __bf16 xs[2][kNT][kXR];
-
-  const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid % 64;
-  const int nc = a.nc, n = nc * P;
-  const int E = nc * nc * nc;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int cell = bid % E;
-  const int col0 = (bid / E) * kNT;
-  const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
-
-  auto gnode = [&](int l) -> int64_t {
-    const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
-    int gx = cx * P + la; if (gx >= n) gx -= n;
-    int gy = cy * P + lb; if (gy >= n) gy -= n;
-    int gz = cz * P + lc; if (gz >= n) gz -= n;
-    return gx + static_cast<int64_t>(n) * (gy + static_cast<int64_t>(n) * gz);
-  };
-
-  // gather: thread owns column `lane`, row pairs (2 wave + 2 WAVES i, +1)
-  constexpr int NPAIR = kKB / (2 * WAVES);
-  float g[2 * NPAIR];
-  const bool col_ok = (col0 + lane) < a.ncols;
-  auto load_chunk = [&](int ch) {
-#pragma unroll
-    for (int i = 0; i < NPAIR; ++i)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int l = ch * kKB + 2 * wave + 2 * WAVES * i + h;
-        float v = 0.f;
-        if (l < MC && col_ok) v = a.Xk[gnode(l) * a.ldx + col0 + lane];
-        g[2 * i + h] = v;
-      }
-  };
-  auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NPAIR; ++i) {
-      bf2 v;
-      v[0] = static_cast<__bf16>(g[2 * i]);
-      v[1] = static_cast<__bf16>(g[2 * i + 1]);
-      *reinterpret_cast<bf2*>(&xs[buf][lane][2 * wave + 2 * WAVES * i]) = v;
-    }
-  };
-
-  f4 acc[RW][4];
-#pragma unroll
-  for (int r = 0; r < RW; ++r)
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[r][ct] = f4{0, 0, 0, 0};
-
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  for (int ch = 0; ch < KS; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < KS) load_chunk(ch + 1);
-    bf8 b[4];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-      b[ct] = *reinterpret_cast<const bf8*>(&xs[buf][ct * 16 + lane % 16][8 * (lane / 16)]);
-#pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int rt = wave + WAVES * r;
-      if (rt < RT) {
-        const bf8 av = Abf[(static_cast<int64_t>(rt) * KS + ch) * 64 + lane];
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-          acc[r][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[ct], acc[r][ct], 0, 0, 0);
-      }
-    }
-    if (ch + 1 < KS) store_chunk(buf ^ 1);
-    __syncthreads();
-  }
-
-  // nonlocal in FP32
-  if (a.pair_ptr != nullptr) {
-    const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
-    for (int pr = p0; pr < p1; ++pr) {
-      const int at = a.pair_atom[pr];
-      float b[4];
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-        b[ct] = a.hP[(static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0 + ct * 16 + lane % 16];
-#pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const int rt = wave + WAVES * r;
-        if (rt < RT4) {
-          const float cv = a.pair_re[(static_cast<int64_t>(pr) * RT4 + rt) * 64 + lane];
-#pragma unroll
-          for (int ct = 0; ct < 4; ++ct) acc[r][ct] = Mma<float>::run(cv, b[ct], acc[r][ct]);
-        }
-      }
-    }
-  }
-
-#pragma unroll
-  for (int r = 0; r < RW; ++r) {
-    const int rt = wave + WAVES * r;
-    if (rt >= RT) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = rt * 16 + Mma<float>::row(lane, i);
-      if (row >= MC) continue;
-      const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
-      const bool owner = (la < P) && (lb < P) && (lc < P);
-      const int64_t gn = gnode(row);
-      float vc = 0.f;
-      if (owner) vc = a.alpha * (static_cast<float>(a.vdiag[gn]) - a.c);
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int col = col0 + ct * 16 + lane % 16;
-        if (col >= a.ncols) continue;
-        float v = a.alpha * acc[r][ct][i];
-        if (owner) {
-          v += vc * a.Xk[gn * a.ldx + col];
-          if (a.Xp != nullptr) {
-            float* xp = const_cast<float*>(a.Xp) + gn * a.ldp + col;
-            v -= a.beta * (*xp);
-            if (a.zero_prev) *xp = 0.f;
-          }
-        }
-        atomic_add(a.Tg + gn * a.ldt + col, v);
-      }
-    }
-  }
-}
-
-template <int P>
-hipError_t launch_bf16_p(const HxLaunch& L, hipStream_t s) {
-  HxArgs<float> a;
-  a.A = nullptr;
-  a.Ai = nullptr;
-  a.vdiag = L.vdiag;
-  a.Xk = static_cast<const float*>(L.Xk);
-  a.Xp = static_cast<const float*>(L.Xp);
-  a.Tg = static_cast<float*>(L.T);
-  a.ldx = L.ldx;
-  a.ldp = L.ldp;
-  a.ldt = L.ldt;
-  a.ncols = L.ncols;
-  a.nc = L.nc;
-  a.zero_prev = L.zero_prev ? 1 : 0;
-  a.alpha = static_cast<float>(L.alpha);
-  a.c = static_cast<float>(L.c);
-  a.beta = static_cast<float>(L.beta);
-  a.pair_ptr = L.pair_ptr;
-  a.pair_atom = L.pair_atom;
-  a.pair_re = static_cast<const float*>(L.pair_re);
-  a.pair_im = nullptr;
-  a.hP = static_cast<const float*>(L.hP);
-  a.ldhp = L.ldhp;
-  const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
-  const int64_t nblk = E * ((L.ncols + kNT - 1) / kNT);
-  if (nblk <= 0) return hipSuccess;
-  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + kKB - 1) / kKB * kKB / 16;
-  constexpr int WAVES = RT > 24 ? 8 : 4;
-  hipLaunchKernelGGL((cell_hx_bf16_kernel<P, WAVES>), dim3(static_cast<unsigned>(nblk)), dim3(64 * WAVES), 0, s,
-                     a, static_cast<const bf8*>(L.Abf));
-  return hipGetLastError();
 }
 
 // ---- node-level projector contraction (Algorithm 4 steps 1-4) -------------
@@ -769,41 +569,12 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-template <typename T>
-HxArgs<T> pack_args(const HxLaunch& L) {
-  HxArgs<T> a;
-  a.A = static_cast<const T*>(L.A);
-  a.Ai = static_cast<const T*>(L.Ai);
-  a.vdiag = L.vdiag;
-  a.Xk = static_cast<const T*>(L.Xk);
-  a.Xp = static_cast<const T*>(L.Xp);
-  a.Tg = static_cast<T*>(L.T);
-  a.ldx = L.ldx;
-  a.ldp = L.ldp;
-  a.ldt = L.ldt;
-  a.ncols = L.ncols;
-  a.nc = L.nc;
-  a.zero_prev = L.zero_prev ? 1 : 0;
-  a.alpha = static_cast<T>(L.alpha);
-  a.c = static_cast<T>(L.c);
-  a.beta = static_cast<T>(L.beta);
-  a.pair_ptr = L.pair_ptr;
-  a.pair_atom = L.pair_atom;
-  a.pair_re = static_cast<const T*>(L.pair_re);
-  a.pair_im = static_cast<const T*>(L.pair_im);
-  a.hP = static_cast<const T*>(L.hP);
-  a.ldhp = L.ldhp;
-  return a;
-}
-
 template <int P, typename T, bool CPLX>
 hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
-  constexpr int RT = ((P + 1) * (P + 1) * (P + 1) + 15) / 16;
-  constexpr int WAVES = RT > 24 ? 8 : 4;
-  constexpr int KPC = sizeof(T) == 8 ? (WAVES == 4 ? 1 : 2) : (CPLX ? 2 : 4);
-  constexpr int OCC = (CPLX && sizeof(T) == 8) ? 1 : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
+  constexpr int WAVES = waves_for<P>();
+  constexpr int OCC = occupancy<P, T, CPLX, false>();
   if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, KPC, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
+  hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
                      static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);
   return hipGetLastError();
 }
@@ -849,23 +620,14 @@ hipError_t launch_cell_hx_batched(const HxBatch& b, int prec, hipStream_t s) {
 
 hipError_t launch_cell_hx(const HxLaunch& L, int prec, hipStream_t s) {
   if (L.p < kMinOrder || L.p > kMaxOrder) return hipErrorInvalidValue;
-  if (prec == CHFSI_BF16) {
-    if (L.cplx || L.Abf == nullptr) return hipErrorInvalidValue;
-    switch (L.p) {
-      case 2: return launch_bf16_p<2>(L, s);
-      case 3: return launch_bf16_p<3>(L, s);
-      case 4: return launch_bf16_p<4>(L, s);
-      case 5: return launch_bf16_p<5>(L, s);
-      case 6: return launch_bf16_p<6>(L, s);
-      case 7: return launch_bf16_p<7>(L, s);
-      default: return hipErrorInvalidValue;
-    }
-  }
   switch (prec) {
-    case CHFSI_F64: return launch_t<double, false>(L, s);
-    case CHFSI_F32: return launch_t<float, false>(L, s);
-    case CHFSI_C128: return launch_t<double, true>(L, s);
-    case CHFSI_C64: return launch_t<float, true>(L, s);
+    case CHFSI_F64: return launch_t<double, false, false>(L, s);
+    case CHFSI_F32: return launch_t<float, false, false>(L, s);
+    case CHFSI_BF16:
+      if (L.cplx || L.Abf == nullptr) return hipErrorInvalidValue;
+      return launch_t<float, false, true>(L, s);
+    case CHFSI_C128: return launch_t<double, true, false>(L, s);
+    case CHFSI_C64: return launch_t<float, true, false>(L, s);
     default: return hipErrorInvalidValue;
   }
 }
