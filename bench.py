@@ -89,9 +89,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "kernels"],
                     help="c1: FP64 pass at production size (the headline line); c2: mixed precision "
-                         "time-to-accuracy at N=1024; c3: batched k-point solves; c4: learned warm start")
+                         "time-to-accuracy at N=1024; c3: batched k-point solves; c4: learned warm start; "
+                         "kernels: one 128-column filter step per precision")
     ap.add_argument("--out", default=None, help="write per-pass histories (npz) here")
     ap.add_argument("--max-passes", type=int, default=0, help="c2: pass cap per run (0: default)")
     ap.add_argument("--c2-runs", default="f32,mixed,bf16", help="c2: runs beside the FP64 reference")
@@ -109,6 +110,8 @@ def main():
         return run_c3(args)
     if args.workload == "c4":
         return run_c4(args)
+    if args.workload == "kernels":
+        return run_kernels(args)
     return run_c1(args)
 
 
@@ -495,13 +498,14 @@ def run_c4(args):
     t_train = time.perf_counter() - t0
     del feats, targets
     # 4. held-out configurations: random start vs learned start
-    rows = []
+    rows, captures = [], []
     for i in range(n_test):
         j = 1800 + i
         op = lib.Operator(ctx, workloads.config("c4", j))
         X = random_block(op, j)
         _, _, st_r = solve(op, X, j)
         Q = X[:, :N].float().contiguous()
+        Qbuf = X[:, N:].clone() if i < 8 else None   # Ritz vectors of states N+1 .. N+n_buf
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         F = featurize(op)
@@ -511,6 +515,14 @@ def run_c4(args):
         t_init = time.perf_counter() - t1
         _, _, st_l = solve(op, Xl, j)
         loss, _ = net.loss_grad(F, Q, want_grads=False)
+        if i < 8:
+            # diagnostic: how much of each converged state the network's span holds
+            Y = torch.empty(op.M, N, dtype=torch.float32, device="cuda")
+            net.forward(F, Y)
+            Qy, _ = torch.linalg.qr(Y.double())
+            Cq = Qy.T @ torch.cat([Q.double(), Qbuf], dim=1)
+            captures.append((Cq * Cq).sum(dim=0).cpu().numpy())
+            del Y, Qy, Cq, Qbuf
         rows.append({"passes_random": st_r["passes"], "passes_learned": st_l["passes"],
                      "ms_random": st_r["t_total"], "ms_learned": st_l["t_total"] + 1e3 * t_init,
                      "converged": bool(st_r["converged"] and st_l["converged"]), "fallback": fallback,
@@ -541,7 +553,64 @@ def run_c4(args):
         "train_loss_first_last": [curve[0], curve[-1]],
         "heldout_loss_mean": float(np.mean([r_["heldout_loss"] for r_ in rows])),
         "data_generation_s": t_gen, "training_s": t_train, "data_passes_mean": float(np.mean(gen_passes)),
+        "captured_fraction_by_state_quarter": [float(x) for x in
+                                               np.mean(captures, axis=0)[:N].reshape(4, -1).mean(axis=1)],
+        "captured_fraction_buffer_states": float(np.mean(np.mean(captures, axis=0)[N:])),
+        "captured_fraction_random_block": N / 216000.0,
     }
+    print(json.dumps(out), flush=True)
+
+
+PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "c128": 78.6, "c64": 157.3}
+
+
+def run_kernels(args):
+    """The cell kernel in every precision on its production operator: 128-column
+    filter steps (the fused recurrence) on the c1 operator (real: F64, F32,
+    BF16) and on the largest c3 operator at its first k-point (C128, C64)."""
+    import torch
+
+    import paper_2203_07820_amd as lib
+    import workloads
+
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+    B, steps = 128, max(2, args.steps * 4)
+    c3 = workloads.config("c3", 7)
+    c1, c3k = workloads.config("c1"), c3.with_k(workloads.kpoints_mp4(c3.L)[0])
+    cases = [("f64", lib.F64, c1), ("f32", lib.F32, c1), ("bf16", lib.BF16, c1),
+             ("c128", lib.C128, c3k), ("c64", lib.C64, c3k)]
+    res, ops = {}, {}
+    for name, prec, sys_ in cases:
+        if id(sys_) not in ops:
+            ops.clear()
+            ops[id(sys_)] = lib.Operator(ctx, sys_)
+        op = ops[id(sys_)]
+        dt = torch.complex128 if op.is_complex else torch.float64
+        X = torch.randn(op.M, B, dtype=dt, device="cuda")
+        b, _ = op.bounds(20, seed=1)
+        op.filter(X, 2, b * 0.1, b, -1.0, prec=prec, block=B)   # warm-up
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ctx.kernel_time(reset=True)
+        op.filter(X, steps, b * 0.1, b, -1.0, prec=prec, block=B)
+        kms, n, kfl = ctx.kernel_time(reset=True)
+        ctx.set_timing(False)
+        ebytes = {"f64": 8, "f32": 4, "bf16": 4, "c128": 16, "c64": 8}[name]
+        ms = kms / n
+        tf = kfl / (kms * 1e-3) / 1e12
+        hbm = 3.0 * op.M * B * ebytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms_per_step": ms, "tflops": tf, "frac_mfma_peak": tf / PEAKS_TFLOPS[name],
+                     "algorithmic_GBps": hbm, "frac_hbm_peak": hbm / PEAK_HBM_GBS, "M": op.M, "E": op.E,
+                     "mcell": op.mcell, "npairs": op.npairs, "launches": n}
+        log(f"# {name}: {ms:.3f} ms per step, {tf:.2f} TFLOP/s, {hbm:.0f} GB/s algorithmic")
+        del X
+    out = {"metric": "cell H·X filter step per precision", "value": res["f64"]["tflops"] * 1e3, "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": steps, "warmup": 2, "ms_per_step": res["f64"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "128-column filter steps: c1 operator (F64, F32, BF16); largest c3 operator "
+                                  "at its first k-point (C128, C64)"},
+           "kernels": res}
     print(json.dumps(out), flush=True)
 
 

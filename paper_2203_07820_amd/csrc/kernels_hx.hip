@@ -95,24 +95,52 @@ struct HxArgs {
   int64_t ldhp;
 };
 
+// Buffer resource over `bytes` bytes at p (raw buffer, 32-bit words).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ bf8 buf_load<bf8>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// Per-cell row tables in LDS, written once per work item: xoff[l] = element
+// offset of cell row l in X (node id * ldx; row 0's for padding rows) and
+// gid[l] = node id | owner << 30 (-1 for padding rows).  The owner of a node
+// is the cell in which its local indices are all < p.
+template <int MP> struct RowTables {
+  int64_t xoff[MP];
+  int32_t gid[MP];
+};
+
 // One work item: cell `cell`, columns [col0, col0 + 64).
 //
 // Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
 // number of 16-row tiles is even for every order p in [2, 7], so each wave
 // owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
 // B fragments are read straight from global memory into registers (no LDS
-// staging, no barriers): in a 4-wide k step, lanes 16 q .. 16 q + 15 read 16
-// consecutive columns of cell row 4 kg + q, one cache line per 16 lanes.  A
-// fragments are loaded one k step ahead and B fragments two (HBM latency);
-// the A load of the next step is issued before the B load two steps ahead,
-// so that the in-order vector-memory counter never makes an MFMA wait on HBM.
+// staging of X, no barriers in the loop): in a 4-wide k step, lanes
+// 16 q .. 16 q + 15 read 16 consecutive columns of cell row 4 kg + q, one
+// cache line per 16 lanes, at the row offset kept in the LDS table.  A
+// fragments come through buffer loads whose per-row-tile offsets live in
+// scalar registers; they are loaded one k step ahead and B fragments two
+// (HBM latency), the A load of the next step issued before the B load two
+// steps ahead, so that the in-order vector-memory counter never makes an MFMA
+// wait on HBM.  Column lanes beyond ncols read a valid column and are never
+// stored; padding rows (l >= mcell) are zeroed.
 //
 // BF selects the bf16 cell products (FP32 iterates): a 32-wide k step needs
-// 8 cell rows per lane, whose node ids come from a per-cell table in LDS
-// (gtab, MP entries); the FP32 values are rounded to bf16 (to nearest even)
+// 8 cell rows per lane; the FP32 values are rounded to bf16 (to nearest even)
 // in registers.
 template <int P, typename T, bool CPLX, int WAVES, bool BF>
-__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0, int32_t* gtab) {
+__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
+                                          RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16)>& tab) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
   constexpr int MP = (MC + 15) / 16 * 16;
@@ -132,13 +160,24 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   const int nc = a.nc, n = nc * P;
   const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
 
-  auto gnode = [&](int l) -> int64_t {
-    const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
-    int gx = cx * P + la; if (gx >= n) gx -= n;
-    int gy = cy * P + lb; if (gy >= n) gy -= n;
-    int gz = cz * P + lc; if (gz >= n) gz -= n;
-    return gx + static_cast<int64_t>(n) * (gy + static_cast<int64_t>(n) * gz);
-  };
+  // row tables (the barrier in front protects the previous item's readers)
+  __syncthreads();
+  for (int l = tid; l < MP; l += 64 * WAVES) {
+    int32_t g = -1;
+    int64_t off = 0;
+    if (l < MC) {
+      const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
+      int gx = cx * P + la; if (gx >= n) gx -= n;
+      int gy = cy * P + lb; if (gy >= n) gy -= n;
+      int gz = cz * P + lc; if (gz >= n) gz -= n;
+      const int32_t node = gx + n * (gy + n * gz);
+      off = static_cast<int64_t>(node) * a.ldx;
+      g = node | ((la < P && lb < P && lc < P) ? (1 << 30) : 0);
+    }
+    tab.xoff[l] = off;
+    tab.gid[l] = g;
+  }
+  __syncthreads();
 
   acc_t acc[RPW][CPW];
 #pragma unroll
@@ -146,35 +185,52 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 #pragma unroll
     for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
 
-  const T* Xc = a.Xk + col0;
+  // per-lane column pointers, clamped to a valid column; complex blocks keep
+  // the lane's parity (re/im) so that the partner column cc ^ 1 stays valid
+  // (their ncols, counted in reals, is even)
+  const T* xcol[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    int cc = col0 + (ct0 + c) * 16 + lane % 16;
+    if (cc >= a.ncols) cc = CPLX ? a.ncols - 2 + (lane & 1) : a.ncols - 1;
+    xcol[c] = a.Xk + cc;
+  }
+
   if constexpr (BF) {
     constexpr int KB = MP / 32;         // 32-wide k steps
-    for (int l = tid; l < MP; l += 64 * WAVES) gtab[l] = l < MC ? static_cast<int32_t>(gnode(l)) : -1;
-    __syncthreads();
-    const bf8* Aw = a.Ab + static_cast<int64_t>(rt0) * KB * 64 + lane;
-    auto load_a = [&](bf8 (&av)[RPW], int kg) {
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.Ab, static_cast<uint32_t>(RT) * KB * 64 * 16);
+    int soff[RPW];
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) av[r] = Aw[(static_cast<int64_t>(r) * KB + kg) * 64];
+    for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KB * 64 * 16);
+    auto load_a = [&](bf8 (&av)[RPW], int kg) {
+      const int vo = (kg * 64 + lane) * 16;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) av[r] = buf_load<bf8>(ra, vo, soff[r]);
     };
     auto load_b = [&](float (&bv)[CPW][8], int kg) {
       const int l0 = kg * 32 + 8 * (lane / 16);
-      int32_t g[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) g[j] = gtab[l0 + j];
+      for (int j = 0; j < 8; ++j) {
+        const int64_t off = tab.xoff[l0 + j];
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        const int cc = (ct0 + c) * 16 + lane % 16;
-        const bool okc = col0 + cc < a.ncols;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          bv[c][j] = (okc && g[j] >= 0) ? Xc[static_cast<int64_t>(g[j]) * a.ldx + cc] : 0.f;
+        for (int c = 0; c < CPW; ++c) bv[c][j] = xcol[c][off];
       }
     };
-    auto pack = [&](const float (&bv)[CPW][8], bf8 (&bp)[CPW]) {
+    // rounds the rows of step kg to bf16; padding rows (>= mcell) become 0
+    // here, at use, so that no wait is forced at the load
+    auto pack = [&](const float (&bv)[CPW][8], bf8 (&bp)[CPW], int kg) {
+      const int l0 = kg * 32 + 8 * (lane / 16);
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int j = 0; j < 8; ++j) bp[c][j] = static_cast<__bf16>(bv[c][j]);
+      if ((kg + 1) * 32 > MC) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (l0 + j >= MC) bp[c][j] = static_cast<__bf16>(0.f);
+      }
     };
     // Pipeline: the raw FP32 rows of step kg + 2 are in flight while step kg
     // multiplies; those of step kg + 1 are rounded to bf16 right after, so
@@ -184,7 +240,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     load_b(braw, 0);
     load_a(a0, 0);
     if (KB > 1) load_b(bnext, 1);
-    pack(braw, p0);
+    pack(braw, p0, 0);
 #pragma unroll 1
     for (int kg = 0; kg < KB; ++kg) {
       if (kg + 1 < KB) load_a(a1, kg + 1);
@@ -194,7 +250,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 #pragma unroll
         for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(a0[r], p0[c], acc[r][c]);
       if (kg + 1 < KB) {
-        pack(bnext, p0);
+        pack(bnext, p0, kg + 1);
 #pragma unroll
         for (int r = 0; r < RPW; ++r) a0[r] = a1[r];
 #pragma unroll
@@ -204,31 +260,51 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
       }
     }
   } else {
-    // A fragments of this wave: tile (rt0 + r, k step kg) at Aw[(r KS + kg) 64]
-    const T* Aw = a.A + static_cast<int64_t>(rt0) * KS * 64 + lane;
-    const T* Aiw = CPLX ? a.Ai + static_cast<int64_t>(rt0) * KS * 64 + lane : nullptr;
+    // A fragments of this wave: tile (rt0 + r, k step kg) at element
+    // ((rt0 + r) KS + kg) 64 + lane
     constexpr int RI = CPLX ? RPW : 1;
     constexpr int CI = CPLX ? CPW : 1;
+    const uint32_t abytes = static_cast<uint32_t>(RT) * KS * 64 * sizeof(T);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.A, abytes);
+    const __amdgpu_buffer_rsrc_t rai = make_rsrc(CPLX ? a.Ai : a.A, abytes);
+    int soff[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KS * 64 * static_cast<int>(sizeof(T)));
     auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
+      const int vo = (kg * 64 + lane) * static_cast<int>(sizeof(T));
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
-        av[r] = Aw[(static_cast<int64_t>(r) * KS + kg) * 64];
-        if constexpr (CPLX) avi[r] = Aiw[(static_cast<int64_t>(r) * KS + kg) * 64];
+        av[r] = buf_load<T>(ra, vo, soff[r]);
+        if constexpr (CPLX) avi[r] = buf_load<T>(rai, vo, soff[r]);
       }
     };
     auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
       const int l = kg * 4 + lane / 16;
-      const int64_t gn = l < MC ? gnode(l) : 0;
+      const int64_t off = tab.xoff[l];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        const int cc = (ct0 + c) * 16 + lane % 16;
-        const bool ok = l < MC && col0 + cc < a.ncols;
-        bv[c] = ok ? Xc[gn * a.ldx + cc] : T(0);
-        if constexpr (CPLX) bo[c] = ok ? Xc[gn * a.ldx + (cc ^ 1)] : T(0);
+        bv[c] = xcol[c][off];
+        // the partner (re <-> im) of column cc is cc ^ 1, one element away
+        if constexpr (CPLX) bo[c] = xcol[c][off + ((lane & 1) ? -1 : 1)];
       }
     };
-    auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bv)[CPW], const T (&bo)[CI]) {
-      T bs[CPW];
+    // padding rows (>= mcell) of step kg are zeroed here, at use, so that no
+    // wait is forced at the load
+    auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bin)[CPW], const T (&boin)[CI], int kg) {
+      T bv[CPW], bo[CI], bs[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        bv[c] = bin[c];
+        if constexpr (CPLX) bo[c] = boin[c];
+      }
+      if ((kg + 1) * 4 > MC) {
+        const bool ok = kg * 4 + lane / 16 < MC;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          bv[c] = ok ? bv[c] : T(0);
+          if constexpr (CPLX) bo[c] = ok ? bo[c] : T(0);
+        }
+      }
       if constexpr (CPLX) {
 #pragma unroll
         for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
@@ -249,10 +325,10 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     for (int kg = 0; kg < KS; kg += 2) {
       load_a(a1, ai1, kg + 1);
       if (kg + 2 < KS) load_b(b2, o2, kg + 2);
-      compute(a0, ai0, b0, o0);
+      compute(a0, ai0, b0, o0, kg);
       if (kg + 2 < KS) load_a(a0, ai0, kg + 2);
       if (kg + 3 < KS) load_b(b3, o3, kg + 3);
-      compute(a1, ai1, b1, o1);
+      compute(a1, ai1, b1, o1, kg + 1);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         b0[c] = b2[c];
@@ -311,11 +387,10 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     T vc[4], xk[4][CPW], xp[4][CPW];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = (rt0 + r) * 16 + Mma<T>::row(lane, i);
-      valid[i] = row < MC;
-      const int la = row % Q, lb = (row / Q) % Q, lc = row / (Q * Q);
-      own[i] = valid[i] && (la < P) && (lb < P) && (lc < P);
-      gn[i] = valid[i] ? gnode(row) : 0;
+      const int32_t g = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
+      valid[i] = g >= 0;
+      own[i] = valid[i] && (g & (1 << 30));
+      gn[i] = valid[i] ? (g & ((1 << 30) - 1)) : 0;
       vc[i] = own[i] ? a.alpha * (static_cast<T>(vd[gn[i]]) - a.c) : T(0);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -348,10 +423,10 @@ template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 
 template <int P, typename T, bool CPLX, int WAVES, int OCC, bool BF>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
-  __shared__ int32_t gtab[BF ? rows_padded<P>() : 1];
+  __shared__ RowTables<rows_padded<P>()> tab;
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, BF>(a, bid % E, (bid / E) * kNT, gtab);
+  cell_item<P, T, CPLX, WAVES, BF>(a, bid % E, (bid / E) * kNT, tab);
 }
 
 // Many problems in one persistent launch: the work list is the concatenation
@@ -365,6 +440,7 @@ template <int P, typename T, bool CPLX, int WAVES, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob,
                        const int contiguous) {
+  __shared__ RowTables<rows_padded<P>()> tab;
   const int64_t nitems = item_off[nprob];
   const int64_t G = gridDim.x;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -378,7 +454,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const HxArgs<T> d = descs[q];
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
-    cell_item<P, T, CPLX, WAVES, false>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, nullptr);
+    cell_item<P, T, CPLX, WAVES, false>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
   }
 }
 
