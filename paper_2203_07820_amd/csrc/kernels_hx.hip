@@ -373,42 +373,52 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     }
   }
 
-  // epilogue: scale, owner terms, atomic assembly.  Per row tile, the owner
-  // operands (potential, X_k, X_{k-1}) are loaded for all rows of the lane
-  // before any atomic is issued, so their latencies overlap.
+  // epilogue: scale, owner terms, atomic assembly.  Per row tile, every
+  // lane first loads its owner operands (potential, X_k, X_{k-1}) without
+  // branches, at addresses that are valid for every lane (padding rows read
+  // node 0, columns beyond ncols read column ncols - 1), so that the tile
+  // waits for memory once; the values of non-owner rows and padding are
+  // discarded by the selects, and only the stores and atomics are masked.
   const T* __restrict__ Xk = a.Xk;
   T* __restrict__ Xp = const_cast<T*>(a.Xp);
   T* __restrict__ Tg = a.Tg;
   const double* __restrict__ vd = a.vdiag;
+  const bool has_prev = Xp != nullptr;
+  int colc[CPW];
+  bool colok[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int col = col0 + (ct0 + c) * 16 + lane % 16;
+    colok[c] = col < a.ncols;
+    colc[c] = colok[c] ? col : a.ncols - 1;
+  }
 #pragma unroll
   for (int r = 0; r < RPW; ++r) {
+    int32_t g[4];
     int64_t gn[4];
-    bool valid[4], own[4];
-    T vc[4], xk[4][CPW], xp[4][CPW];
+    T vv[4], xk[4][CPW], xp[4][CPW];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int32_t g = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
-      valid[i] = g >= 0;
-      own[i] = valid[i] && (g & (1 << 30));
-      gn[i] = valid[i] ? (g & ((1 << 30) - 1)) : 0;
-      vc[i] = own[i] ? a.alpha * (static_cast<T>(vd[gn[i]]) - a.c) : T(0);
+      g[i] = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
+      gn[i] = g[i] >= 0 ? (g[i] & ((1 << 30) - 1)) : 0;
+      vv[i] = static_cast<T>(vd[gn[i]]);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        const int col = col0 + (ct0 + c) * 16 + lane % 16;
-        const bool ok = own[i] && col < a.ncols;
-        xk[i][c] = ok ? Xk[gn[i] * a.ldx + col] : T(0);
-        xp[i][c] = (ok && Xp != nullptr) ? Xp[gn[i] * a.ldp + col] : T(0);
+        xk[i][c] = Xk[gn[i] * a.ldx + colc[c]];
+        xp[i][c] = has_prev ? Xp[gn[i] * a.ldp + colc[c]] : T(0);
       }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      const bool valid = g[i] >= 0;
+      const bool own = valid && (g[i] & (1 << 30));
+      const T vc = own ? a.alpha * (vv[i] - a.c) : T(0);
+      const T bp = own ? a.beta : T(0);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        const int col = col0 + (ct0 + c) * 16 + lane % 16;
-        if (!valid[i] || col >= a.ncols) continue;
-        const T v = a.alpha * acc[r][c][i] + vc[i] * xk[i][c] - a.beta * xp[i][c];
-        if (own[i] && Xp != nullptr && a.zero_prev) Xp[gn[i] * a.ldp + col] = T(0);
-        atomic_add(Tg + gn[i] * a.ldt + col, v);
+        const T v = a.alpha * acc[r][c][i] + vc * xk[i][c] - bp * xp[i][c];
+        if (own && has_prev && a.zero_prev && colok[c]) Xp[gn[i] * a.ldp + colc[c]] = T(0);
+        if (valid && colok[c]) atomic_add(Tg + gn[i] * a.ldt + colc[c], v);
       }
     }
   }
