@@ -195,7 +195,7 @@ int chfsi_abi_sizes(int64_t* system, int64_t* params, int64_t* stats);
  * the projector tables (per atom node lists and per (cell, atom) cell
  * matrices split by node multiplicity).  Then uploads them.  The operator
  * keeps a pointer to ctx, which must outlive it.  CHFSI_EINVAL for p outside
- * [2, 7] or a mesh of 2^30 nodes or more.  Synchronous. */
+ * [2, 7] or a mesh of 2^29 nodes or more.  Synchronous. */
 int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
 int chfsi_op_destroy(chfsi_op* op);
 /* M nodes, E cells, mcell = (p+1)^3 nodes per cell, nproj = 4 * natoms (0

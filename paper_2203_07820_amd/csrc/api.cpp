@@ -873,7 +873,7 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   if (sys->p < kMinOrder || sys->p > kMaxOrder) return fail(ctx, CHFSI_EINVAL, "order p must be in [2, 7]");
   if (sys->ncell < 1 || !(sys->L > 0.0) || sys->natoms < 0) return fail(ctx, CHFSI_EINVAL, "bad mesh size");
   const int64_t n = static_cast<int64_t>(sys->ncell) * sys->p;
-  if (n * n * n >= (1LL << 30)) return fail(ctx, CHFSI_EINVAL, "mesh too large (node ids must stay below 2^30)");
+  if (n * n * n >= (1LL << 29)) return fail(ctx, CHFSI_EINVAL, "mesh too large (node ids must stay below 2^29)");
   if (sys->natoms > 0 && (!sys->pos || !sys->Z || !sys->s)) return fail(ctx, CHFSI_EINVAL, "null atom arrays");
   if (sys->has_proj && sys->natoms > 0 && (!sys->w || !sys->h_s || !sys->h_p))
     return fail(ctx, CHFSI_EINVAL, "null projector arrays");

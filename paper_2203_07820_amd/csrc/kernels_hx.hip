@@ -112,8 +112,9 @@ template <> __device__ __forceinline__ bf8 buf_load<bf8>(__amdgpu_buffer_rsrc_t 
 
 // Per-cell row tables in LDS, written once per work item: xoff[l] = element
 // offset of cell row l in X (node id * ldx; row 0's for padding rows) and
-// gid[l] = node id | owner << 30 (-1 for padding rows).  The owner of a node
-// is the cell in which its local indices are all < p.
+// gid[l] = node id | owner << 30 | interior << 29 (-1 for padding rows).  The
+// owner of a node is the cell in which its local indices are all < p; an
+// interior node (all local indices in [1, p-1]) belongs to this cell only.
 template <int MP> struct RowTables {
   int64_t xoff[MP];
   int32_t gid[MP];
@@ -172,7 +173,8 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
       int gz = cz * P + lc; if (gz >= n) gz -= n;
       const int32_t node = gx + n * (gy + n * gz);
       off = static_cast<int64_t>(node) * a.ldx;
-      g = node | ((la < P && lb < P && lc < P) ? (1 << 30) : 0);
+      const bool inner = la > 0 && la < P && lb > 0 && lb < P && lc > 0 && lc < P;
+      g = node | ((la < P && lb < P && lc < P) ? (1 << 30) : 0) | (inner ? (1 << 29) : 0);
     }
     tab.xoff[l] = off;
     tab.gid[l] = g;
@@ -400,7 +402,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       g[i] = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
-      gn[i] = g[i] >= 0 ? (g[i] & ((1 << 30) - 1)) : 0;
+      gn[i] = g[i] >= 0 ? (g[i] & ((1 << 29) - 1)) : 0;
       vv[i] = static_cast<T>(vd[gn[i]]);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -412,13 +414,17 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     for (int i = 0; i < 4; ++i) {
       const bool valid = g[i] >= 0;
       const bool own = valid && (g[i] & (1 << 30));
+      const bool inner = valid && (g[i] & (1 << 29));
       const T vc = own ? a.alpha * (vv[i] - a.c) : T(0);
       const T bp = own ? a.beta : T(0);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const T v = a.alpha * acc[r][c][i] + vc * xk[i][c] - bp * xp[i][c];
         if (own && has_prev && a.zero_prev && colok[c]) Xp[gn[i] * a.ldp + colc[c]] = T(0);
-        if (valid && colok[c]) atomic_add(Tg + gn[i] * a.ldt + colc[c], v);
+        // the target starts at zero and an interior node has no other
+        // contributor: a plain store is the sum
+        if (inner && colok[c]) Tg[gn[i] * a.ldt + colc[c]] = v;
+        else if (valid && colok[c]) atomic_add(Tg + gn[i] * a.ldt + colc[c], v);
       }
     }
   }
