@@ -377,10 +377,11 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 
   // epilogue: scale, owner terms, atomic assembly.  Per row tile, every
   // lane first loads its owner operands (potential, X_k, X_{k-1}) without
-  // branches, at addresses that are valid for every lane (padding rows read
-  // node 0, columns beyond ncols read column ncols - 1), so that the tile
-  // waits for memory once; the values of non-owner rows and padding are
-  // discarded by the selects, and only the stores and atomics are masked.
+  // branches, at addresses that are valid for every lane: rows this cell
+  // does not own (and padding rows) read node 0's row, which stays in cache,
+  // columns beyond ncols read column ncols - 1.  The tile then waits for
+  // memory once; the selects discard what non-owners read, and only the
+  // stores and atomics are masked.
   const T* __restrict__ Xk = a.Xk;
   T* __restrict__ Xp = const_cast<T*>(a.Xp);
   T* __restrict__ Tg = a.Tg;
@@ -403,11 +404,12 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     for (int i = 0; i < 4; ++i) {
       g[i] = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
       gn[i] = g[i] >= 0 ? (g[i] & ((1 << 29) - 1)) : 0;
-      vv[i] = static_cast<T>(vd[gn[i]]);
+      const int64_t go = (g[i] >= 0 && (g[i] & (1 << 30))) ? gn[i] : 0;   // owner rows only
+      vv[i] = static_cast<T>(vd[go]);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        xk[i][c] = Xk[gn[i] * a.ldx + colc[c]];
-        xp[i][c] = has_prev ? Xp[gn[i] * a.ldp + colc[c]] : T(0);
+        xk[i][c] = Xk[go * a.ldx + colc[c]];
+        xp[i][c] = has_prev ? Xp[go * a.ldp + colc[c]] : T(0);
       }
     }
 #pragma unroll
