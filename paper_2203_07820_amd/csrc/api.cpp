@@ -252,7 +252,7 @@ int gram(chfsi_op* op, const double* X, int64_t ldx, const double* Y, int64_t ld
   const int cf = op->t.cplx ? 2 : 1;
   const int n = static_cast<int>(N * cf);
   void *part, *G, *S;
-  CHECK(ws_get(ctx, WS_GPART, gram_partial_bytes(op->t.M, n), &part));
+  CHECK(ws_get(ctx, WS_GPART, gram_partial_bytes(op->t.M, n, std::max(ldx, ldy) * cf), &part));
   CHECK(ws_get(ctx, WS_G, static_cast<size_t>(n) * n * 8, &G));
   CHECK(ws_get(ctx, WS_S, static_cast<size_t>(N) * N * 8 * cf, &S));
   HIP_TRY(ctx, launch_gram(X, ldx * cf, Y, ldy * cf, op->t.M, n, static_cast<double*>(part),

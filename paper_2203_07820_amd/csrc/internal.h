@@ -126,7 +126,7 @@ hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, in
 // Dense FP64 kernels on real views.
 // Lower-triangular Gram G = X^T Y (n x n, real view) -> partial buffers then
 // reduced into G (row-major, ldg), upper triangle mirrored.
-size_t gram_partial_bytes(int64_t M, int n);
+size_t gram_partial_bytes(int64_t M, int n, int64_t ld);
 hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
                        double* partial, double* G, int64_t ldg, hipStream_t s);
 // C = X Z, X: M x K (ldx), Z: K x N2 row-major (ldz); upper = Z upper-triangular.

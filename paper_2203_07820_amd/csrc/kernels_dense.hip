@@ -23,14 +23,27 @@ __device__ __forceinline__ d4 mma(double a, double b, d4 c) {
 __device__ __forceinline__ int acc_row(int lane, int i) { return 4 * i + lane / 16; }
 
 // ---- Gram: partial[chunk] tile (I, J), I >= J, of X^T Y --------------------
+// One workgroup computes a 128 x 128 tile over the rows of one chunk; 4 waves
+// of 64 x 64 (4 x 4 MFMA tiles).  In a 4-row k step, lanes 16 q .. 16 q + 15
+// read 16 consecutive columns of row 4 s + q, which is both the A operand
+// (X^T) and the B operand (Y) layout of the f64 MFMA, so the fragments go
+// straight from memory into registers: buffer loads from the chunk's first
+// row, the row offset in the lane's voffset (clamped to the chunk, tail rows
+// zeroed at use), the four 16-column groups in the instruction offset.
+// Loads run two k steps ahead of the MFMAs; no LDS, no barriers.
 constexpr int kGT = 128;  // Gram tile
-constexpr int kGK = 16;   // rows per LDS stage
 
-__global__ void __launch_bounds__(256)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, bytes, 0x00020000);
+}
+template <int OFF>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff + OFF, 0, 0));
+}
+
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y, int64_t ldy,
             int64_t M, int n, int64_t rows_per_chunk, int npad, double* __restrict__ part) {
-  __shared__ double xs[kGK][kGT];
-  __shared__ double ys[kGK][kGT];
   const int t = blockIdx.x;
   // lower-triangular tile index -> (I, J)
   int I = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
@@ -41,6 +54,7 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
   const int64_t m0 = chunk * rows_per_chunk;
   int64_t m1 = m0 + rows_per_chunk;
   if (m1 > M) m1 = M;
+  const int nrows = static_cast<int>(m1 - m0);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wi = (wave / 2) * 64, wj = (wave % 2) * 64;
   d4 acc[4][4];
@@ -48,37 +62,55 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  const int lc = tid % kGT, lr = tid / kGT;  // loader: column, row phase (0..1)
-  const int gi = I * kGT + lc, gj = J * kGT + lc;
-  for (int64_t m = m0; m < m1; m += kGK) {
+  if (nrows <= 0) return;
+  // per-lane column of the first 16-column group (the others are +16 k).
+  // Columns at or beyond n belong to the tile's padding, which is never read
+  // back: what they load (the rest of the row, the next row, or zero past the
+  // end of the chunk, where the buffer range check returns 0) does not matter.
+  const int ci = I * kGT + wi + lane % 16;
+  const int cj = J * kGT + wj + lane % 16;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(X + m0 * ldx, static_cast<uint32_t>(nrows * ldx * 8));
+  const __amdgpu_buffer_rsrc_t ry = rsrc(Y + m0 * ldy, static_cast<uint32_t>(nrows * ldy * 8));
+  const int KS = (nrows + 3) / 4;
+  auto load = [&](double (&xv)[4], double (&yv)[4], int s) {
+    const int row = min(4 * s + lane / 16, nrows - 1);
+    const int vx = (row * static_cast<int>(ldx) + ci) * 8;
+    const int vy = (row * static_cast<int>(ldy) + cj) * 8;
+    xv[0] = bload<0>(rx, vx);
+    xv[1] = bload<128>(rx, vx);
+    xv[2] = bload<256>(rx, vx);
+    xv[3] = bload<384>(rx, vx);
+    yv[0] = bload<0>(ry, vy);
+    yv[1] = bload<128>(ry, vy);
+    yv[2] = bload<256>(ry, vy);
+    yv[3] = bload<384>(ry, vy);
+  };
+  auto compute = [&](const double (&xin)[4], const double (&yin)[4], int s) {
+    double xv[4], yv[4];
+    const bool ok = 4 * s + lane / 16 < nrows;
 #pragma unroll
-    for (int i = 0; i < kGK / 2; ++i) {
-      const int r = lr + 2 * i;
-      const int64_t row = m + r;
-      double xv = 0.0, yv = 0.0;
-      if (row < m1) {
-        if (gi < n) xv = X[row * ldx + gi];
-        if (gj < n) yv = Y[row * ldy + gj];
-      }
-      xs[r][lc] = xv;
-      ys[r][lc] = yv;
+    for (int a = 0; a < 4; ++a) {
+      xv[a] = ok ? xin[a] : 0.0;
+      yv[a] = ok ? yin[a] : 0.0;
     }
-    __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < kGK / 4; ++ks) {
-      const int kr = ks * 4 + lane / 16;
-      double av[4], bv[4];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        av[q] = xs[kr][wi + q * 16 + lane % 16];
-        bv[q] = ys[kr][wj + q * 16 + lane % 16];
-      }
+      for (int b = 0; b < 4; ++b) acc[a][b] = mma(xv[a], yv[b], acc[a][b]);
+  };
+  double x0[4], y0[4], x1[4], y1[4], x2[4], y2[4];
+  load(x0, y0, 0);
+  if (KS > 1) load(x1, y1, 1);
+  for (int s = 0; s < KS; ++s) {
+    if (s + 2 < KS) load(x2, y2, s + 2);
+    compute(x0, y0, s);
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mma(av[a], bv[b], acc[a][b]);
+    for (int a = 0; a < 4; ++a) {
+      x0[a] = x1[a];
+      y0[a] = y1[a];
+      x1[a] = x2[a];
+      y1[a] = y2[a];
     }
-    __syncthreads();
   }
   double* out = part + static_cast<int64_t>(chunk) * npad * npad;
 #pragma unroll
@@ -93,7 +125,6 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
       }
 }
 
-// G[i][j] = sum over chunks, for entries of lower tiles (tile(i) >= tile(j)).
 __global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks, int n, int npad,
                                    double* __restrict__ G, int64_t ldg) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -140,56 +171,105 @@ __global__ void gram_combine_complex_kernel(const double* __restrict__ G, int64_
 }
 
 // ---- rotation C = X Z --------------------------------------------------------
+// Workgroup tile 64 rows x 128 columns, 4 waves of 32 x 64 (2 x 4 MFMA tiles).
+// X rows are staged through LDS (the A operand needs 16 rows per fragment),
+// Z through LDS as well; both double buffered, with the next 16-deep k chunk
+// loaded into registers from global memory while the current one multiplies,
+// so there is one barrier per chunk and the global latency overlaps the
+// MFMAs.  upper: Z is upper triangular, k stops at the tile's last column.
 constexpr int kRM = 64;   // rows per workgroup
 constexpr int kRN = 128;  // columns per workgroup
-constexpr int kRK = 16;   // k per LDS stage
+constexpr int kRK = 16;   // k per stage
+constexpr int kZP = kRN + 8;  // padded LDS row of the Z stage
 
-__global__ void __launch_bounds__(256)
+__global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Z, int64_t ldz,
               double* __restrict__ C, int64_t ldc, int64_t M, int K, int N2, int upper) {
-  __shared__ double xs[kRM][kRK + 1];
-  __shared__ double zs[kRK][kRN];
+  __shared__ double xs[2][kRM][kRK + 1];
+  __shared__ double zs[2][kRK][kZP];
   const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRM);
   const int c0 = blockIdx.y * kRN;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  d4 acc[8];
+  const int wr = (wave / 2) * 32, wc = (wave % 2) * 64;
+  d4 acc[2][4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = d4{0, 0, 0, 0};
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
   int kend = K;
   if (upper && c0 + kRN < kend) kend = c0 + kRN;
-  const int xk = tid % kRK, xr = tid / kRK;        // X loader: 16 k x 16 rows per pass
-  const int zc = tid % kRN, zr = tid / kRN;        // Z loader: 128 cols x 2 rows per pass
-  for (int k0 = 0; k0 < kend; k0 += kRK) {
-#pragma unroll
-    for (int i = 0; i < kRM / 16; ++i) {
-      const int r = xr + 16 * i;
-      const int64_t row = r0 + r;
-      const int k = k0 + xk;
-      xs[r][xk] = (row < M && k < K) ? X[row * ldx + k] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < kRK / 2; ++i) {
-      const int r = zr + 2 * i;
-      const int k = k0 + r, c = c0 + zc;
-      zs[r][zc] = (k < K && c < N2) ? Z[static_cast<int64_t>(k) * ldz + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kRK / 4; ++ks) {
-      const double av = xs[wave * 16 + lane % 16][ks * 4 + lane / 16];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = mma(av, zs[ks * 4 + lane / 16][q * 16 + lane % 16], acc[q]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < 8; ++q)
+  // loaders: X 64 rows x 16 k (4 per thread, 16 threads per row), Z 16 k x
+  // 128 columns (8 per thread, one row per 128 threads); addresses clamped,
+  // out-of-range values zeroed when stored to LDS
+  const int xk = tid % kRK, xr = tid / kRK;
+  const int zc = tid % kRN, zr = tid / kRN;
+  double gx[4], gz[8];
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t row = r0 + wave * 16 + acc_row(lane, i);
-      const int col = c0 + q * 16 + lane % 16;
-      if (row < M && col < N2) C[row * ldc + col] = acc[q][i];
+      int64_t row = r0 + xr + 16 * i;
+      row = row < M ? row : M - 1;
+      int k = k0 + xk;
+      k = k < K ? k : K - 1;
+      gx[i] = X[row * ldx + k];
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      int k = k0 + zr + 2 * i;
+      k = k < K ? k : K - 1;
+      int c = c0 + zc;
+      c = c < N2 ? c : N2 - 1;
+      gz[i] = Z[static_cast<int64_t>(k) * ldz + c];
+    }
+  };
+  auto sstore = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool ok = r0 + xr + 16 * i < M && k0 + xk < K;
+      xs[buf][xr + 16 * i][xk] = ok ? gx[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool ok = k0 + zr + 2 * i < K && c0 + zc < N2;
+      zs[buf][zr + 2 * i][zc] = ok ? gz[i] : 0.0;
+    }
+  };
+  if (kend > 0) {
+    gload(0);
+    sstore(0, 0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < kend; k0 += kRK) {
+    const bool more = k0 + kRK < kend;
+    if (more) gload(k0 + kRK);
+#pragma unroll
+    for (int ks = 0; ks < kRK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double av[2], bv[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = xs[buf][wr + a * 16 + lane % 16][kr];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = zs[buf][kr][wc + b * 16 + lane % 16];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mma(av[a], bv[b], acc[a][b]);
+    }
+    if (more) sstore(buf ^ 1, k0 + kRK);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = r0 + wr + a * 16 + acc_row(lane, i);
+        const int col = c0 + wc + b * 16 + lane % 16;
+        if (row < M && col < N2) C[row * ldc + col] = acc[a][b][i];
+      }
 }
 
 // ---- residual column sums ------------------------------------------------
@@ -298,21 +378,27 @@ unsigned blocks_for(int64_t total, int per = 256) {
   return static_cast<unsigned>((total + per - 1) / per);
 }
 
-int gram_chunks(int64_t M, int n) {
+// Row chunks of the Gram products: about 1024 workgroups in all, at least
+// 256 rows per chunk, and few enough rows that a chunk of the widest operand
+// (ld doubles per row) spans less than 2^31 bytes (32-bit buffer offsets).
+int gram_chunks(int64_t M, int n, int64_t ld) {
   const int nt = (n + kGT - 1) / kGT;
   const int ntiles = nt * (nt + 1) / 2;
   int64_t ch = (1024 + ntiles - 1) / ntiles;
-  const int64_t max_ch = (M + 255) / 256;  // at least 256 rows per chunk
+  const int64_t max_ch = (M + 255) / 256;
   if (ch > max_ch) ch = max_ch;
+  const int64_t max_rows = ((int64_t{1} << 31) - 1) / (8 * (ld > 0 ? ld : 1)) - 16;
+  const int64_t min_ch = max_rows > 0 ? (M + max_rows - 1) / max_rows : M;
+  if (ch < min_ch) ch = min_ch;
   if (ch < 1) ch = 1;
   return static_cast<int>(ch);
 }
 
 }  // namespace
 
-size_t gram_partial_bytes(int64_t M, int n) {
+size_t gram_partial_bytes(int64_t M, int n, int64_t ld) {
   const int npad = (n + kGT - 1) / kGT * kGT;
-  return static_cast<size_t>(gram_chunks(M, n)) * npad * npad * sizeof(double);
+  return static_cast<size_t>(gram_chunks(M, n, ld)) * npad * npad * sizeof(double);
 }
 
 hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
@@ -321,9 +407,9 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ld
   const int nt = (n + kGT - 1) / kGT;
   const int ntiles = nt * (nt + 1) / 2;
   const int npad = nt * kGT;
-  const int nch = gram_chunks(M, n);
+  const int nch = gram_chunks(M, n, ldx > ldy ? ldx : ldy);
   int64_t rpc = (M + nch - 1) / nch;
-  rpc = (rpc + kGK - 1) / kGK * kGK;
+  rpc = (rpc + 15) / 16 * 16;
   hipLaunchKernelGGL(gram_kernel, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
                      partial, nch, n, npad, G, ldg);

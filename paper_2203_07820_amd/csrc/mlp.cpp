@@ -351,7 +351,7 @@ int chfsi_initial_block(chfsi_op* op, chfsi_mlp* net, uint64_t seed, void* Xv, i
       // overlap matrix must be positive definite (Cholesky of X^T X)
       const int nc = static_cast<int>(ncols);
       void *part, *G, *S, *info;
-      CHECK(ws_get(c, WS_GPART, gram_partial_bytes(M, nc), &part));
+      CHECK(ws_get(c, WS_GPART, gram_partial_bytes(M, nc, ld), &part));
       CHECK(ws_get(c, WS_G, static_cast<size_t>(nc) * nc * 8, &G));
       CHECK(ws_get(c, WS_S, static_cast<size_t>(nc) * nc * 8, &S));
       CHECK(ws_get(c, WS_INFO, 64, &info));

@@ -170,6 +170,28 @@ def test_orthonormalize_matches_oracle(ctx, case):
     assert relerr(L, Lref) < 1e-12
 
 
+@pytest.mark.parametrize("k", [(0, 0, 0), (0.1, -0.2, 0.15)])
+def test_subspace_kernels_multi_tile(ctx, k):
+    # 200 columns (400 in the real view of a complex block): several
+    # 128-wide Gram tiles, two or more rotation column blocks, the triangular
+    # cut-off of X L^-H, and an odd row count (15^3 = 3375) that leaves a
+    # ragged last k step
+    s = workloads.small_system(3, 5, 2, seed=21, has_proj=True, k=k)
+    op = lib.Operator(ctx, s)
+    N = 200
+    X = workloads.start_block(op.M, N, seed=22, complex_=op.is_complex)
+    Xo, Lref, _ = ochfsi.cholgs(X)
+    Xd = dev(X)
+    L = op.orthonormalize(Xd, want_L=True)
+    assert relerr(host(Xd), Xo) < 1e-11
+    assert relerr(L, Lref) < 1e-11
+    H = fe.assemble(fe.build_operator(s))
+    th_ref, Psi_ref, _, r_ref, _ = ochfsi.rayleigh_ritz(lambda v: H @ v, Xo)
+    th, r = op.rayleigh_ritz(Xd)
+    assert np.max(np.abs(th - th_ref)) < 1e-10 * max(1.0, np.max(np.abs(th_ref)))
+    assert np.max(np.abs(r - r_ref)) < 1e-9
+
+
 def test_orthonormalize_rank_deficient_fails(ctx):
     s = _sys(*SMALL[1])
     op = lib.Operator(ctx, s)
