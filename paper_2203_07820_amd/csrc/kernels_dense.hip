@@ -62,16 +62,16 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
-  if (nrows <= 0) return;
   // per-lane column of the first 16-column group (the others are +16 k).
   // Columns at or beyond n belong to the tile's padding, which is never read
   // back: what they load (the rest of the row, the next row, or zero past the
   // end of the chunk, where the buffer range check returns 0) does not matter.
   const int ci = I * kGT + wi + lane % 16;
   const int cj = J * kGT + wj + lane % 16;
-  const __amdgpu_buffer_rsrc_t rx = rsrc(X + m0 * ldx, static_cast<uint32_t>(nrows * ldx * 8));
-  const __amdgpu_buffer_rsrc_t ry = rsrc(Y + m0 * ldy, static_cast<uint32_t>(nrows * ldy * 8));
-  const int KS = (nrows + 3) / 4;
+  const int64_t nr = nrows > 0 ? nrows : 0;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(X + (nr > 0 ? m0 * ldx : 0), static_cast<uint32_t>(nr * ldx * 8));
+  const __amdgpu_buffer_rsrc_t ry = rsrc(Y + (nr > 0 ? m0 * ldy : 0), static_cast<uint32_t>(nr * ldy * 8));
+  const int KS = nrows > 0 ? (nrows + 3) / 4 : 0;   // every chunk still writes its tile
   auto load = [&](double (&xv)[4], double (&yv)[4], int s) {
     const int row = min(4 * s + lane / 16, nrows - 1);
     const int vx = (row * static_cast<int>(ldx) + ci) * 8;
@@ -99,7 +99,7 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
       for (int b = 0; b < 4; ++b) acc[a][b] = mma(xv[a], yv[b], acc[a][b]);
   };
   double x0[4], y0[4], x1[4], y1[4], x2[4], y2[4];
-  load(x0, y0, 0);
+  if (KS > 0) load(x0, y0, 0);
   if (KS > 1) load(x1, y1, 1);
   for (int s = 0; s < KS; ++s) {
     if (s + 2 < KS) load(x2, y2, s + 2);
@@ -407,9 +407,10 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ld
   const int nt = (n + kGT - 1) / kGT;
   const int ntiles = nt * (nt + 1) / 2;
   const int npad = nt * kGT;
-  const int nch = gram_chunks(M, n, ldx > ldy ? ldx : ldy);
+  int nch = gram_chunks(M, n, ldx > ldy ? ldx : ldy);
   int64_t rpc = (M + nch - 1) / nch;
   rpc = (rpc + 15) / 16 * 16;
+  nch = static_cast<int>((M + rpc - 1) / rpc);   // rounding rpc up can leave trailing chunks empty
   hipLaunchKernelGGL(gram_kernel, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
                      partial, nch, n, npad, G, ldg);

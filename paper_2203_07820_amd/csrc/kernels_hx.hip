@@ -12,7 +12,7 @@
 //      X' is X with (re, im) -> (-im, re);
 //   3. adds the nonlocal term C^{c,a} (h P_a) for every atom a whose
 //      projectors touch the cell, as extra 4-wide k steps (Algorithm 4 steps
-//      5-6, with P_a from the node-level contraction below);
+//      5-6, with P_a from the node-level contraction of kernels_nl.hip);
 //   4. scatters alpha * Y^c into the target with atomic adds (ASEMB_FEM).
 //      The owner cell of each node (local indices all < p) also adds
 //      alpha (V_j - c) X_k[j] - beta X_{k-1}[j], so the target ends up holding
@@ -115,9 +115,10 @@ template <> __device__ __forceinline__ bf8 buf_load<bf8>(__amdgpu_buffer_rsrc_t 
 // gid[l] = node id | owner << 30 | interior << 29 (-1 for padding rows).  The
 // owner of a node is the cell in which its local indices are all < p; an
 // interior node (all local indices in [1, p-1]) belongs to this cell only.
-template <int MP> struct RowTables {
+template <int MP, typename T> struct RowTables {
   int64_t xoff[MP];
   int32_t gid[MP];
+  T wv[MP];     // alpha (V_j - c) for owned rows, 0 otherwise
 };
 
 // One work item: cell `cell`, columns [col0, col0 + 64).
@@ -141,7 +142,7 @@ template <int MP> struct RowTables {
 // in registers.
 template <int P, typename T, bool CPLX, int WAVES, bool BF>
 __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
-                                          RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16)>& tab) {
+                                          RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
   constexpr int MP = (MC + 15) / 16 * 16;
@@ -166,6 +167,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   for (int l = tid; l < MP; l += 64 * WAVES) {
     int32_t g = -1;
     int64_t off = 0;
+    T w = T(0);
     if (l < MC) {
       const int la = l % Q, lb = (l / Q) % Q, lc = l / (Q * Q);
       int gx = cx * P + la; if (gx >= n) gx -= n;
@@ -174,10 +176,13 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
       const int32_t node = gx + n * (gy + n * gz);
       off = static_cast<int64_t>(node) * a.ldx;
       const bool inner = la > 0 && la < P && lb > 0 && lb < P && lc > 0 && lc < P;
-      g = node | ((la < P && lb < P && lc < P) ? (1 << 30) : 0) | (inner ? (1 << 29) : 0);
+      const bool owner = la < P && lb < P && lc < P;
+      g = node | (owner ? (1 << 30) : 0) | (inner ? (1 << 29) : 0);
+      if (owner) w = a.alpha * (static_cast<T>(a.vdiag[node]) - a.c);
     }
     tab.xoff[l] = off;
     tab.gid[l] = g;
+    tab.wv[l] = w;
   }
   __syncthreads();
 
@@ -376,16 +381,16 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   }
 
   // epilogue: scale, owner terms, atomic assembly.  Per row tile, every
-  // lane first loads its owner operands (potential, X_k, X_{k-1}) without
-  // branches, at addresses that are valid for every lane: rows this cell
-  // does not own (and padding rows) read node 0's row, which stays in cache,
-  // columns beyond ncols read column ncols - 1.  The tile then waits for
-  // memory once; the selects discard what non-owners read, and only the
-  // stores and atomics are masked.
+  // lane loads its owner operands (X_k, X_{k-1}) without branches, at
+  // addresses that are valid for every lane: rows this cell does not own (and
+  // padding rows) read node 0's row, which stays in cache, columns beyond
+  // ncols read column ncols - 1.  The loads of tile r + 1 are issued before
+  // the stores and atomics of tile r, so that their latency overlaps; the
+  // selects discard what non-owners read, and only stores and atomics are
+  // masked.  alpha (V - c) of owned rows comes from the LDS table.
   const T* __restrict__ Xk = a.Xk;
   T* __restrict__ Xp = const_cast<T*>(a.Xp);
   T* __restrict__ Tg = a.Tg;
-  const double* __restrict__ vd = a.vdiag;
   const bool has_prev = Xp != nullptr;
   int colc[CPW];
   bool colok[CPW];
@@ -395,39 +400,61 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     colok[c] = col < a.ncols;
     colc[c] = colok[c] ? col : a.ncols - 1;
   }
+  // stages of SR of the 4 accumulator rows of each lane: half a row tile for
+  // 8-byte values (whole tiles would not fit next to the FP64 accumulators),
+  // a whole tile for 4-byte values
+  constexpr int SR = sizeof(T) == 8 ? 2 : 4;
+  struct Ops {
+    int32_t g[SR];
+    T xk[SR][CPW], xp[SR][CPW];
+  };
+  auto fetch = [&](int h, Ops& o) {
+    const int r = h / (4 / SR);
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    int32_t g[4];
-    int64_t gn[4];
-    T vv[4], xk[4][CPW], xp[4][CPW];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      g[i] = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
-      gn[i] = g[i] >= 0 ? (g[i] & ((1 << 29) - 1)) : 0;
-      const int64_t go = (g[i] >= 0 && (g[i] & (1 << 30))) ? gn[i] : 0;   // owner rows only
-      vv[i] = static_cast<T>(vd[go]);
+    for (int k = 0; k < SR; ++k) {
+      const int i = (h % (4 / SR)) * SR + k;
+      o.g[k] = tab.gid[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
+      const int64_t go = (o.g[k] >= 0 && (o.g[k] & (1 << 30))) ? (o.g[k] & ((1 << 29) - 1)) : 0;
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        xk[i][c] = Xk[go * a.ldx + colc[c]];
-        xp[i][c] = has_prev ? Xp[go * a.ldp + colc[c]] : T(0);
+        o.xk[k][c] = Xk[go * a.ldx + colc[c]];
+        o.xp[k][c] = has_prev ? Xp[go * a.ldp + colc[c]] : T(0);
       }
     }
+  };
+  auto finish = [&](int h, const Ops& o) {
+    const int r = h / (4 / SR);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool valid = g[i] >= 0;
-      const bool own = valid && (g[i] & (1 << 30));
-      const bool inner = valid && (g[i] & (1 << 29));
-      const T vc = own ? a.alpha * (vv[i] - a.c) : T(0);
+    for (int k = 0; k < SR; ++k) {
+      const int i = (h % (4 / SR)) * SR + k;
+      const int32_t g = o.g[k];
+      const bool valid = g >= 0;
+      const bool own = valid && (g & (1 << 30));
+      const bool inner = valid && (g & (1 << 29));
+      const int64_t gn = valid ? (g & ((1 << 29) - 1)) : 0;
+      const T vc = tab.wv[(rt0 + r) * 16 + Mma<T>::row(lane, i)];
       const T bp = own ? a.beta : T(0);
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
-        const T v = a.alpha * acc[r][c][i] + vc * xk[i][c] - bp * xp[i][c];
-        if (own && has_prev && a.zero_prev && colok[c]) Xp[gn[i] * a.ldp + colc[c]] = T(0);
+        const T v = a.alpha * acc[r][c][i] + vc * o.xk[k][c] - bp * o.xp[k][c];
+        if (own && has_prev && a.zero_prev && colok[c]) Xp[gn * a.ldp + colc[c]] = T(0);
         // the target starts at zero and an interior node has no other
         // contributor: a plain store is the sum
-        if (inner && colok[c]) Tg[gn[i] * a.ldt + colc[c]] = v;
-        else if (valid && colok[c]) atomic_add(Tg + gn[i] * a.ldt + colc[c], v);
+        if (inner && colok[c]) Tg[gn * a.ldt + colc[c]] = v;
+        else if (valid && colok[c]) atomic_add(Tg + gn * a.ldt + colc[c], v);
       }
+    }
+  };
+  constexpr int NH = (4 / SR) * RPW;   // stages (odd when SR = 4 and RPW is odd)
+  Ops o0, o1;
+  fetch(0, o0);
+#pragma unroll
+  for (int h = 0; h < NH; h += 2) {
+    if (h + 1 < NH) fetch(h + 1, o1);
+    finish(h, o0);
+    if (h + 1 < NH) {
+      if (h + 2 < NH) fetch(h + 2, o0);
+      finish(h + 1, o1);
     }
   }
 }
@@ -441,7 +468,7 @@ template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 
 template <int P, typename T, bool CPLX, int WAVES, int OCC, bool BF>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
-  __shared__ RowTables<rows_padded<P>()> tab;
+  __shared__ RowTables<rows_padded<P>(), T> tab;
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   cell_item<P, T, CPLX, WAVES, BF>(a, bid % E, (bid / E) * kNT, tab);
@@ -458,7 +485,7 @@ template <int P, typename T, bool CPLX, int WAVES, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob,
                        const int contiguous) {
-  __shared__ RowTables<rows_padded<P>()> tab;
+  __shared__ RowTables<rows_padded<P>(), T> tab;
   const int64_t nitems = item_off[nprob];
   const int64_t G = gridDim.x;
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -540,127 +567,6 @@ hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
   }
 }
 
-// ---- node-level projector contraction (Algorithm 4 steps 1-4) -------------
-// P_a = h_a * sum_j conj(c~_{a,j}) X[j, :], computed from atom-major node
-// lists (each node row read once per atom), in two deterministic phases:
-// fixed-size chunks of an atom's list give partial sums, then the chunks of
-// each atom are summed in order and scaled by the couplings.
-constexpr int kNlChunk = 512;
-
-template <typename T, bool CPLX>
-__global__ void __launch_bounds__(256)
-nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const int64_t* atom_ptr,
-                  const int32_t* atom_node, const double* atom_val, const T* X, int64_t ldx,
-                  int ncols, T* partial, int64_t ldhp) {
-  __shared__ T red[4][CPLX ? 8 : 4][64];
-  const int chunk = blockIdx.x;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int col = blockIdx.y * 64 + lane;  // logical column
-  const int at = chunk_atom[chunk];
-  const int64_t e0 = chunk_begin[chunk];
-  int64_t e1 = e0 + kNlChunk;
-  if (e1 > atom_ptr[at + 1]) e1 = atom_ptr[at + 1];
-  constexpr int NV = CPLX ? 8 : 4;
-  T acc[NV];
-#pragma unroll
-  for (int m = 0; m < NV; ++m) acc[m] = T(0);
-  if (col < ncols) {
-    for (int64_t e = e0 + wave; e < e1; e += 4) {
-      const int64_t j = atom_node[e];
-      const double* v = atom_val + e * NV;
-      if constexpr (CPLX) {
-        const T xr = X[(j * ldx + col) * 2], xi = X[(j * ldx + col) * 2 + 1];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const T cr = static_cast<T>(v[2 * m]), ci = static_cast<T>(v[2 * m + 1]);
-          acc[2 * m] += cr * xr + ci * xi;       // conj(c) x, real part
-          acc[2 * m + 1] += cr * xi - ci * xr;   // imaginary part
-        }
-      } else {
-        const T x = X[j * ldx + col];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] += static_cast<T>(v[m]) * x;
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < NV; ++m) red[wave][m][lane] = acc[m];
-  __syncthreads();
-  if (wave == 0 && col < ncols) {
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
-      const T s = ((red[0][m][lane] + red[1][m][lane]) + red[2][m][lane]) + red[3][m][lane];
-      if constexpr (CPLX) {
-        partial[(static_cast<int64_t>(chunk) * 4 + m / 2) * ldhp + 2 * col + (m & 1)] = s;
-      } else {
-        partial[(static_cast<int64_t>(chunk) * 4 + m) * ldhp + col] = s;
-      }
-    }
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* partial, T* hP,
-                 int64_t ldhp, int nreal) {
-  const int am = blockIdx.x;  // atom * 4 + component
-  const int at = am / 4, m = am % 4;
-  const int j = blockIdx.y * 256 + threadIdx.x;
-  if (j >= ldhp) return;
-  T s = T(0);
-  if (j < nreal) {
-    for (int ch = atom_chunk_ptr[at]; ch < atom_chunk_ptr[at + 1]; ++ch)
-      s += partial[(static_cast<int64_t>(ch) * 4 + m) * ldhp + j];
-    s *= static_cast<T>(hcoef[am]);
-  }
-  hP[static_cast<int64_t>(am) * ldhp + j] = s;
-}
-
-template <typename T, bool CPLX>
-hipError_t nl_launch(const NlLaunch& L, hipStream_t s) {
-  if (L.nchunks <= 0) return hipSuccess;
-  const int nct = (L.ncols + 63) / 64;
-  hipLaunchKernelGGL((nl_partial_kernel<T, CPLX>), dim3(L.nchunks, nct), dim3(256), 0, s,
-                     L.chunk_atom, L.chunk_begin, L.atom_ptr, L.atom_node, L.atom_val,
-                     static_cast<const T*>(L.X), L.ldx, L.ncols, static_cast<T*>(L.partial), L.ldhp);
-  const int nreal = CPLX ? 2 * L.ncols : L.ncols;
-  hipLaunchKernelGGL((nl_reduce_kernel<T>), dim3(L.natoms * 4, (L.ldhp + 255) / 256), dim3(256), 0, s,
-                     L.atom_chunk_ptr, L.hcoef, static_cast<const T*>(L.partial), static_cast<T*>(L.hP),
-                     L.ldhp, nreal);
-  return hipGetLastError();
-}
-
-// ---- elementwise helpers ----------------------------------------------------
-template <typename T>
-__global__ void fill_kernel(T* dst, int64_t rows, int64_t cols, int64_t ld) {
-  const int64_t total = rows * cols;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t r = i / cols, c = i % cols;
-    dst[r * ld + c] = T(0);
-  }
-}
-
-template <typename TD, typename TS>
-__global__ void convert_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds, int64_t rows,
-                               int64_t cols) {
-  const int64_t total = rows * cols;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t r = i / cols, c = i % cols;
-    dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
-  }
-}
-
-inline bool is_double(int prec) { return prec == CHFSI_F64 || prec == CHFSI_C128; }
-
-unsigned grid_for(int64_t total) {
-  int64_t g = (total + 255) / 256;
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  return static_cast<unsigned>(g);
-}
-
 }  // namespace
 
 template <int P, typename T, bool CPLX>
@@ -724,47 +630,6 @@ hipError_t launch_cell_hx(const HxLaunch& L, int prec, hipStream_t s) {
     case CHFSI_C64: return launch_t<float, true, false>(L, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_nl_project(const NlLaunch& L, int prec, hipStream_t s) {
-  switch (prec) {
-    case CHFSI_F64: return nl_launch<double, false>(L, s);
-    case CHFSI_F32:
-    case CHFSI_BF16: return nl_launch<float, false>(L, s);
-    case CHFSI_C128: return nl_launch<double, true>(L, s);
-    case CHFSI_C64: return nl_launch<float, true>(L, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  const unsigned g = grid_for(rows * cols);
-  if (is_double(prec))
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(dst), rows, cols, ld);
-  else
-    hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(dst), rows, cols, ld);
-  return hipGetLastError();
-}
-
-hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, int64_t lds, int sprec,
-                          int64_t rows, int64_t cols, hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  const unsigned g = grid_for(rows * cols);
-  const bool dd = is_double(dprec), sd = is_double(sprec);
-  if (dd && sd)
-    hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
-                       static_cast<const double*>(src), lds, rows, cols);
-  else if (dd && !sd)
-    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
-                       static_cast<const float*>(src), lds, rows, cols);
-  else if (!dd && sd)
-    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
-                       static_cast<const double*>(src), lds, rows, cols);
-  else
-    hipLaunchKernelGGL((convert_kernel<float, float>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
-                       static_cast<const float*>(src), lds, rows, cols);
-  return hipGetLastError();
 }
 
 }  // namespace chfsi

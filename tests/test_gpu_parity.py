@@ -192,6 +192,20 @@ def test_subspace_kernels_multi_tile(ctx, k):
     assert np.max(np.abs(r - r_ref)) < 1e-9
 
 
+def test_orthonormalize_with_trailing_gram_chunks(ctx):
+    # M = 45^3 = 91,125 rows and 200 columns: 342 row chunks of 272 rows
+    # would cover more than M, so the launch must not leave chunks (and their
+    # partial tiles) empty
+    s = workloads.small_system(15, 3, 2, seed=23)
+    op = lib.Operator(ctx, s)
+    X = workloads.start_block(op.M, 200, seed=24)
+    Xo, Lref, _ = ochfsi.cholgs(X)
+    Xd = dev(X)
+    L = op.orthonormalize(Xd, want_L=True)
+    assert relerr(L, Lref) < 1e-11
+    assert relerr(host(Xd), Xo) < 1e-10
+
+
 def test_orthonormalize_rank_deficient_fails(ctx):
     s = _sys(*SMALL[1])
     op = lib.Operator(ctx, s)
