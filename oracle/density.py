@@ -8,6 +8,10 @@ computation algorithm, and the Fermi-Dirac occupations of Section 2.1):
 * Occupations f_i = 1 / (1 + exp((theta_i - mu) / kT)) of the Ritz values,
   with the Fermi level mu fixed by the electron count,
   2 sum_i w_i f_i = N_e (spin factor 2, optional k-point weights w_i).
+* The density at the (p+1)^3 Gauss-Legendre points of every cell (the
+  algorithm evaluates it inside each cell through the cell's FE basis
+  functions): psi^ restricted to the cell is interpolated with the
+  tensor-product Lagrange basis on the GLL nodes, then squared and weighted.
 * The density at a node x_j of the spectral mesh.  The FE basis function of
   node j is 1 at x_j and 0 at every other node, so n(x_j) = e_j and the
   density algorithm reduces to
@@ -23,6 +27,8 @@ from __future__ import annotations
 from typing import Optional
 
 import numpy as np
+
+from . import fe
 
 
 def occupations(theta: np.ndarray, mu: float, kT: float) -> np.ndarray:
@@ -66,3 +72,30 @@ def density(Psi: np.ndarray, w: np.ndarray, Mdiag: np.ndarray) -> np.ndarray:
     Psi = np.asarray(Psi)
     s = (np.abs(Psi) ** 2) @ np.asarray(w, dtype=np.float64)
     return s / np.asarray(Mdiag, dtype=np.float64)
+
+
+def density_gauss_cell(p: int, Ph_e: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """rho at the (p+1)^3 Gauss points of one cell from the cell's scaled
+    nodal values Ph_e (mcell x ncols, psi^ = M^-1/2 psi~, local node order
+    a + (p+1)(b + (p+1) c)).  Point order qx + (p+1)(qy + (p+1) qz)."""
+    xi, _ = fe.gll(p)
+    gq, _ = fe.gauss_legendre(p + 1)
+    L1, _ = fe.lagrange(xi, gq)          # L1[q, a] = l_a(g_q)
+    N = fe.kron3(L1, L1, L1)              # N[point, node]
+    vals = N @ Ph_e
+    return (np.abs(vals) ** 2) @ np.asarray(w, dtype=np.float64)
+
+
+def density_gauss(ncell: int, p: int, L: float, Psi: np.ndarray, w: np.ndarray,
+                  cells: Optional[np.ndarray] = None) -> np.ndarray:
+    """rho[e, point] for the listed cells (default all), cell id
+    cx + ncell (cy + ncell cz)."""
+    Mdiag = fe.lumped_mass(ncell, p, L)
+    D = 1.0 / np.sqrt(Mdiag)
+    nodes = fe.cell_nodes(ncell, p)
+    ids = np.arange(nodes.shape[0]) if cells is None else np.asarray(cells)
+    out = np.empty((ids.size, (p + 1) ** 3))
+    for i, e in enumerate(ids):
+        rows = nodes[e]
+        out[i] = density_gauss_cell(p, D[rows, None] * Psi[rows], w)
+    return out

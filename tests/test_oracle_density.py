@@ -77,3 +77,63 @@ def test_fermi_level_limits_and_closed_form():
     w = np.array([0.25, 0.25, 0.25, 0.25, 0.25])
     mu3 = dens.fermi_level(th, 1.0, 0.01, weights=w)
     assert abs(dens.electron_count(th, mu3, 0.01, weights=w) - 1.0) < 1e-12
+
+
+def test_gauss_density_free_electron_is_uniform():
+    for (nc, p, L) in ((2, 4, 5.0), (3, 2, 4.0)):
+        s = workloads.small_system(nc, p, 0, seed=2, L=L)
+        op, th, Psi = _eig(s, 1)
+        rho = dens.density_gauss(nc, p, L, Psi, np.array([2.0]))
+        assert rho.shape == (nc ** 3, (p + 1) ** 3)
+        assert np.max(np.abs(rho - 2.0 / L ** 3)) < 1e-10 * (2.0 / L ** 3)
+
+
+def test_gauss_density_reproduces_cell_polynomials():
+    # psi^ = g at the nodes with g a polynomial of degree <= p per axis: inside
+    # every cell that does not wrap around the periodic box the interpolant is
+    # g itself, so rho at the Gauss points equals w g(x_q)^2 (an anisotropic g
+    # catches a transposed point order)
+    nc, p, L = 3, 3, 6.0
+    h = L / nc
+    X = fe.node_coords(nc, p, L)
+    g = lambda x, y, z: (1.0 + 0.3 * x - 0.05 * x ** 2 + 0.01 * x ** 3) * (2.0 - 0.1 * y ** 2) * (1.0 + 0.2 * z - 0.02 * z ** 3)
+    Mdiag = fe.lumped_mass(nc, p, L)
+    Psi = (np.sqrt(Mdiag) * g(X[:, 0], X[:, 1], X[:, 2]))[:, None]
+    rho = dens.density_gauss(nc, p, L, Psi, np.array([0.7]))
+    gq, _ = fe.gauss_legendre(p + 1)
+    q1 = (1.0 + gq) * h / 2.0
+    qz, qy, qx = np.meshgrid(q1, q1, q1, indexing="ij")
+    checked = 0
+    for cz in range(nc - 1):
+        for cy in range(nc - 1):
+            for cx in range(nc - 1):
+                e = cx + nc * (cy + nc * cz)
+                ref = 0.7 * g(cx * h + qx.ravel(), cy * h + qy.ravel(), cz * h + qz.ravel()) ** 2
+                assert np.max(np.abs(rho[e] - ref)) < 1e-12 * np.max(np.abs(ref))
+                checked += 1
+    assert checked == 8
+
+
+def test_gauss_density_integrates_to_consistent_mass_norms():
+    # the (p+1)-point Gauss rule integrates |psi^|^2 exactly (degree 2p), so the
+    # quadrature sum of rho equals sum_c w_c psi^_c^H M_cons psi^_c with the
+    # consistent mass assembled cell by cell from the exact 1D mass matrices
+    nc, p, L = 2, 4, 5.0
+    s = workloads.small_system(nc, p, 2, seed=8, L=L, k=(0.3, -0.2, 0.1))
+    op = fe.build_operator(s)
+    rng = np.random.default_rng(4)
+    Psi = rng.standard_normal((op.M, 5)) + 1j * rng.standard_normal((op.M, 5))
+    w = np.array([2.0, 1.5, -0.3, 0.8, 2.0])
+    rho = dens.density_gauss(nc, p, L, Psi, w)
+    h = L / nc
+    _, gw = fe.gauss_legendre(p + 1)
+    Wq = fe.kron3(gw, gw, gw) * (h / 2.0) ** 3
+    lhs = float(np.sum(rho * Wq[None, :]))
+    t = fe.tables_1d(p, h)
+    Mc = fe.kron3(t.M1c, t.M1c, t.M1c)
+    Ph = op.D[:, None] * Psi
+    rhs = 0.0
+    for e in range(op.E):
+        v = Ph[op.cells[e]]
+        rhs += float(np.real(np.einsum("ac,ab,bc->c", v.conj(), Mc, v) @ w))
+    assert abs(lhs - rhs) < 1e-11 * abs(rhs)
