@@ -1,9 +1,10 @@
 """Benchmark: one ChFSI pass on the production-size FP64 workload on one MI355X.
 
-Workload (synthetic, seeded): periodic cube L = 48 bohr, 24^3 cells of order
-p = 6 (M = 144^3 = 2,985,984 nodes, 343 nodes per cell), 64 Gaussian atoms
-(minimum separation 2 bohr) with local potentials and 4 s/p projectors each,
-N = 256 wanted states, column blocks of B = 128, Chebyshev degree m = 30.
+Default workload (c1; synthetic, seeded): periodic cube L = 48 bohr, 24^3
+cells of order p = 6 (M = 144^3 = 2,985,984 nodes, 343 nodes per cell), 64
+Gaussian atoms (minimum separation 2 bohr) with local potentials and 4 s/p
+projectors each, N = 256 wanted states, column blocks of B = 128, Chebyshev
+degree m = 30.
 
 A step is one pass of the hot path: the Chebyshev filter of every column
 block (cell-wise H~.X with nonlocal projectors, fused recurrence), the
@@ -14,9 +15,20 @@ Prints one JSON line.  ``value`` is the pass's algorithmic flop rate
 (cell products, nonlocal products and subspace GEMMs counted without
 padding) in GFLOP/s; ``ms_per_step`` is the pass time.  The ``roofline``
 object reports the dominant kernel (the cell H~.X kernel) against the FP64
-MFMA peak, timed with HIP events on the library's stream.  The
-``cpu_baseline`` object times the FP64 oracle (numpy/scipy) on a bounded
-sample of the same workload on the host cores.
+MFMA peak, timed with HIP events on the library's stream, with the HBM
+traffic per launch from the committed rocprofv3 counter summary when it was
+taken on the current kernel source.  The ``cpu_baseline`` object times the
+FP64 oracle (numpy/scipy) on a bounded sample of the same workload on the
+host cores.
+
+Other workloads (``--workload``), each printing one JSON line of its own:
+c2 (time to Delta E <= 1e-6 Ha at N = 1024 for FP64, FP32, BF16 and the
+mixed schedule), c3 (32 batched complex k-point problems, sequential vs
+persistent launch vs hipGraph, complex128 vs complex64), c4 (learned warm
+start: training on solver output, passes saved on held-out configurations)
+kernels (one 128-column filter step per precision) and density (electron
+density of the c2 block at the nodes and at the Gauss points of every cell,
+with the Fermi level).
 """
 from __future__ import annotations
 
@@ -89,10 +101,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "kernels"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "kernels", "density"],
                     help="c1: FP64 pass at production size (the headline line); c2: mixed precision "
                          "time-to-accuracy at N=1024; c3: batched k-point solves; c4: learned warm start; "
-                         "kernels: one 128-column filter step per precision")
+                         "kernels: one 128-column filter step per precision; density: electron density "
+                         "of the c2 block")
     ap.add_argument("--out", default=None, help="write per-pass histories (npz) here")
     ap.add_argument("--max-passes", type=int, default=0, help="c2: pass cap per run (0: default)")
     ap.add_argument("--c2-runs", default="f32,mixed,bf16", help="c2: runs beside the FP64 reference")
@@ -112,6 +125,8 @@ def main():
         return run_c4(args)
     if args.workload == "kernels":
         return run_kernels(args)
+    if args.workload == "density":
+        return run_density(args)
     return run_c1(args)
 
 
@@ -612,6 +627,89 @@ def run_kernels(args):
                                   "at its first k-point (C128, C64)"},
            "kernels": res}
     print(json.dumps(out), flush=True)
+
+
+def run_density(args):
+    """Electron density of a c2-sized block: the c1 operator (M = 2,985,984,
+    p = 6) with 1024 + 128 FP64 columns, at the nodes and at the 343 Gauss
+    points of each of the 13,824 cells, weights 2 f_i from the Fermi level of
+    a synthetic spectrum (N_e = 2048, Fermi-Dirac smearing at 500 K)."""
+    import numpy as np
+    import torch
+
+    import paper_2203_07820_amd as lib
+    import workloads
+
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+    s = workloads.config("c1")
+    op = lib.Operator(ctx, s)
+    ncols, steps = 1152, max(2, args.steps * 2)
+    g = torch.Generator(device="cuda").manual_seed(61)
+    X = torch.randn(op.M, ncols, dtype=torch.float64, device="cuda", generator=g)
+    theta = np.sort(np.random.default_rng(62).uniform(-1.0, 1.5, ncols))
+    kT = 500.0 * 3.166811563e-6     # Hartree per kelvin
+    t0 = time.perf_counter()
+    mu, f = lib.fermi_level(theta, 2048.0, kT)
+    fermi_ms = (time.perf_counter() - t0) * 1e3
+    w = 2.0 * f
+    nq = (s.p + 1) ** 3
+    outs = {"nodes": (lib.RHO_NODES, torch.empty(op.M, dtype=torch.float64, device="cuda")),
+            "gauss": (lib.RHO_GAUSS, torch.empty(op.E * nq, dtype=torch.float64, device="cuda"))}
+    res = {}
+    for name, (points, out) in outs.items():
+        for _ in range(max(1, args.warmup)):
+            op.density(X, w, out, points=points)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(steps):
+            op.density(X, w, out, points=points)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        nbytes = op.M * ncols * 8 + op.M * 8 + out.numel() * 8   # X, M^-1/2, rho
+        res[name] = {"ms": ms, "algorithmic_bytes": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+                     "frac_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "outputs": out.numel()}
+        log(f"# density {name}: {ms:.3f} ms, {res[name]['GBps']:.0f} GB/s algorithmic")
+    gq = res["gauss"]
+    out = {"metric": "electron density at the Gauss points of every cell (algorithmic HBM GB/s)",
+           "value": gq["GBps"], "unit": "GB/s", "n_gpus": 1, "steps": steps, "warmup": max(1, args.warmup),
+           "ms_per_step": gq["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "density of a 1152-column FP64 block on the c1 operator (24^3 cells, p=6, "
+                                  "M=2985984), 343 Gauss points per cell", "ncols": ncols, "M": op.M,
+                      "E": op.E, "mu": mu, "kT": kT, "fermi_level_ms": fermi_ms},
+           "roofline": {"bound": "hbm", "achieved": gq["GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": gq["frac_hbm_peak"], "traffic": None},
+           "kernels": res}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = density_oracle_sample(s, X, w, op.E)
+    print(json.dumps(out), flush=True)
+
+
+def density_oracle_sample(s, X, w, E):
+    """The oracle's Gauss-point density on a sample of cells, timed."""
+    import numpy as np
+    import torch
+
+    from oracle import density as dens
+    from oracle import fe
+    cores = len(os.sched_getaffinity(0))
+    Mdiag = fe.lumped_mass(s.ncell, s.p, s.L)
+    cells = np.arange(0, E, max(1, E // 200))[:200]
+    nodes = fe.cell_nodes(s.ncell, s.p)[cells]
+    uniq, inv = np.unique(nodes.ravel(), return_inverse=True)
+    Xu = X[torch.from_numpy(uniq).cuda()].cpu().numpy()
+    Ph = ((1.0 / np.sqrt(Mdiag[uniq]))[:, None] * Xu)[inv.reshape(nodes.shape)]
+    t0 = time.perf_counter()
+    for i in range(cells.size):
+        dens.density_gauss_cell(s.p, Ph[i], w)
+    dt = time.perf_counter() - t0
+    per_cell = (X.shape[0] // E) * X.shape[1] * 8     # unique nodes per cell x columns x 8 B
+    return {"value": cells.size * per_cell / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle.density.density_gauss_cell on {cells.size} of {E} cells with all "
+                      f"{X.shape[1]} columns ({dt:.1f} s)", "seconds": dt}
 
 
 def c2_oracle_sample(sys_, Xref, theta, ref_tol):

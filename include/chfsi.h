@@ -282,6 +282,39 @@ int32_t chfsi_next_prec(int32_t prec, const double* max_resid, int32_t k, double
 int chfsi_pass(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double a, double b, double aL,
                double* theta, double* resid);
 
+/* ---- Fermi level and electron density ---------------------------------------
+ * Fermi-Dirac occupations f_i = 1 / (1 + exp((theta_i - mu) / kT)) of the
+ * Ritz values (Section 2.1, Fermi-Dirac smearing and the electron-count
+ * constraint; first step of the density-computation algorithm of Section
+ * 3.2).  chfsi_fermi_level() finds mu with 2 sum_i w_i f_i = n_electrons by
+ * bisection down to the spacing of doubles (the count rises monotonically
+ * with mu).  theta: host, n values; weights: host, n non-negative k-point
+ * weights (NULL: all 1); occ (host, n, nullable) receives f_i.  Requires
+ * 0 < n_electrons < 2 sum_i w_i and kT > 0, else CHFSI_EINVAL.  Host only. */
+int chfsi_fermi_level(const double* theta, int32_t n, const double* weights, double n_electrons, double kT,
+                      double* mu, double* occ);
+
+#define CHFSI_RHO_NODES 0  /* rho at the mesh nodes: M values, node order      */
+#define CHFSI_RHO_GAUSS 1  /* rho at the (p+1)^3 Gauss-Legendre points of every
+                              cell: E x (p+1)^3 values, cell cx + nc (cy + nc cz)
+                              major, point qx + (p+1) (qy + (p+1) qz) within the
+                              cell at origin + (1 + g_q) h / 2 per axis         */
+
+/* Electron density of the density-computation algorithm of Section 3.2:
+ *   rho(x) (+)= sum_c w_c |psi^_c(x)|^2,   psi^_c = M^-1/2 X_c
+ * interpolated with the FE basis (nodal values at the nodes; the cell's
+ * tensor-product Lagrange basis at the Gauss points).  X: device, M x ld,
+ * FP64 for a real operator or complex double for a complex one (the block
+ * type of chfsi_solve); w: host, ncols finite weights of any sign, e.g.
+ * 2 f_i for Ritz vectors, or in the spectrum-split form 2 for an orthonormal
+ * basis of the filtered space and 2 (f_i - 1) for the fractionally occupied
+ * Ritz vectors, accumulated in two calls; k-point weights multiply in.
+ * rho: device, overwritten (accumulate == 0) or added to.  The weights are
+ * copied before the call returns (it waits for the stream once to do so);
+ * the kernel itself runs asynchronously. */
+int chfsi_density(chfsi_op* op, const void* X, int64_t ncols, int64_t ld, const double* w, int32_t points,
+                  int32_t accumulate, double* rho);
+
 /* ---- batched filter (many operators, one persistent launch per step) -------
  * Applies the filter of chfsi_filter() to n independent blocks at once:
  * block q is X[q] (device, double / complex double, ncols[q] columns, ld[q])
@@ -294,9 +327,9 @@ int chfsi_pass(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, do
  * arguments and recurrence scalars come from device tables.  use_graph != 0
  * captures the whole sequence into a hipGraph (kept in the context and
  * replayed while the operators, buffers and shapes stay the same).  Grid
- * shape from chfsi_autotune() when tuned, else 1 (C128) or 2 workgroups per
- * CU.  Results equal chfsi_filter() on each block up to the order of the
- * atomic assembly.  Asynchronous. */
+ * shape from chfsi_autotune() when tuned, else one workgroup per item.
+ * Results equal chfsi_filter() on each block up to the order of the atomic
+ * assembly.  Asynchronous. */
 int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* const* X, const int64_t* ncols,
                          const int64_t* ld, int32_t m, const double* a, const double* b, const double* aL,
                          int32_t prec, int32_t block, int32_t use_graph);
@@ -318,7 +351,8 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
 
 /* ---- autotuner of the batched launch ----------------------------------------
  * Times the batched filter on a synthetic batch of four uneven boxes of order
- * p with `block` columns over persistent-grid shapes (1..4 workgroups per CU,
+ * p with `block` columns over grid shapes (one workgroup per item, reported as
+ * grid_per_cu = 0, or a persistent grid of 1..4 workgroups per CU with
  * contiguous or strided item assignment), keeps the fastest for the key
  * (gfx950, p, prec, block) in the context and, when cache_json is not NULL,
  * merges it into that JSON file (read first, then rewritten).  Synchronous.

@@ -16,10 +16,10 @@ from typing import Optional
 import numpy as np
 
 from . import _lib
-from ._lib import BF16, C64, C128, F32, F64  # noqa: F401
+from ._lib import BF16, C64, C128, F32, F64, RHO_GAUSS, RHO_NODES  # noqa: F401
 
-__all__ = ["ChfsiError", "Context", "Operator", "Network", "features", "initial_block", "F64", "F32", "BF16",
-           "C128", "C64", "load"]
+__all__ = ["ChfsiError", "Context", "Operator", "Network", "features", "initial_block", "fermi_level", "F64",
+           "F32", "BF16", "C128", "C64", "RHO_NODES", "RHO_GAUSS", "load"]
 
 
 class ChfsiError(RuntimeError):
@@ -43,6 +43,16 @@ def _tptr(t) -> C.c_void_p:
         raise ValueError("device tensor expected")
     if not t.is_contiguous():
         raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _bptr(t) -> C.c_void_p:
+    """Device pointer of a row-major block that may be a column slice of a
+    wider one (unit column stride, row stride = ld)."""
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if t.dim() == 2 and t.stride(1) != 1 or t.dim() == 1 and not t.is_contiguous():
+        raise ValueError("block rows must be contiguous (unit column stride)")
     return C.c_void_p(t.data_ptr())
 
 
@@ -262,6 +272,20 @@ class Operator:
             raise ValueError("X and Y must have the same shape and ld")
         self.ctx.check(self.ctx.lib.chfsi_apply(self.h, _tptr(X), _tptr(Y), ncols, ld, int(prec)))
 
+    def density(self, X, w, rho, points: int = RHO_NODES, accumulate: bool = False):
+        """chfsi_density: rho (device float64; M values at the nodes, or
+        E x (p+1)^3 at the Gauss points) (+)= sum_c w_c |M^-1/2 X_c|^2
+        interpolated by the FE basis; X is the FP64 / complex128 block."""
+        ncols, ld = _ld_cols(X)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        if w.size != ncols:
+            raise ValueError("one weight per column")
+        n_out = self.M if points == RHO_NODES else self.E * (self.p + 1) ** 3
+        if rho.numel() != n_out:
+            raise ValueError(f"rho must hold {n_out} values")
+        self.ctx.check(self.ctx.lib.chfsi_density(self.h, _bptr(X), ncols, ld, _dptr(w), int(points),
+                                                  int(bool(accumulate)), _tptr(rho)))
+
     def bounds(self, steps: int = 20, v0=None, seed: int = 0):
         b, lmin = C.c_double(), C.c_double()
         self.ctx.check(self.ctx.lib.chfsi_bounds(self.h, int(steps), _tptr(v0), C.c_uint64(seed), C.byref(b),
@@ -421,6 +445,21 @@ def next_prec(prec: int, max_resid_history, b_upper: float) -> int:
     solve, given max residuals after the initial Rayleigh-Ritz and each pass."""
     h = np.ascontiguousarray(max_resid_history, dtype=np.float64)
     return int(_lib.load().chfsi_next_prec(int(prec), _dptr(h), int(h.size - 1), float(b_upper)))
+
+
+def fermi_level(theta, n_electrons: float, kT: float, weights=None):
+    """chfsi_fermi_level: (mu, occupations) with 2 sum_i w_i f_i = n_electrons."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if w is not None and w.size != th.size:
+        raise ValueError("one weight per Ritz value")
+    mu = C.c_double()
+    occ = np.empty_like(th)
+    rc = _lib.load().chfsi_fermi_level(_dptr(th), int(th.size), None if w is None else _dptr(w), float(n_electrons),
+                                       float(kT), C.byref(mu), _dptr(occ))
+    if rc != 0:
+        raise ChfsiError(rc, "chfsi_fermi_level: need 0 < n_electrons < 2 sum(w), kT > 0, finite values")
+    return mu.value, occ
 
 
 def features(op: Operator, F) -> None:

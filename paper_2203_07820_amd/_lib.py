@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libchfsi.so")
 
 OK, NOTCONV, EINVAL, ENOMEM, EHIP, ECHOL, EDIVERGE = 0, 1, -1, -2, -3, -4, -5
 F64, F32, BF16, C128, C64 = 0, 1, 2, 3, 4
+RHO_NODES, RHO_GAUSS = 0, 1
 
 # every symbol include/chfsi.h declares
 EXPORTS = [
@@ -20,7 +21,7 @@ EXPORTS = [
     "chfsi_filter_batched", "chfsi_solve_batched", "chfsi_autotune", "chfsi_load_tuning", "chfsi_get_tuning",
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
-    "chfsi_initial_block", "chfsi_next_prec",
+    "chfsi_initial_block", "chfsi_next_prec", "chfsi_fermi_level", "chfsi_density",
 ]
 
 
@@ -109,6 +110,8 @@ def load() -> C.CDLL:
         "chfsi_mlp_train_step": (C.c_int, [vp, vp, i64, vp, i32, C.c_float, pd]),
         "chfsi_initial_block": (C.c_int, [vp, vp, u64, vp, i64, i64, C.POINTER(i32)]),
         "chfsi_next_prec": (i32, [i32, pd, i32, dbl]),
+        "chfsi_fermi_level": (C.c_int, [pd, i32, pd, dbl, dbl, pd, pd]),
+        "chfsi_density": (C.c_int, [vp, vp, i64, i64, pd, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -545,7 +545,8 @@ chfsi_ctx::Tuning tuning_for(chfsi_ctx* ctx, int p, int prec, int64_t block) {
   auto it = ctx->tuning.find(tune_key(p, prec, block));
   if (it != ctx->tuning.end()) return it->second;
   chfsi_ctx::Tuning t;
-  t.grid_per_cu = (prec == CHFSI_C128) ? 1 : 2;  // resident workgroups per CU
+  t.grid_per_cu = 0;  // one workgroup per item: the hardware dispatcher balances the load
+  (void)prec;
   return t;
 }
 
@@ -691,7 +692,11 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
         hb.descs = dtab + (static_cast<size_t>(r) * m + (st - 1)) * n * db;
         hb.item_off = doff + r * (n + 1);
         hb.nprob = na;
-        hb.grid = std::max(1, ctx->ncu * tu.grid_per_cu);
+        // grid_per_cu > 0: a persistent grid of that many workgroups per CU;
+        // 0: one workgroup per item of the round
+        const int64_t nitems_r = hoff[r * (n + 1) + na];
+        hb.grid = tu.grid_per_cu > 0 ? std::max(1, ctx->ncu * tu.grid_per_cu)
+                                     : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nitems_r, 0x7fffffff)));
         hb.contiguous = tu.contiguous;
         HIP_TRY(ctx, launch_cell_hx_batched(hb, prec, ctx->stream));
       }
@@ -752,7 +757,7 @@ int load_tuning_file(chfsi_ctx* ctx, const std::string& path) {
     t.grid_per_cu = std::atoi(line.c_str() + g + 15);
     t.contiguous = std::atoi(line.c_str() + c + 14);
     if (ms != std::string::npos) t.ms = std::atof(line.c_str() + ms + 6);
-    if (t.grid_per_cu >= 1 && t.grid_per_cu <= 16) ctx->tuning[line.substr(k0 + 8, k1 - k0 - 8)] = t;
+    if (t.grid_per_cu >= 0 && t.grid_per_cu <= 16) ctx->tuning[line.substr(k0 + 8, k1 - k0 - 8)] = t;
   }
   return 0;
 }
@@ -914,6 +919,7 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
       if ((rc = upload_f32(op.get(), sw, &op->Ai32)) < 0) break;
     }
     if ((rc = upload(op.get(), t.vdiag, &op->vdiag)) < 0) break;
+    if ((rc = upload(op.get(), t.dscale, &op->dscale)) < 0) break;
     if (t.has_proj) {
       if ((rc = upload(op.get(), t.atom_ptr, &op->atom_ptr)) < 0) break;
       if ((rc = upload(op.get(), t.atom_node, &op->atom_node)) < 0) break;
@@ -1082,6 +1088,83 @@ int chfsi_pass(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, doub
   for (int64_t i = 0; i < N; ++i)
     if (!std::isfinite(theta[i]) || !std::isfinite(r[i]))
       return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
+  return 0;
+}
+
+int chfsi_fermi_level(const double* theta, int32_t n, const double* weights, double n_electrons, double kT,
+                      double* mu, double* occ) {
+  if (!theta || !mu || n < 1 || !(kT > 0.0) || !std::isfinite(kT)) return CHFSI_EINVAL;
+  double wsum = 0.0, lo = theta[0], hi = theta[0];
+  for (int32_t i = 0; i < n; ++i) {
+    const double wi = weights ? weights[i] : 1.0;
+    if (!std::isfinite(theta[i]) || !(wi >= 0.0)) return CHFSI_EINVAL;
+    wsum += wi;
+    lo = std::min(lo, theta[i]);
+    hi = std::max(hi, theta[i]);
+  }
+  if (!(n_electrons > 0.0) || !(n_electrons < 2.0 * wsum)) return CHFSI_EINVAL;
+  // f(e) = 1 / (1 + exp((e - mu) / kT)), written so that exp never overflows
+  auto fermi = [kT](double e, double m) {
+    const double x = (e - m) / kT;
+    if (x > 0.0) {
+      const double t = std::exp(-x);
+      return t / (1.0 + t);
+    }
+    return 1.0 / (1.0 + std::exp(x));
+  };
+  auto count = [&](double m) {
+    double c = 0.0;
+    for (int32_t i = 0; i < n; ++i) c += (weights ? weights[i] : 1.0) * fermi(theta[i], m);
+    return 2.0 * c;
+  };
+  // the count rises monotonically with mu: bisect to the width of a double
+  lo -= 50.0 * kT;
+  hi += 50.0 * kT;
+  for (int it = 0; it < 2000 && hi - lo > 0.0; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count(mid) < n_electrons) lo = mid;
+    else hi = mid;
+  }
+  *mu = 0.5 * (lo + hi);
+  if (occ)
+    for (int32_t i = 0; i < n; ++i) occ[i] = fermi(theta[i], *mu);
+  return 0;
+}
+
+int chfsi_density(chfsi_op* op, const void* X, int64_t ncols, int64_t ld, const double* w, int32_t points,
+                  int32_t accumulate, double* rho) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  if (!w || !rho) return fail(ctx, CHFSI_EINVAL, "null weights or output");
+  if (points != CHFSI_RHO_NODES && points != CHFSI_RHO_GAUSS)
+    return fail(ctx, CHFSI_EINVAL, "points must be CHFSI_RHO_NODES or CHFSI_RHO_GAUSS");
+  for (int64_t i = 0; i < ncols; ++i)
+    if (!std::isfinite(w[i])) return fail(ctx, CHFSI_EINVAL, "weights must be finite");
+  const HostTables& t = op->t;
+  const int cf = t.cplx ? 2 : 1;
+  if (ncols * cf > (1LL << 30) || ld * cf > (1LL << 40)) return fail(ctx, CHFSI_EINVAL, "block too wide");
+  void* dw;
+  CHECK(ws_get(ctx, WS_DENS, static_cast<size_t>(ncols) * 8, &dw));
+  HIP_TRY(ctx, hipMemcpyAsync(dw, w, static_cast<size_t>(ncols) * 8, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // w may be reused once the call returns
+  DensityLaunch d{};
+  d.X = static_cast<const double*>(X);
+  d.ld = ld;
+  d.ncols = static_cast<int>(ncols);
+  d.cplx = t.cplx;
+  d.w = static_cast<const double*>(dw);
+  d.dscale = op->dscale;
+  d.rho = rho;
+  d.M = t.M;
+  d.E = t.E;
+  d.p = t.p;
+  d.nc = t.ncell;
+  d.points = points;
+  d.accumulate = accumulate ? 1 : 0;
+  d.interp = t.interp.data();
+  HIP_TRY(ctx, launch_density(d, ctx->stream));
   return 0;
 }
 
@@ -1420,8 +1503,9 @@ int chfsi_autotune(chfsi_ctx* ctx, const char* cache_json, int32_t p, int32_t pr
   chfsi_ctx::Tuning best;
   best.ms = 1e300;
   const int m = 4;
-  for (int g = 1; g <= 4 && rc == 0; ++g)
+  for (int g = 0; g <= 4 && rc == 0; ++g)
     for (int cont = 1; cont >= 0 && rc == 0; --cont) {
+      if (g == 0 && cont == 1) continue;  // one item per workgroup: assignment is moot
       chfsi_ctx::Tuning t;
       t.grid_per_cu = g;
       t.contiguous = cont;

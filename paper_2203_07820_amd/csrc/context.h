@@ -19,6 +19,7 @@ enum Slot {
   WS_W, WS_X2, WS_HPSI,            // M x N work blocks
   WS_RPART, WS_VEC, WS_SMALL, WS_EIG, WS_INFO,
   WS_BATCH, WS_BTAB,               // batched filter buffers and descriptor tables
+  WS_DENS,                         // density weights
   WS_COUNT
 };
 
@@ -60,6 +61,7 @@ struct chfsi_op {
   void* A32 = nullptr;  void* Ai32 = nullptr;   // float
   void* Abf = nullptr;                          // bf16, 16x16x32 operand order
   double* vdiag = nullptr;
+  double* dscale = nullptr;     // M^-1/2 per node (density)
   int64_t* atom_ptr = nullptr;
   int32_t* atom_node = nullptr;
   double* atom_val = nullptr;

@@ -32,6 +32,7 @@ struct HostTables {
   std::vector<double> cell_re;      // mcell x mcell
   std::vector<double> cell_im;      // mcell x mcell (complex only)
   std::vector<double> dscale;       // per node M^-1/2 (M)
+  std::vector<double> interp;       // (p+1) x (p+1): interp[q*(p+1)+a] = l_a(g_q)
   std::vector<double> vdiag;        // V + |k|^2/2 (M)
   int natoms = 0;
   bool has_proj = false;
@@ -116,6 +117,22 @@ struct NlLaunch {
   void* hP; int64_t ldhp;           // natoms*4 x ldhp (real view)
 };
 hipError_t launch_nl_project(const NlLaunch& a, int prec, hipStream_t s);
+
+// Electron density (kernels_density.hip).  points 0: at the nodes (M
+// values); 1: at the (p+1)^3 Gauss points of every cell (E x (p+1)^3).
+struct DensityLaunch {
+  const double* X; int64_t ld;      // logical ld (complex entries for complex)
+  int ncols;                        // logical columns
+  bool cplx;
+  const double* w;                  // device, ncols weights
+  const double* dscale;             // device, M^-1/2 per node
+  double* rho;
+  int64_t M, E;
+  int p, nc;
+  int points, accumulate;
+  const double* interp;             // host, (p+1) x (p+1)
+};
+hipError_t launch_density(const DensityLaunch& d, hipStream_t s);
 
 // Elementwise helpers on row-major blocks (real view).
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);

@@ -13,8 +13,9 @@
 //   3. adds the nonlocal term C^{c,a} (h P_a) for every atom a whose
 //      projectors touch the cell, as extra 4-wide k steps (Algorithm 4 steps
 //      5-6, with P_a from the node-level contraction of kernels_nl.hip);
-//   4. scatters alpha * Y^c into the target with atomic adds (ASEMB_FEM).
-//      The owner cell of each node (local indices all < p) also adds
+//   4. scatters alpha * Y^c into the target with atomic adds (ASEMB_FEM;
+//      plain stores for nodes interior to the cell, which have no other
+//      contributor).  The owner cell of each node (local indices all < p) adds
 //      alpha (V_j - c) X_k[j] - beta X_{k-1}[j], so the target ends up holding
 //      X_{k+1} = alpha (H~ X_k - c X_k) - beta X_{k-1} without a separate pass;
 //      the owner then zeroes X_{k-1}[j], which becomes the target two steps on.

@@ -173,8 +173,10 @@ std::string build_tables(const chfsi_system& sys, HostTables& t) {
   gauss_rule(p + 1, gq, gw);
   std::vector<double> K1(q * q, 0.0), Mc(q * q, 0.0), G1(q * q, 0.0);
   std::vector<double> l, dl;
+  t.interp.assign(static_cast<size_t>(q) * q, 0.0);
   for (int iq = 0; iq <= p; ++iq) {
     lagrange_at(xi, gq[iq], l, dl);
+    for (int a = 0; a < q; ++a) t.interp[iq * q + a] = l[a];
     for (int a = 0; a < q; ++a)
       for (int b = 0; b < q; ++b) {
         K1[a * q + b] += gw[iq] * (2.0 / h) * dl[a] * dl[b];

@@ -134,7 +134,7 @@ def test_solve_batched_tolerance_retires_problems(ctx):
 def test_autotune_writes_cache_and_is_used(ctx, tmp_path):
     path = str(tmp_path / "tune.json")
     t = ctx.autotune(3, lib.C128, 16, cache_json=path)
-    assert 1 <= t["grid_per_cu"] <= 4 and t["contiguous"] in (0, 1) and t["ms"] > 0
+    assert 0 <= t["grid_per_cu"] <= 4 and t["contiguous"] in (0, 1) and t["ms"] > 0
     data = json.loads(open(path).read())
     assert any(e["key"] == "gfx950:p3:prec3:B16" for e in data)
     c2 = lib.Context(0)
