@@ -698,6 +698,7 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
         hb.grid = tu.grid_per_cu > 0 ? std::max(1, ctx->ncu * tu.grid_per_cu)
                                      : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nitems_r, 0x7fffffff)));
         hb.contiguous = tu.contiguous;
+        hb.one_per_item = tu.grid_per_cu == 0 && nitems_r <= 0x7fffffff;
         HIP_TRY(ctx, launch_cell_hx_batched(hb, prec, ctx->stream));
       }
       for (int k = 0; k < na; ++k) {

@@ -99,6 +99,7 @@ struct HxBatch {
   int nprob;
   int grid;        // persistent workgroups
   int contiguous;  // 1: contiguous item range per workgroup, 0: strided
+  int one_per_item = 0;  // grid equals the number of items: one item per workgroup
 };
 size_t hx_desc_bytes(int prec);
 void pack_hx_desc(const HxLaunch& L, int prec, void* out);

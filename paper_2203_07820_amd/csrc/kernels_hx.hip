@@ -504,6 +504,26 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
   }
 }
 
+// The same work list with exactly one workgroup per item (grid = number of
+// items): no item loop, the problem found by a binary search over item_off,
+// which keeps the scalar registers of the loop free for the cell item.
+template <int P, typename T, bool CPLX, int WAVES, int OCC>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
+cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob) {
+  __shared__ RowTables<rows_padded<P>(), T> tab;
+  const int it = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = nprob - 1;  // last problem whose first item is <= it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (item_off[mid] <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  const HxArgs<T> d = descs[lo];
+  const int local = it - static_cast<int>(item_off[lo]);
+  const int E = d.nc * d.nc * d.nc;
+  cell_item<P, T, CPLX, WAVES, false>(d, local % E, (local / E) * kNT, tab);
+}
+
 // Waves per SIMD: two for real and complex FP64, complex FP32 and bf16 (one
 // workgroup's epilogue overlaps the other's MFMAs), three for real FP32
 // (140 VGPRs at p = 6); complex FP64 at p = 6 (11 row tiles per wave, A and
@@ -575,8 +595,12 @@ hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
   constexpr int WAVES = waves_for<P>();
   constexpr int OCC = occupancy<P, T, CPLX, false>();
   if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
-                     static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);
+  if (b.one_per_item)
+    hipLaunchKernelGGL((cell_hx_batched1_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
+                       static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob);
+  else
+    hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
+                       static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);
   return hipGetLastError();
 }
 
