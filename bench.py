@@ -57,14 +57,14 @@ def pass_flops(M, E, mcell, npairs, N, m, cplx=False):
     return cell, nonlocal_, sub
 
 
-def profiled_traffic():
-    """HBM bytes per 128-column filter launch of the cell kernel, from the
-    committed rocprofv3 counter summary, if it was taken on the current
-    kernel source (else None)."""
+def profiled_traffic(profile="cell_hx_c1_fp64.md", source="kernels_hx.hip"):
+    """HBM bytes per launch of a kernel (by default the cell kernel's
+    128-column filter step), from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
     import hashlib
     import re
-    prof = os.path.join(ROOT, "profiles", "cell_hx_c1_fp64.md")
-    src = os.path.join(ROOT, "paper_2203_07820_amd", "csrc", "kernels_hx.hip")
+    prof = os.path.join(ROOT, "profiles", profile)
+    src = os.path.join(ROOT, "paper_2203_07820_amd", "csrc", source)
     try:
         text = open(prof).read()
         m = re.search(r"```json\s*(\{.*?\})\s*```", text, re.S)
@@ -681,7 +681,9 @@ def run_density(args):
                                   "M=2985984), 343 Gauss points per cell", "ncols": ncols, "M": op.M,
                       "E": op.E, "mu": mu, "kT": kT, "fermi_level_ms": fermi_ms},
            "roofline": {"bound": "hbm", "achieved": gq["GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": gq["frac_hbm_peak"], "traffic": None},
+                        "frac": gq["frac_hbm_peak"],
+                        "traffic": profiled_traffic("density_c1_1152.md", "kernels_density.hip"),
+                        "traffic_unit": "HBM bytes per Gauss-point launch"},
            "kernels": res}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = density_oracle_sample(s, X, w, op.E)
