@@ -286,6 +286,19 @@ class Operator:
         self.ctx.check(self.ctx.lib.chfsi_density(self.h, _bptr(X), ncols, ld, _dptr(w), int(points),
                                                   int(bool(accumulate)), _tptr(rho)))
 
+    def rayleigh_ritz_split(self, X, nfr: int, Psi_fr, mixed: bool = False):
+        """chfsi_rayleigh_ritz_split: X (FP64 filtered block) becomes Psi_o;
+        Psi_fr receives the nfr highest Ritz vectors; returns all N
+        generalised eigenvalues."""
+        ncols, ld = _ld_cols(X)
+        nf, ldf = _ld_cols(Psi_fr)
+        if nf != nfr:
+            raise ValueError("Psi_fr must have nfr columns")
+        th = np.zeros(ncols)
+        self.ctx.check(self.ctx.lib.chfsi_rayleigh_ritz_split(self.h, _bptr(X), ncols, ld, int(nfr),
+                                                              int(bool(mixed)), _dptr(th), _bptr(Psi_fr), ldf))
+        return th
+
     def bounds(self, steps: int = 20, v0=None, seed: int = 0):
         b, lmin = C.c_double(), C.c_double()
         self.ctx.check(self.ctx.lib.chfsi_bounds(self.h, int(steps), _tptr(v0), C.c_uint64(seed), C.byref(b),

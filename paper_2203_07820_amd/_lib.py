@@ -22,6 +22,7 @@ EXPORTS = [
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
     "chfsi_initial_block", "chfsi_next_prec", "chfsi_fermi_level", "chfsi_density",
+    "chfsi_rayleigh_ritz_split",
 ]
 
 
@@ -112,6 +113,7 @@ def load() -> C.CDLL:
         "chfsi_next_prec": (i32, [i32, pd, i32, dbl]),
         "chfsi_fermi_level": (C.c_int, [pd, i32, pd, dbl, dbl, pd, pd]),
         "chfsi_density": (C.c_int, [vp, vp, i64, i64, pd, i32, i32, vp]),
+        "chfsi_rayleigh_ritz_split": (C.c_int, [vp, vp, i64, i64, i32, i32, pd, vp, i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -401,6 +401,124 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
   return 0;
 }
 
+// Rayleigh-Ritz through the generalised eigenproblem with spectrum splitting
+// (Algorithm 2), real operators.  X (M x N, ldx) holds the filtered block on
+// entry and Psi_o = X L^-T on exit; Pfr (M x nfr, ldfr) receives the nfr
+// highest Ritz vectors X Q_fr; theta (host, N) all generalised eigenvalues.
+// mixed: S off-diagonal 128-blocks and H^ outside its fr-fr block from FP32
+// copies in FP32 arithmetic, Psi_o = FP32[X L^-T without diagonal] +
+// FP64[X diag(L^-T)].
+int rrgep_split(chfsi_op* op, double* X, int64_t ldx, int64_t N, int nfr, bool mixed, double* theta, double* Pfr,
+                int64_t ldfr) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int64_t M = t.M;
+  const int n = static_cast<int>(N);
+  hipStream_t st = ctx->stream;
+  void *W, *part, *G, *S, *Hh, *Zb, *dinfo, *eig;
+  CHECK(ws_get(ctx, WS_W, static_cast<size_t>(M) * N * 8, &W));
+  // the partial buffer serves the full Gram and the 128-wide and fr-wide ones
+  const int64_t ldm = std::max<int64_t>(ldx, N);
+  const size_t pbytes = std::max({gram_partial_bytes(M, n, ldm), gram_partial_bytes(M, std::min(n, 128), ldm),
+                                  gram_partial_bytes(M, nfr, ldm)});
+  CHECK(ws_get(ctx, WS_GPART, pbytes, &part));
+  CHECK(ws_get(ctx, WS_RR_G, static_cast<size_t>(N) * N * 8, &G));
+  CHECK(ws_get(ctx, WS_RR_S, static_cast<size_t>(N) * N * 8, &S));
+  CHECK(ws_get(ctx, WS_RR_H, static_cast<size_t>(N) * N * 8, &Hh));
+  CHECK(ws_get(ctx, WS_RR_Z, static_cast<size_t>(N) * N * 8 + static_cast<size_t>(N) * 8, &Zb));
+  CHECK(ws_get(ctx, WS_INFO, 64, &dinfo));
+  CHECK(ws_get(ctx, WS_EIG, static_cast<size_t>(N) * 3 * 8, &eig));
+  double* Gd = static_cast<double*>(G);
+  double* Sd = static_cast<double*>(S);
+  double* Hd = static_cast<double*>(Hh);
+  double* Zd = static_cast<double*>(Zb);
+  double* D = static_cast<double*>(eig);
+  double* Ework = D + N;
+  double* Wd = static_cast<double*>(W);
+  double* partd = static_cast<double*>(part);
+  // RRGEP-P needs W = H~ X
+  HIP_TRY(ctx, launch_fill(W, M, N, N, CHFSI_F64, st));
+  CHECK(hx_step(op, CHFSI_F64, X, ldx, nullptr, 0, W, N, N, 1.0, 0.0, 0.0, false));
+  float *X32 = nullptr, *W32 = nullptr;
+  if (mixed) {
+    void *a, *b;
+    CHECK(ws_get(ctx, WS_X32, static_cast<size_t>(M) * N * 4, &a));
+    CHECK(ws_get(ctx, WS_W32, static_cast<size_t>(M) * N * 4, &b));
+    X32 = static_cast<float*>(a);
+    W32 = static_cast<float*>(b);
+    HIP_TRY(ctx, launch_convert(X32, N, CHFSI_F32, X, ldx, CHFSI_F64, M, N, st));
+    HIP_TRY(ctx, launch_convert(W32, N, CHFSI_F32, W, N, CHFSI_F64, M, N, st));
+  }
+  // RRGEP-O: lower tiles of S; with mixed, FP32 everywhere, then the
+  // diagonal 128-blocks again in FP64
+  if (mixed) {
+    HIP_TRY(ctx, launch_gram(X32, N, X32, N, M, n, partd, Gd, N, st));
+    for (int64_t c0 = 0; c0 < N; c0 += 128) {
+      const int nb = static_cast<int>(std::min<int64_t>(128, N - c0));
+      HIP_TRY(ctx, launch_gram(X + c0, ldx, X + c0, ldx, M, nb, partd, Gd + c0 * N + c0, N, st, c0, c0));
+    }
+  } else {
+    HIP_TRY(ctx, launch_gram(X, ldx, X, ldx, M, n, partd, Gd, N, st));
+  }
+  HIP_TRY(ctx, launch_sym_from_lower(Gd, N, Sd, n, st));
+  // RRGEP-P: H^ = X^T W; with mixed, FP32 except the fr-fr block
+  const int64_t f0 = N - nfr;
+  if (mixed) {
+    HIP_TRY(ctx, launch_gram(X32, N, W32, N, M, n, partd, Gd, N, st));
+    HIP_TRY(ctx, launch_gram(X + f0, ldx, Wd + f0, N, M, nfr, partd, Gd + f0 * N + f0, N, st, f0, f0));
+  } else {
+    HIP_TRY(ctx, launch_gram(X, ldx, Wd, N, M, n, partd, Gd, N, st));
+  }
+  HIP_TRY(ctx, launch_sym_from_lower(Gd, N, Hd, n, st));
+  // RRGEP-D: S = L L^T, H' = L^-1 H^ L^-T, eigenpairs, Q_fr = L^-T Q'_fr
+  const rocblas_int rn = static_cast<rocblas_int>(N);
+  RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, rn, Sd, rn, static_cast<rocblas_int*>(dinfo)));
+  int info = 0;
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0)
+    return fail(ctx, CHFSI_ECHOL, "overlap matrix is not positive definite (leading minor " + std::to_string(info) +
+                                      ")");
+  const double one = 1.0;
+  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                            rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
+  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                            rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
+  RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, rn, Hd, rn, D, Ework,
+                               static_cast<rocblas_int*>(dinfo)));
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
+  double* Qfr = Hd + f0 * N;  // column-major N x nfr
+  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                            rocblas_diagonal_non_unit, rn, static_cast<rocblas_int>(nfr), &one, Sd, rn, Qfr, rn));
+  // RRGEP-ST-F: Psi^R_fr = X Q_fr (row-major N x nfr rotation)
+  HIP_TRY(ctx, launch_transpose_rect(Qfr, N, nfr, n, Zd, nfr, st));
+  HIP_TRY(ctx, launch_rotate(X, ldx, Zd, nfr, Pfr, ldfr, M, n, nfr, false, st));
+  // RRGEP-ST-O: Psi_o = X L^-T; the column-major lower L^-1 read row-major is
+  // the upper L^-T once its other triangle is cleared
+  RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, rn, Sd, rn,
+                               static_cast<rocblas_int*>(dinfo)));
+  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  if (info != 0) return fail(ctx, CHFSI_ECHOL, "Cholesky factor is singular");
+  HIP_TRY(ctx, launch_zero_strict_lower(Sd, n, N, st));
+  if (mixed) {
+    void* c32;
+    CHECK(ws_get(ctx, WS_C32, static_cast<size_t>(M) * N * 4, &c32));
+    float* Z32 = reinterpret_cast<float*>(Zd);  // N x N floats, then N doubles of the diagonal
+    double* dg = Zd + (static_cast<int64_t>(N) * N + 1) / 2;
+    HIP_TRY(ctx, launch_split_diag(Sd, N, n, Z32, dg, st));
+    HIP_TRY(ctx, launch_rotate(X32, N, Z32, N, static_cast<float*>(c32), N, M, n, n, true, st));
+    HIP_TRY(ctx, launch_add_scaled_cols(static_cast<float*>(c32), N, dg, X, ldx, M, n, st));
+  } else {
+    void* X2;
+    CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(M) * N * 8, &X2));
+    HIP_TRY(ctx, launch_rotate(X, ldx, Sd, N, static_cast<double*>(X2), N, M, n, n, true, st));
+    HIP_TRY(ctx, launch_convert(X, ldx, CHFSI_F64, X2, N, CHFSI_F64, M, N, st));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return 0;
+}
+
 // Eigenvalues of a small symmetric matrix by cyclic Jacobi rotations.
 std::vector<double> small_eigvals(std::vector<double> A, int n) {
   for (int sweep = 0; sweep < 100; ++sweep) {
@@ -1064,6 +1182,20 @@ int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double
   HIP_TRY(ctx, launch_convert(X, ld * cf, CHFSI_F64, X2, ncols * cf, CHFSI_F64, op->t.M, ncols * cf, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return 0;
+}
+
+int chfsi_rayleigh_ritz_split(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int32_t nfr, int32_t mixed,
+                              double* theta, void* Psi_fr, int64_t ld_fr) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  if (op->t.cplx) return fail(ctx, CHFSI_EINVAL, "the split Rayleigh-Ritz step is implemented for real operators");
+  if (!theta || !Psi_fr) return fail(ctx, CHFSI_EINVAL, "null theta or Psi_fr");
+  if (nfr < 1 || nfr > ncols) return fail(ctx, CHFSI_EINVAL, "need 1 <= nfr <= ncols");
+  if (ld_fr < nfr) return fail(ctx, CHFSI_EINVAL, "ld_fr < nfr");
+  if (ncols > 46340) return fail(ctx, CHFSI_EINVAL, "ncols too large for the N x N workspace");
+  return rrgep_split(op, static_cast<double*>(X), ld, ncols, nfr, mixed != 0, theta, static_cast<double*>(Psi_fr),
+                     ld_fr);
 }
 
 int chfsi_pass(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, double a, double b, double aL,

@@ -20,6 +20,8 @@ enum Slot {
   WS_RPART, WS_VEC, WS_SMALL, WS_EIG, WS_INFO,
   WS_BATCH, WS_BTAB,               // batched filter buffers and descriptor tables
   WS_DENS,                         // density weights
+  WS_RR_G, WS_RR_S, WS_RR_H, WS_RR_Z, // split Rayleigh-Ritz: lower Gram, S, H^, rotation
+  WS_X32, WS_W32, WS_C32,          // FP32 copies of X, H X and the FP32 rotation
   WS_COUNT
 };
 

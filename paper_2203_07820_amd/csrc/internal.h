@@ -145,10 +145,20 @@ hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, in
 // Lower-triangular Gram G = X^T Y (n x n, real view) -> partial buffers then
 // reduced into G (row-major, ldg), upper triangle mirrored.
 size_t gram_partial_bytes(int64_t M, int n, int64_t ld);
+// X / Y may point offx / offy columns into their rows (a column slice of a
+// block whose rows hold ldx / ldy values); offx + n <= ldx, offy + n <= ldy.
 hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
-                       double* partial, double* G, int64_t ldg, hipStream_t s);
+                       double* partial, double* G, int64_t ldg, hipStream_t s, int64_t offx = 0,
+                       int64_t offy = 0);
+// the same product on FP32 data in FP32 arithmetic (per row chunk; the chunk
+// partials are summed in FP64)
+hipError_t launch_gram(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t M, int n,
+                       double* partial, double* G, int64_t ldg, hipStream_t s, int64_t offx = 0,
+                       int64_t offy = 0);
 // C = X Z, X: M x K (ldx), Z: K x N2 row-major (ldz); upper = Z upper-triangular.
 hipError_t launch_rotate(const double* X, int64_t ldx, const double* Z, int64_t ldz, double* C,
+                         int64_t ldc, int64_t M, int K, int N2, bool upper, hipStream_t s);
+hipError_t launch_rotate(const float* X, int64_t ldx, const float* Z, int64_t ldz, float* C,
                          int64_t ldc, int64_t M, int K, int N2, bool upper, hipStream_t s);
 // Residual column sums: partial[chunk][j] = sum_rows |HX[r][j] - th[j] X[r][j]|^2
 // (complex: j indexes complex columns, data interleaved).
@@ -164,6 +174,14 @@ hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t 
 // small matrix helpers (n x n)
 hipError_t launch_transpose(const double* in, double* out, int n, hipStream_t s);
 hipError_t launch_zero_strict_lower(double* A, int n, int64_t lda, hipStream_t s);
+// out (cols x rows, ldo) = in^T for row-major in (rows x cols, ldi)
+hipError_t launch_transpose_rect(const double* in, int64_t ldi, int rows, int cols, double* out, int64_t ldo,
+                                 hipStream_t s);
+// Zo (n x n FP32) = Z without its diagonal, d = diag(Z) (FP64)
+hipError_t launch_split_diag(const double* Z, int64_t ldz, int n, float* Zo, double* d, hipStream_t s);
+// X[r][j] = C[r][j] + d[j] X[r][j], C FP32, M x n
+hipError_t launch_add_scaled_cols(const float* C, int64_t ldc, const double* d, double* X, int64_t ldx, int64_t M,
+                                  int n, hipStream_t s);
 // S[i][j] = G[max(i,j)][min(i,j)] (real symmetric from the lower Gram tiles)
 hipError_t launch_sym_from_lower(const double* G, int64_t ldg, double* S, int n, hipStream_t s);
 // complex Hermitian S (n x n column-major interleaved) from the real-view Gram

@@ -14,6 +14,7 @@ namespace chfsi {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register i holds D[4 i + l / 16][l % 16].
@@ -21,6 +22,25 @@ __device__ __forceinline__ d4 mma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ int acc_row(int lane, int i) { return 4 * i + lane / 16; }
+
+// The same products for FP64 and FP32 data.  v_mfma_f32_16x16x4f32 takes its
+// operands in the same lanes as the f64 instruction; its accumulator
+// register i holds D[4 (l / 16) + i][l % 16].
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using Acc = d4;
+  static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * i + lane / 16; }
+};
+template <> struct Mfma<float> {
+  using Acc = f4;
+  static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane / 16) + i; }
+};
 
 // ---- Gram: partial[chunk] tile (I, J), I >= J, of X^T Y --------------------
 // One workgroup computes a 128 x 128 tile over the rows of one chunk; 4 waves
@@ -33,17 +53,30 @@ __device__ __forceinline__ int acc_row(int lane, int i) { return 4 * i + lane / 
 // Loads run two k steps ahead of the MFMAs; no LDS, no barriers.
 constexpr int kGT = 128;  // Gram tile
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, bytes, 0x00020000);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
 }
+template <typename T, int OFF>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff);
 template <int OFF>
-__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, int voff) {
+__device__ __forceinline__ double bload64(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff + OFF, 0, 0));
 }
+template <int OFF>
+__device__ __forceinline__ float bload32(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff + OFF, 0, 0));
+}
+template <typename T, int G>   // 16-column group G of the lane's row
+__device__ __forceinline__ T bload_group(__amdgpu_buffer_rsrc_t r, int voff) {
+  if constexpr (sizeof(T) == 8) return bload64<G * 128>(r, voff);
+  else return bload32<G * 64>(r, voff);
+}
 
+template <typename T>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Y, int64_t ldy,
-            int64_t M, int n, int64_t rows_per_chunk, int npad, double* __restrict__ part) {
+gram_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t ldy,
+            int64_t M, int n, int64_t rows_per_chunk, int npad, double* __restrict__ part, int64_t offx,
+            int64_t offy) {
   const int t = blockIdx.x;
   // lower-triangular tile index -> (I, J)
   int I = static_cast<int>((sqrt(8.0 * t + 1.0) - 1.0) / 2.0);
@@ -57,11 +90,12 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
   const int nrows = static_cast<int>(m1 - m0);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wi = (wave / 2) * 64, wj = (wave % 2) * 64;
-  d4 acc[4][4];
+  using Acc = typename Mfma<T>::Acc;
+  Acc acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   // per-lane column of the first 16-column group (the others are +16 k).
   // Columns at or beyond n belong to the tile's padding, which is never read
   // back: what they load (the rest of the row, the next row, or zero past the
@@ -69,36 +103,41 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
   const int ci = I * kGT + wi + lane % 16;
   const int cj = J * kGT + wj + lane % 16;
   const int64_t nr = nrows > 0 ? nrows : 0;
-  const __amdgpu_buffer_rsrc_t rx = rsrc(X + (nr > 0 ? m0 * ldx : 0), static_cast<uint32_t>(nr * ldx * 8));
-  const __amdgpu_buffer_rsrc_t ry = rsrc(Y + (nr > 0 ? m0 * ldy : 0), static_cast<uint32_t>(nr * ldy * 8));
+  // X and Y may start offx / offy columns into their rows (a column slice):
+  // the ranges then end offx / offy elements before the last row's end, so
+  // the padding columns of the last chunk never reach past the allocation
+  const int64_t ex = nr > 0 ? (nr * ldx < (M - m0) * ldx - offx ? nr * ldx : (M - m0) * ldx - offx) : 0;
+  const int64_t ey = nr > 0 ? (nr * ldy < (M - m0) * ldy - offy ? nr * ldy : (M - m0) * ldy - offy) : 0;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(X + (nr > 0 ? m0 * ldx : 0), static_cast<uint32_t>(ex * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t ry = rsrc(Y + (nr > 0 ? m0 * ldy : 0), static_cast<uint32_t>(ey * sizeof(T)));
   const int KS = nrows > 0 ? (nrows + 3) / 4 : 0;   // every chunk still writes its tile
-  auto load = [&](double (&xv)[4], double (&yv)[4], int s) {
+  auto load = [&](T (&xv)[4], T (&yv)[4], int s) {
     const int row = min(4 * s + lane / 16, nrows - 1);
-    const int vx = (row * static_cast<int>(ldx) + ci) * 8;
-    const int vy = (row * static_cast<int>(ldy) + cj) * 8;
-    xv[0] = bload<0>(rx, vx);
-    xv[1] = bload<128>(rx, vx);
-    xv[2] = bload<256>(rx, vx);
-    xv[3] = bload<384>(rx, vx);
-    yv[0] = bload<0>(ry, vy);
-    yv[1] = bload<128>(ry, vy);
-    yv[2] = bload<256>(ry, vy);
-    yv[3] = bload<384>(ry, vy);
+    const int vx = (row * static_cast<int>(ldx) + ci) * static_cast<int>(sizeof(T));
+    const int vy = (row * static_cast<int>(ldy) + cj) * static_cast<int>(sizeof(T));
+    xv[0] = bload_group<T, 0>(rx, vx);
+    xv[1] = bload_group<T, 1>(rx, vx);
+    xv[2] = bload_group<T, 2>(rx, vx);
+    xv[3] = bload_group<T, 3>(rx, vx);
+    yv[0] = bload_group<T, 0>(ry, vy);
+    yv[1] = bload_group<T, 1>(ry, vy);
+    yv[2] = bload_group<T, 2>(ry, vy);
+    yv[3] = bload_group<T, 3>(ry, vy);
   };
-  auto compute = [&](const double (&xin)[4], const double (&yin)[4], int s) {
-    double xv[4], yv[4];
+  auto compute = [&](const T (&xin)[4], const T (&yin)[4], int s) {
+    T xv[4], yv[4];
     const bool ok = 4 * s + lane / 16 < nrows;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      xv[a] = ok ? xin[a] : 0.0;
-      yv[a] = ok ? yin[a] : 0.0;
+      xv[a] = ok ? xin[a] : T(0);
+      yv[a] = ok ? yin[a] : T(0);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = mma(xv[a], yv[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mma(xv[a], yv[b], acc[a][b]);
   };
-  double x0[4], y0[4], x1[4], y1[4], x2[4], y2[4];
+  T x0[4], y0[4], x1[4], y1[4], x2[4], y2[4];
   if (KS > 0) load(x0, y0, 0);
   if (KS > 1) load(x1, y1, 1);
   for (int s = 0; s < KS; ++s) {
@@ -119,9 +158,9 @@ gram_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict_
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = I * kGT + wi + a * 16 + acc_row(lane, i);
+        const int row = I * kGT + wi + a * 16 + Mfma<T>::row(lane, i);
         const int col = J * kGT + wj + b * 16 + lane % 16;
-        out[static_cast<int64_t>(row) * npad + col] = acc[a][b][i];
+        out[static_cast<int64_t>(row) * npad + col] = static_cast<double>(acc[a][b][i]);
       }
 }
 
@@ -182,20 +221,22 @@ constexpr int kRN = 128;  // columns per workgroup
 constexpr int kRK = 16;   // k per stage
 constexpr int kZP = kRN + 8;  // padded LDS row of the Z stage
 
+template <typename T>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
-rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restrict__ Z, int64_t ldz,
-              double* __restrict__ C, int64_t ldc, int64_t M, int K, int N2, int upper) {
-  __shared__ double xs[2][kRM][kRK + 1];
-  __shared__ double zs[2][kRK][kZP];
+rotate_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int64_t ldz,
+              T* __restrict__ C, int64_t ldc, int64_t M, int K, int N2, int upper) {
+  __shared__ T xs[2][kRM][kRK + 1];
+  __shared__ T zs[2][kRK][kZP];
   const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRM);
   const int c0 = blockIdx.y * kRN;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wr = (wave / 2) * 32, wc = (wave % 2) * 64;
-  d4 acc[2][4];
+  using Acc = typename Mfma<T>::Acc;
+  Acc acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   int kend = K;
   if (upper && c0 + kRN < kend) kend = c0 + kRN;
   // loaders: X 64 rows x 16 k (4 per thread, 16 threads per row), Z 16 k x
@@ -203,7 +244,7 @@ rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restric
   // out-of-range values zeroed when stored to LDS
   const int xk = tid % kRK, xr = tid / kRK;
   const int zc = tid % kRN, zr = tid / kRN;
-  double gx[4], gz[8];
+  T gx[4], gz[8];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -226,12 +267,12 @@ rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restric
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const bool ok = r0 + xr + 16 * i < M && k0 + xk < K;
-      xs[buf][xr + 16 * i][xk] = ok ? gx[i] : 0.0;
+      xs[buf][xr + 16 * i][xk] = ok ? gx[i] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const bool ok = k0 + zr + 2 * i < K && c0 + zc < N2;
-      zs[buf][zr + 2 * i][zc] = ok ? gz[i] : 0.0;
+      zs[buf][zr + 2 * i][zc] = ok ? gz[i] : T(0);
     }
   };
   if (kend > 0) {
@@ -246,7 +287,7 @@ rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restric
 #pragma unroll
     for (int ks = 0; ks < kRK / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
-      double av[2], bv[4];
+      T av[2], bv[4];
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = xs[buf][wr + a * 16 + lane % 16][kr];
 #pragma unroll
@@ -254,7 +295,7 @@ rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restric
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mma(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mma(av[a], bv[b], acc[a][b]);
     }
     if (more) sstore(buf ^ 1, k0 + kRK);
     __syncthreads();
@@ -266,7 +307,7 @@ rotate_kernel(const double* __restrict__ X, int64_t ldx, const double* __restric
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t row = r0 + wr + a * 16 + acc_row(lane, i);
+        const int64_t row = r0 + wr + a * 16 + Mfma<T>::row(lane, i);
         const int col = c0 + wc + b * 16 + lane % 16;
         if (row < M && col < N2) C[row * ldc + col] = acc[a][b][i];
       }
@@ -329,6 +370,38 @@ __global__ void transpose_kernel(const double* __restrict__ in, double* __restri
   if (idx >= static_cast<int64_t>(n) * n) return;
   const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
   out[static_cast<int64_t>(j) * n + i] = in[idx];
+}
+
+// out (cols x rows, ldo) = in^T, in rows x cols (ldi), row-major
+__global__ void transpose_rect_kernel(const double* __restrict__ in, int64_t ldi, int rows, int cols,
+                                      double* __restrict__ out, int64_t ldo) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(rows) * cols) return;
+  const int i = static_cast<int>(idx / cols), j = static_cast<int>(idx % cols);
+  out[static_cast<int64_t>(j) * ldo + i] = in[static_cast<int64_t>(i) * ldi + j];
+}
+
+// Splits the upper-triangular n x n Z (row-major, ldz): Zo = FP32 copy with
+// the diagonal removed, d = the diagonal in FP64.
+__global__ void split_diag_kernel(const double* __restrict__ Z, int64_t ldz, int n, float* __restrict__ Zo,
+                                  double* __restrict__ d) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  const double z = Z[static_cast<int64_t>(i) * ldz + j];
+  Zo[idx] = i == j ? 0.0f : static_cast<float>(z);
+  if (i == j) d[i] = z;
+}
+
+// X[r][j] <- C[r][j] + d[j] X[r][j]   (C in FP32, X and d in FP64)
+__global__ void add_scaled_cols_kernel(const float* __restrict__ C, int64_t ldc, const double* __restrict__ d,
+                                       double* __restrict__ X, int64_t ldx, int64_t M, int n) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= M * n) return;
+  const int64_t r = idx / n;
+  const int j = static_cast<int>(idx % n);
+  double* x = X + r * ldx + j;
+  *x = static_cast<double>(C[r * ldc + j]) + d[j] * *x;
 }
 
 __global__ void zero_strict_lower_kernel(double* A, int n, int64_t lda) {
@@ -401,8 +474,10 @@ size_t gram_partial_bytes(int64_t M, int n, int64_t ld) {
   return static_cast<size_t>(gram_chunks(M, n, ld)) * npad * npad * sizeof(double);
 }
 
-hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
-                       double* partial, double* G, int64_t ldg, hipStream_t s) {
+template <typename T>
+hipError_t gram_t(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t M, int n, double* partial,
+                  double* G, int64_t ldg, hipStream_t s, int64_t offx, int64_t offy) {
+  if (offx < 0 || offy < 0 || offx + n > ldx || offy + n > ldy) return hipErrorInvalidValue;
   if (n <= 0) return hipSuccess;
   const int nt = (n + kGT - 1) / kGT;
   const int ntiles = nt * (nt + 1) / 2;
@@ -411,10 +486,21 @@ hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ld
   int64_t rpc = (M + nch - 1) / nch;
   rpc = (rpc + 15) / 16 * 16;
   nch = static_cast<int>((M + rpc - 1) / rpc);   // rounding rpc up can leave trailing chunks empty
-  hipLaunchKernelGGL(gram_kernel, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial);
+  hipLaunchKernelGGL(gram_kernel<T>, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial,
+                     offx, offy);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
                      partial, nch, n, npad, G, ldg);
   return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t M, int n,
+                       double* partial, double* G, int64_t ldg, hipStream_t s, int64_t offx, int64_t offy) {
+  return gram_t(X, ldx, Y, ldy, M, n, partial, G, ldg, s, offx, offy);
+}
+
+hipError_t launch_gram(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t M, int n,
+                       double* partial, double* G, int64_t ldg, hipStream_t s, int64_t offx, int64_t offy) {
+  return gram_t(X, ldx, Y, ldy, M, n, partial, G, ldg, s, offx, offy);
 }
 
 hipError_t launch_sym_from_lower(const double* G, int64_t ldg, double* S, int n, hipStream_t s) {
@@ -429,14 +515,25 @@ hipError_t launch_gram_combine_complex(const double* G2, int64_t ldg2, double* S
   return hipGetLastError();
 }
 
-hipError_t launch_rotate(const double* X, int64_t ldx, const double* Z, int64_t ldz, double* C, int64_t ldc,
-                         int64_t M, int K, int N2, bool upper, hipStream_t s) {
+template <typename T>
+hipError_t rotate_t(const T* X, int64_t ldx, const T* Z, int64_t ldz, T* C, int64_t ldc, int64_t M, int K, int N2,
+                    bool upper, hipStream_t s) {
   if (M <= 0 || N2 <= 0) return hipSuccess;
   const int64_t gx = (M + kRM - 1) / kRM;
   if (gx > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rotate_kernel, dim3(static_cast<unsigned>(gx), (N2 + kRN - 1) / kRN), dim3(256), 0, s, X,
+  hipLaunchKernelGGL(rotate_kernel<T>, dim3(static_cast<unsigned>(gx), (N2 + kRN - 1) / kRN), dim3(256), 0, s, X,
                      ldx, Z, ldz, C, ldc, M, K, N2, upper ? 1 : 0);
   return hipGetLastError();
+}
+
+hipError_t launch_rotate(const double* X, int64_t ldx, const double* Z, int64_t ldz, double* C, int64_t ldc,
+                         int64_t M, int K, int N2, bool upper, hipStream_t s) {
+  return rotate_t(X, ldx, Z, ldz, C, ldc, M, K, N2, upper, s);
+}
+
+hipError_t launch_rotate(const float* X, int64_t ldx, const float* Z, int64_t ldz, float* C, int64_t ldc,
+                         int64_t M, int K, int N2, bool upper, hipStream_t s) {
+  return rotate_t(X, ldx, Z, ldz, C, ldc, M, K, N2, upper, s);
 }
 
 size_t resid_partial_count(int64_t M, int ncols) {
@@ -471,6 +568,28 @@ hipError_t launch_axpby(double a, const double* x, double b, double* y, int64_t 
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(axpby_kernel, dim3(static_cast<unsigned>(g)), dim3(256), 0, s, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_rect(const double* in, int64_t ldi, int rows, int cols, double* out, int64_t ldo,
+                                 hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_rect_kernel, dim3(blocks_for(static_cast<int64_t>(rows) * cols)), dim3(256), 0, s,
+                     in, ldi, rows, cols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_diag(const double* Z, int64_t ldz, int n, float* Zo, double* d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_diag_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s, Z, ldz, n,
+                     Zo, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_scaled_cols(const float* C, int64_t ldc, const double* d, double* X, int64_t ldx, int64_t M,
+                                  int n, hipStream_t s) {
+  if (M <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_scaled_cols_kernel, dim3(blocks_for(M * n)), dim3(256), 0, s, C, ldc, d, X, ldx, M, n);
   return hipGetLastError();
 }
 
