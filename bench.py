@@ -26,9 +26,11 @@ c2 (time to Delta E <= 1e-6 Ha at N = 1024 for FP64, FP32, BF16 and the
 mixed schedule), c3 (32 batched complex k-point problems, sequential vs
 persistent launch vs hipGraph, complex128 vs complex64), c4 (learned warm
 start: training on solver output, passes saved on held-out configurations)
-kernels (one 128-column filter step per precision) and density (electron
+kernels (one 128-column filter step per precision), density (electron
 density of the c2 block at the nodes and at the Gauss points of every cell,
-with the Fermi level).
+with the Fermi level) and rrgep (the spectrum-splitting Rayleigh-Ritz step in
+FP64 and in the paper's mixed precision: time at the c2 block size, accuracy
+on a converged c4 problem).
 """
 from __future__ import annotations
 
@@ -101,11 +103,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "kernels", "density"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4", "kernels", "density", "rrgep"],
                     help="c1: FP64 pass at production size (the headline line); c2: mixed precision "
                          "time-to-accuracy at N=1024; c3: batched k-point solves; c4: learned warm start; "
                          "kernels: one 128-column filter step per precision; density: electron density "
-                         "of the c2 block")
+                         "of the c2 block; rrgep: spectrum-splitting Rayleigh-Ritz, FP64 vs mixed")
     ap.add_argument("--out", default=None, help="write per-pass histories (npz) here")
     ap.add_argument("--max-passes", type=int, default=0, help="c2: pass cap per run (0: default)")
     ap.add_argument("--c2-runs", default="f32,mixed,bf16", help="c2: runs beside the FP64 reference")
@@ -127,6 +129,8 @@ def main():
         return run_kernels(args)
     if args.workload == "density":
         return run_density(args)
+    if args.workload == "rrgep":
+        return run_rrgep(args)
     return run_c1(args)
 
 
@@ -687,6 +691,95 @@ def run_density(args):
            "kernels": res}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = density_oracle_sample(s, X, w, op.E)
+    print(json.dumps(out), flush=True)
+
+
+def run_rrgep(args):
+    """Spectrum-splitting Rayleigh-Ritz (Algorithm 2) in FP64 and in the
+    paper's mixed precision.  Time: the c1 operator with a c2-sized filtered
+    block (M = 2,985,984, N = 1152 FP64 columns, N_fr = 128 fractionally
+    occupied states, about 11 % of N), beside the orthonormalise-then-project
+    route (CholGS + Rayleigh-Ritz with all N Ritz vectors and residuals) the
+    solver uses.  Accuracy: a c4 problem solved to max r <= 1e-6, filtered
+    once more (m = 30), then the split step in both precisions: top-N_fr
+    Ritz values and the spectrum-split density against FP64."""
+    import numpy as np
+    import torch
+
+    import paper_2203_07820_amd as lib
+    import workloads
+
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+    steps = max(1, args.steps)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        fn()
+        e1.record(ctx.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    # ---- accuracy on a converged c4 problem
+    s4 = workloads.config("c4", 1800)
+    op4 = lib.Operator(ctx, s4)
+    N4, nb4, nfr4 = 128, 32, 16
+    X4 = torch.from_numpy(workloads.start_block(op4.M, N4 + nb4, seed=7)).cuda()
+    th4, r4, st4 = op4.solve(X4, N4, m=30, block=128, n_buf=nb4, tol=1e-6, max_passes=100)
+    b4, _ = op4.bounds(20, seed=1)
+    op4.filter(X4, 30, float(th4[-1]), b4, float(th4[0]))
+    outs = {}
+    for mode in (False, True):
+        Xm = X4[:, :N4].clone()
+        Pm = torch.empty(op4.M, nfr4, dtype=torch.float64, device="cuda")
+        th = op4.rayleigh_ritz_split(Xm, nfr4, Pm, mixed=mode)
+        mu, f = lib.fermi_level(th, 2.0 * (N4 - nfr4) + 8.0, 500.0 * 3.166811563e-6)
+        f[:N4 - nfr4] = 1.0
+        rho = torch.zeros(op4.M, dtype=torch.float64, device="cuda")
+        op4.density(Xm, np.full(N4, 2.0), rho)
+        op4.density(Pm, 2.0 * (f[N4 - nfr4:] - 1.0), rho, accumulate=True)
+        outs[mode] = (th, rho.cpu().numpy())
+    th64, rho64 = outs[False]
+    thmx, rhomx = outs[True]
+    acc = {"passes_to_converge": int(st4["passes"]), "N": N4, "nfr": nfr4,
+           "max_dtheta_top_nfr_Ha": float(np.max(np.abs(thmx[N4 - nfr4:] - th64[N4 - nfr4:]))),
+           "max_dtheta_all_Ha": float(np.max(np.abs(thmx - th64))),
+           "density_rel_err": float(np.max(np.abs(rhomx - rho64)) / np.max(np.abs(rho64))),
+           "final_max_resid": float(np.max(r4[:N4]))}
+    log(f"# accuracy (c4): top-N_fr dtheta {acc['max_dtheta_top_nfr_Ha']:.2e} Ha, all {acc['max_dtheta_all_Ha']:.2e},"
+        f" density {acc['density_rel_err']:.2e}")
+    del X4, op4
+    # ---- time at the c2 block size
+    s1 = workloads.config("c1")
+    op = lib.Operator(ctx, s1)
+    N, nfr = 1152, 128
+    g = torch.Generator(device="cuda").manual_seed(71)
+    X0 = torch.randn(op.M, N, dtype=torch.float64, device="cuda", generator=g)
+    X = torch.empty_like(X0)
+    P = torch.empty(op.M, nfr, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, fn in (("split_fp64", lambda: op.rayleigh_ritz_split(X, nfr, P, mixed=False)),
+                     ("split_mixed", lambda: op.rayleigh_ritz_split(X, nfr, P, mixed=True)),
+                     ("cholgs_rr_fp64", lambda: (op.orthonormalize(X), op.rayleigh_ritz(X)))):
+        X.copy_(X0)
+        fn()                                  # warm-up (workspace growth)
+        ms = []
+        for _ in range(steps):
+            X.copy_(X0)
+            ms.append(timed(fn))
+        res[name] = {"ms": float(np.mean(ms))}
+        log(f"# {name}: {res[name]['ms']:.1f} ms")
+    out = {"metric": "spectrum-splitting Rayleigh-Ritz step, mixed precision vs FP64 (c2 block size)",
+           "value": res["split_fp64"]["ms"] / res["split_mixed"]["ms"], "unit": "x speed-up",
+           "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": res["split_mixed"]["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 / f32 blocks", "data": "synthetic",
+           "config": {"workload": "rrgep: c1 operator (24^3 cells, p=6, M=2985984) with a 1152-column FP64 "
+                                  "block, N_fr=128; accuracy on a converged c4 problem (N=128, N_fr=16)",
+                      "N": N, "nfr": nfr, "M": op.M},
+           "modes": res, "accuracy": acc}
     print(json.dumps(out), flush=True)
 
 
