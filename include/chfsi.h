@@ -198,6 +198,18 @@ int chfsi_abi_sizes(int64_t* system, int64_t* params, int64_t* stats);
  * [2, 7] or a mesh of 2^29 nodes or more.  Synchronous. */
 int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
 int chfsi_op_destroy(chfsi_op* op);
+
+/* The same operator with the local potential integrated per cell by the
+ * (p+1)^3-point Gauss rule instead of collocated at the nodes: the
+ * discrete-Hamiltonian construction of Section 4.2 (Eq. quadLocal, with all
+ * cells' matrices K^loc_e[j,k] = sum_q N_j N_k V w_q |J| formed as one
+ * GEMM, Eq. gemmLoc).  Every cell then has its own real cell matrix
+ * D_c (K^c/2 + K^loc_e) D_c (imaginary k-part shared), stored per cell in
+ * FP64 and FP32 (E x mpad^2 each: 13.7 + 6.9 GB at 24^3 cells, p = 6); the
+ * diagonal keeps |k|^2/2.  All functions accept the result; the filter
+ * precisions are F64 and F32 (C128 and C64 for k != 0): BF16 returns
+ * CHFSI_EINVAL.  Same arguments and ownership as chfsi_op_build(). */
+int chfsi_op_build_quadrature(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
 /* M nodes, E cells, mcell = (p+1)^3 nodes per cell, nproj = 4 * natoms (0
  * without projectors), npairs = number of (cell, atom) pairs, is_complex. */
 int chfsi_op_info(const chfsi_op* op, int64_t* M, int64_t* E, int32_t* mcell,

@@ -204,9 +204,13 @@ class Context:
 
 class Operator:
     """The operator H~(k) of one system (``workloads.System`` or any object
-    with the same fields)."""
+    with the same fields).  potential="quadrature" integrates the local
+    potential per cell by the Gauss rule (chfsi_op_build_quadrature)
+    instead of collocating it at the nodes."""
 
-    def __init__(self, ctx: Context, sys):
+    def __init__(self, ctx: Context, sys, potential: str = "nodal"):
+        if potential not in ("nodal", "quadrature"):
+            raise ValueError("potential must be 'nodal' or 'quadrature'")
         self.ctx = ctx
         lib = ctx.lib
         na = int(sys.pos.shape[0])
@@ -237,7 +241,8 @@ class Operator:
         h = C.c_void_p()
         if not getattr(ctx, "h", None):
             raise ValueError("context is closed")
-        ctx.check(lib.chfsi_op_build(ctx.h, C.byref(s), C.byref(h)))
+        build = lib.chfsi_op_build if potential == "nodal" else lib.chfsi_op_build_quadrature
+        ctx.check(build(ctx.h, C.byref(s), C.byref(h)))
         self.h = h
         ctx._ops.add(self)
         self._keep.clear()

@@ -22,7 +22,7 @@ EXPORTS = [
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
     "chfsi_initial_block", "chfsi_next_prec", "chfsi_fermi_level", "chfsi_density",
-    "chfsi_rayleigh_ritz_split",
+    "chfsi_rayleigh_ritz_split", "chfsi_op_build_quadrature",
 ]
 
 
@@ -81,6 +81,7 @@ def load() -> C.CDLL:
         "chfsi_abi_sizes": (C.c_int, [C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
         "chfsi_op_build": (C.c_int, [vp, C.POINTER(System), C.POINTER(vp)]),
         "chfsi_op_destroy": (C.c_int, [vp]),
+        "chfsi_op_build_quadrature": (C.c_int, [vp, C.POINTER(System), C.POINTER(vp)]),
         "chfsi_op_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
                                     C.POINTER(i64), C.POINTER(i32)]),
         "chfsi_op_tables": (C.c_int, [vp, pd, pd, pd, pd, pd]),

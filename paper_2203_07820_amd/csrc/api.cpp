@@ -56,7 +56,8 @@ int upload_f32(chfsi_op* op, const std::vector<double>& v, void** out) {
 
 bool prec_valid_for(const chfsi_op* op, int prec) {
   if (op->t.cplx) return prec == CHFSI_C128 || prec == CHFSI_C64;
-  return prec == CHFSI_F64 || prec == CHFSI_F32 || prec == CHFSI_BF16;
+  // per-cell matrices exist in FP64 and FP32 only
+  return prec == CHFSI_F64 || prec == CHFSI_F32 || (prec == CHFSI_BF16 && op->astride == 0);
 }
 
 size_t prec_bytes(int prec) {
@@ -116,6 +117,7 @@ HxLaunch make_hx(const chfsi_op* op, int prec, const void* Xk, int64_t ldx, cons
   L.ncols = static_cast<int>(ncols * cf);
   L.cplx = t.cplx;
   L.A = single ? op->A32 : op->A64;
+  L.astride = op->astride;
   L.Ai = single ? op->Ai32 : op->Ai64;
   L.vdiag = op->vdiag;
   L.Xk = Xk;
@@ -1082,6 +1084,142 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   std::vector<double>().swap(t.pair_im);
   *out = op.release();
   return 0;
+}
+
+// Replaces the nodal (collocated) local potential of a freshly built
+// operator by the per-cell Gauss-quadrature one (Section 4.2): V~ on the
+// device, K^loc = P V~ as one GEMM, per-cell matrices A_e = A + D_c K^loc_e D_c
+// in FP64 and FP32, and a diagonal that keeps only |k|^2 / 2.
+int build_quadrature_potential(chfsi_op* op, const chfsi_system* sys) {
+  chfsi_ctx* ctx = op->ctx;
+  HostTables& t = op->t;
+  const int p = t.p, q = p + 1, nq = q * q * q, mc = t.mcell, mp = t.mpad;
+  const int64_t E = t.E, msym = static_cast<int64_t>(mc) * (mc + 1) / 2;
+  // basis products at the Gauss points, pairs j <= k (j-major) by points
+  std::vector<double> Nq(static_cast<size_t>(nq) * mc);
+  for (int qp = 0; qp < nq; ++qp) {
+    const int qx = qp % q, qy = (qp / q) % q, qz = qp / (q * q);
+    for (int l = 0; l < mc; ++l) {
+      const int ax = l % q, ay = (l / q) % q, az = l / (q * q);
+      Nq[static_cast<size_t>(qp) * mc + l] = t.interp[qx * q + ax] * t.interp[qy * q + ay] * t.interp[qz * q + az];
+    }
+  }
+  std::vector<double> P(static_cast<size_t>(msym) * nq);
+  for (int qp = 0; qp < nq; ++qp) {
+    const double* n = &Nq[static_cast<size_t>(qp) * mc];
+    int64_t r = 0;
+    for (int j = 0; j < mc; ++j)
+      for (int k = j; k < mc; ++k) P[static_cast<size_t>(qp) * msym + r++] = n[j] * n[k];
+  }
+  // Gauss rule and the cell's Loewdin scale per local node
+  std::vector<double> gq(q), gw(q), Dl(mc);
+  gauss_legendre_rule(q, gq, gw);
+  for (int l = 0; l < mc; ++l) {
+    const int ax = l % q, ay = (l / q) % q, az = l / (q * q);
+    const int64_t nd = (ax % t.n) + static_cast<int64_t>(t.n) * ((ay % t.n) + static_cast<int64_t>(t.n) * (az % t.n));
+    Dl[l] = t.dscale[nd];
+  }
+  std::vector<double> atoms(static_cast<size_t>(std::max(1, sys->natoms)) * 8, 0.0);
+  for (int a = 0; a < sys->natoms; ++a) {
+    atoms[8 * a + 0] = sys->pos[3 * a];
+    atoms[8 * a + 1] = sys->pos[3 * a + 1];
+    atoms[8 * a + 2] = sys->pos[3 * a + 2];
+    atoms[8 * a + 3] = sys->Z[a];
+    atoms[8 * a + 4] = sys->s[a];
+  }
+  std::vector<void*> tmp;
+  auto dalloc = [&](size_t bytes, void** out) -> int {
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) return fail(ctx, CHFSI_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    tmp.push_back(*out);
+    return 0;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* v : tmp) (void)hipFree(v);
+  };
+  int rc = 0;
+  do {
+    void *dP, *dV, *dK, *dA, *dgq, *dgw, *dD, *dAt;
+    if ((rc = dalloc(P.size() * 8, &dP)) < 0) break;
+    if ((rc = dalloc(static_cast<size_t>(nq) * E * 8, &dV)) < 0) break;
+    if ((rc = dalloc(static_cast<size_t>(msym) * E * 8, &dK)) < 0) break;
+    if ((rc = dalloc(q * 8, &dgq)) < 0 || (rc = dalloc(q * 8, &dgw)) < 0) break;
+    if ((rc = dalloc(mc * 8, &dD)) < 0 || (rc = dalloc(atoms.size() * 8, &dAt)) < 0) break;
+    hipStream_t st = ctx->stream;
+    if (hipMemcpy(dP, P.data(), P.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dgq, gq.data(), q * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dgw, gw.data(), q * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dD, Dl.data(), mc * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dAt, atoms.data(), atoms.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "upload of the quadrature tables failed");
+      break;
+    }
+    if (launch_gauss_potential(static_cast<double*>(dAt), sys->natoms, t.L, t.ncell, p, static_cast<double*>(dgq),
+                               static_cast<double*>(dgw), static_cast<double*>(dV), st) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "Gauss-point potential launch failed");
+      break;
+    }
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, static_cast<rocblas_int>(msym),
+                      static_cast<rocblas_int>(E), nq, &one, static_cast<double*>(dP),
+                      static_cast<rocblas_int>(msym), static_cast<double*>(dV), nq, &zero, static_cast<double*>(dK),
+                      static_cast<rocblas_int>(msym)) != rocblas_status_success) {
+      rc = fail(ctx, CHFSI_EHIP, "cell potential GEMM failed");
+      break;
+    }
+    const int64_t per = static_cast<int64_t>(mp) * mp;
+    hipError_t e = hipMalloc(&dA, static_cast<size_t>(E) * per * 8);
+    if (e != hipSuccess) {
+      rc = fail(ctx, CHFSI_ENOMEM, "per-cell matrices do not fit");
+      break;
+    }
+    op->allocs.push_back(dA);
+    if (launch_assemble_cell_matrices(static_cast<const double*>(op->A64), static_cast<double*>(dK), msym,
+                                      static_cast<double*>(dD), mc, mp, E, static_cast<double*>(dA), st) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "cell matrix assembly launch failed");
+      break;
+    }
+    void* dA32;
+    e = hipMalloc(&dA32, static_cast<size_t>(E) * per * 4);
+    if (e != hipSuccess) {
+      rc = fail(ctx, CHFSI_ENOMEM, "per-cell FP32 matrices do not fit");
+      break;
+    }
+    op->allocs.push_back(dA32);
+    if (launch_convert(dA32, per, CHFSI_F32, dA, per, CHFSI_F64, E, per, st) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "cell matrix conversion launch failed");
+      break;
+    }
+    // the diagonal keeps |k|^2 / 2 only
+    const double k2 = 0.5 * (t.k[0] * t.k[0] + t.k[1] * t.k[1] + t.k[2] * t.k[2]);
+    t.vdiag.assign(static_cast<size_t>(t.M), k2);
+    if (hipMemcpy(op->vdiag, t.vdiag.data(), t.M * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "diagonal upload failed");
+      break;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(ctx, CHFSI_EHIP, "quadrature potential build failed");
+      break;
+    }
+    op->A64 = dA;
+    op->A32 = dA32;
+    op->astride = per;
+  } while (0);
+  cleanup();
+  return rc;
+}
+
+int chfsi_op_build_quadrature(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (!sys || !out) return fail(ctx, CHFSI_EINVAL, "null argument");
+  CHECK(chfsi_op_build(ctx, sys, out));
+  const int rc = build_quadrature_potential(*out, sys);
+  if (rc < 0) {
+    chfsi_op_destroy(*out);
+    *out = nullptr;
+  }
+  return rc;
 }
 
 int chfsi_op_destroy(chfsi_op* op) {

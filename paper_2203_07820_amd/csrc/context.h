@@ -64,6 +64,7 @@ struct chfsi_op {
   void* Abf = nullptr;                          // bf16, 16x16x32 operand order
   double* vdiag = nullptr;
   double* dscale = nullptr;     // M^-1/2 per node (density)
+  int64_t astride = 0;          // per-cell real cell matrices (quadrature potential): elements per cell
   int64_t* atom_ptr = nullptr;
   int32_t* atom_node = nullptr;
   double* atom_val = nullptr;

@@ -51,6 +51,9 @@ struct HostTables {
   std::vector<double> atoms;        // natoms x 8: x, y, z, Z, s, h_s, h_p, 0
 };
 
+// n-point Gauss-Legendre nodes and weights on [-1, 1] (op_build.cpp).
+void gauss_legendre_rule(int n, std::vector<double>& x, std::vector<double>& w);
+
 // Builds the tables on the host (op_build.cpp).  Returns "" or an error text.
 std::string build_tables(const chfsi_system& sys, HostTables& t);
 
@@ -83,6 +86,7 @@ struct HxLaunch {
   const void* pair_re; const void* pair_im;
   const void* hP; int64_t ldhp;    // scaled projector coefficients (real view)
   const void* Abf = nullptr;       // bf16 cell matrix in 16x16x32 operand order
+  int64_t astride = 0;             // per-cell real matrices: elements per cell (0: shared)
 };
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).
@@ -134,6 +138,14 @@ struct DensityLaunch {
   const double* interp;             // host, (p+1) x (p+1)
 };
 hipError_t launch_density(const DensityLaunch& d, hipStream_t s);
+
+// Per-cell local potential by Gauss quadrature (kernels_dhm.hip).
+// Vw[e * nq + q] = V(x_q^e) w_q |J| for the (p+1)^3 Gauss points of every cell.
+hipError_t launch_gauss_potential(const double* atoms, int natoms, double L, int nc, int p, const double* gq,
+                                  const double* gw, double* Vw, hipStream_t s);
+// Ae (E x mpad^2, A-operand order) = Ash + D_i D_k Kloc_e[pair(i, k)].
+hipError_t launch_assemble_cell_matrices(const double* Ash, const double* Kloc, int64_t msym, const double* Dl,
+                                         int mcell, int mpad, int64_t E, double* Ae, hipStream_t s);
 
 // Elementwise helpers on row-major blocks (real view).
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);

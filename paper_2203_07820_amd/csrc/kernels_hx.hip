@@ -94,6 +94,7 @@ struct HxArgs {
   const T* pair_im;
   const T* hP;
   int64_t ldhp;
+  int64_t astride;  // elements between the real cell matrices of consecutive cells (0: one shared)
 };
 
 // Buffer resource over `bytes` bytes at p (raw buffer, 32-bit words).
@@ -273,7 +274,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     constexpr int RI = CPLX ? RPW : 1;
     constexpr int CI = CPLX ? CPW : 1;
     const uint32_t abytes = static_cast<uint32_t>(RT) * KS * 64 * sizeof(T);
-    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.A, abytes);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.A + static_cast<int64_t>(cell) * a.astride, abytes);
     const __amdgpu_buffer_rsrc_t rai = make_rsrc(CPLX ? a.Ai : a.A, abytes);
     int soff[RPW];
 #pragma unroll
@@ -557,6 +558,7 @@ HxArgs<T> pack_args(const HxLaunch& L) {
   a.pair_im = static_cast<const T*>(L.pair_im);
   a.hP = static_cast<const T*>(L.hP);
   a.ldhp = L.ldhp;
+  a.astride = L.astride;
   return a;
 }
 

@@ -150,6 +150,8 @@ void swizzle_cell_matrix_bf16(const double* A, int mcell, uint16_t* out) {
         }
 }
 
+void gauss_legendre_rule(int n, std::vector<double>& x, std::vector<double>& w) { gauss_rule(n, x, w); }
+
 std::string build_tables(const chfsi_system& sys, HostTables& t) {
   const int p = sys.p, nc = sys.ncell, q = p + 1;
   t.p = p;
