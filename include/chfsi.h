@@ -344,6 +344,48 @@ int chfsi_fermi_level(const double* theta, int32_t n, const double* weights, dou
 int chfsi_density(chfsi_op* op, const void* X, int64_t ncols, int64_t ld, const double* w, int32_t points,
                   int32_t accumulate, double* rho);
 
+/* ---- self-consistent field loop (Section 3, Algorithm 1) ----------------------
+ * chfsi_op_set_potential: replaces the nodal local potential of a real or
+ * complex operator built by chfsi_op_build() with V (device, M values, Ha);
+ * |k|^2/2 is added as at build time.  chfsi_op_tables() keeps reporting the
+ * build-time potential.  CHFSI_EINVAL for an operator from
+ * chfsi_op_build_quadrature().  Asynchronous (synchronous when k != 0). */
+int chfsi_op_set_potential(chfsi_op* op, const double* V);
+
+/* Hartree potential of the density rho (device, M nodal values): the
+ * periodic Poisson problem -lap v = 4 pi (rho - rho_bar) in the FE basis,
+ * K v = 4 pi M (rho - rho_bar) with rho_bar the mean charge and
+ * sum_j M_jj v_j = 0, solved as D K D u = 4 pi M^1/2 (rho - rho_bar),
+ * v = D u, by Jacobi-preconditioned CG (the paper's Poisson solver) to a
+ * relative residual tol, at most maxit iterations.  vH: device, M values.
+ * iters / relres (nullable) receive the iteration count and the final
+ * relative residual.  Real operators with a nodal potential only.  Returns
+ * CHFSI_NOTCONV if tol was not reached.  Synchronous. */
+int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32_t maxit, int32_t* iters,
+                  double* relres);
+
+/* A self-consistent field loop around the eigensolver (Algorithm 1 with a
+ * synthetic exchange-correlation term): per step, the Hartree potential of
+ * the input density (chfsi_hartree, tol 1e-10), V = V_ext + v_H + v_x with
+ * V_ext the operator's build-time potential and LDA exchange
+ * v_x = -(3 rho / pi)^(1/3), one ChFSI pass on X (four on the first step,
+ * which starts by orthonormalising X), the Fermi level of the nwanted lowest
+ * Ritz values (kT, n_electrons), the nodal output density, and Anderson
+ * mixing of the density (weight beta, the last `depth` differences,
+ * M-weighted inner products).  Stops when the M-weighted norm of
+ * rho_out - rho_in falls below tol or after maxit steps.
+ * X: device, M x ld FP64, nwanted + n_buf columns (start block in, Ritz
+ * vectors out); rho: device, M values (initial density in; the converged
+ * output density, or the last mixed density if not converged, out); theta:
+ * host, nwanted + n_buf Ritz values of the last step; mu_out, res_hist
+ * (host, maxit values: the residual norm of every step) and iters nullable.
+ * m, block: filter degree and column block as in chfsi_params.  Real
+ * operators with a nodal potential; 0 < n_electrons < 2 nwanted.  Returns
+ * CHFSI_NOTCONV if tol was not met.  Synchronous. */
+int chfsi_scf(chfsi_op* op, void* X, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
+              double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit, double* rho,
+              double* theta, double* mu_out, double* res_hist, int32_t* iters);
+
 /* ---- batched filter (many operators, one persistent launch per step) -------
  * Applies the filter of chfsi_filter() to n independent blocks at once:
  * block q is X[q] (device, double / complex double, ncols[q] columns, ld[q])

@@ -304,6 +304,35 @@ class Operator:
                                                               int(bool(mixed)), _dptr(th), _bptr(Psi_fr), ldf))
         return th
 
+    def set_potential(self, V):
+        """chfsi_op_set_potential: nodal local potential V (device float64, M)."""
+        self.ctx.check(self.ctx.lib.chfsi_op_set_potential(self.h, _tptr(V)))
+
+    def hartree(self, rho, vH, tol: float = 1e-10, maxit: int = 5000):
+        """chfsi_hartree: vH <- Hartree potential of rho (device float64, M);
+        returns (iterations, relative residual)."""
+        it, rr = C.c_int32(), C.c_double()
+        self.ctx.check(self.ctx.lib.chfsi_hartree(self.h, _tptr(rho), _tptr(vH), float(tol), int(maxit),
+                                                  C.byref(it), C.byref(rr)), allow=(0, 1))
+        return it.value, rr.value
+
+    def scf(self, X, rho, nwanted: int, n_buf: int, n_electrons: float, kT: float, m: int = 20, block: int = 0,
+            beta: float = 0.3, depth: int = 4, tol: float = 1e-8, maxit: int = 60):
+        """chfsi_scf: self-consistent loop; X (start block -> Ritz vectors)
+        and rho (initial -> final density) are device tensors."""
+        ncols, ld = _ld_cols(X)
+        if ncols != nwanted + n_buf:
+            raise ValueError("X must have nwanted + n_buf columns")
+        th = np.zeros(ncols)
+        hist = np.zeros(maxit)
+        mu, it = C.c_double(), C.c_int32()
+        rc = self.ctx.check(self.ctx.lib.chfsi_scf(self.h, _tptr(X), ld, int(nwanted), int(n_buf), int(m), int(block),
+                                                   float(n_electrons), float(kT), float(beta), int(depth), float(tol),
+                                                   int(maxit), _tptr(rho), _dptr(th), C.byref(mu), _dptr(hist),
+                                                   C.byref(it)), allow=(0, 1))
+        return {"theta": th, "mu": mu.value, "iters": it.value, "residuals": hist[:it.value],
+                "converged": rc == 0}
+
     def bounds(self, steps: int = 20, v0=None, seed: int = 0):
         b, lmin = C.c_double(), C.c_double()
         self.ctx.check(self.ctx.lib.chfsi_bounds(self.h, int(steps), _tptr(v0), C.c_uint64(seed), C.byref(b),

@@ -22,7 +22,8 @@ EXPORTS = [
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
     "chfsi_initial_block", "chfsi_next_prec", "chfsi_fermi_level", "chfsi_density",
-    "chfsi_rayleigh_ritz_split", "chfsi_op_build_quadrature",
+    "chfsi_rayleigh_ritz_split", "chfsi_op_build_quadrature", "chfsi_op_set_potential", "chfsi_hartree",
+    "chfsi_scf",
 ]
 
 
@@ -115,6 +116,10 @@ def load() -> C.CDLL:
         "chfsi_fermi_level": (C.c_int, [pd, i32, pd, dbl, dbl, pd, pd]),
         "chfsi_density": (C.c_int, [vp, vp, i64, i64, pd, i32, i32, vp]),
         "chfsi_rayleigh_ritz_split": (C.c_int, [vp, vp, i64, i64, i32, i32, pd, vp, i64]),
+        "chfsi_op_set_potential": (C.c_int, [vp, vp]),
+        "chfsi_hartree": (C.c_int, [vp, vp, vp, dbl, i32, C.POINTER(i32), pd]),
+        "chfsi_scf": (C.c_int, [vp, vp, i64, i32, i32, i32, i32, dbl, dbl, dbl, i32, dbl, i32, vp, pd, pd, pd,
+                                C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

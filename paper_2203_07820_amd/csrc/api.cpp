@@ -915,6 +915,136 @@ int next_prec(int prec, const double* r, int k, double b) {
   return (floor_reached || growing) ? up : prec;
 }
 
+// ---- SCF loop helpers --------------------------------------------------------
+
+// Device tables of the SCF loop, built once per operator: the build-time
+// nodal potential V_ext, M^1/2, M, the diagonal of D K D (the Jacobi
+// preconditioner of the Hartree problem) and a zero vector.
+int scf_tables(chfsi_op* op) {
+  if (op->scf_tab) return 0;
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int64_t M = t.M;
+  const int p = t.p, q = p + 1, n = t.n;
+  std::vector<double> h(static_cast<size_t>(5) * M, 0.0);
+  double* vext = h.data();
+  double* sqm = vext + M;
+  double* mm = sqm + M;
+  double* kd = mm + M;
+  for (int64_t j = 0; j < M; ++j) {
+    vext[j] = t.vdiag[j];
+    sqm[j] = 1.0 / t.dscale[j];
+    mm[j] = sqm[j] * sqm[j];
+  }
+  // diag(D K D)_j = sum over the (cell, local index) pairs of node j of
+  // 2 A_ll, A = D_c (K^c / 2) D_c; along each axis a vertex-type index
+  // (i mod p = 0) is local index 0 of one cell and p of its neighbour
+  auto opts = [&](int i, int* o) -> int {
+    if (i % p == 0) {
+      o[0] = 0;
+      o[1] = p;
+      return 2;
+    }
+    o[0] = i % p;
+    return 1;
+  };
+  for (int iz = 0; iz < n; ++iz)
+    for (int iy = 0; iy < n; ++iy)
+      for (int ix = 0; ix < n; ++ix) {
+        int ox[2], oy[2], oz[2];
+        const int nx = opts(ix, ox), ny = opts(iy, oy), nz = opts(iz, oz);
+        double s = 0.0;
+        for (int c = 0; c < nz; ++c)
+          for (int b = 0; b < ny; ++b)
+            for (int a = 0; a < nx; ++a) {
+              const int64_t l = ox[a] + q * (oy[b] + static_cast<int64_t>(q) * oz[c]);
+              s += 2.0 * t.cell_re[l * t.mcell + l];
+            }
+        kd[ix + static_cast<int64_t>(n) * (iy + static_cast<int64_t>(n) * iz)] = s;
+      }
+  double* d;
+  CHECK(upload(op, h, &d));
+  op->scf_tab = d;
+  return 0;
+}
+
+// q = (D K D) u on the operator's mesh: the cell kernel with alpha = 2 on a
+// zero diagonal and no projectors (H~ without potential is D (K/2) D).
+int apply_stiffness(chfsi_op* op, const double* u, double* qv) {
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  HIP_TRY(ctx, launch_fill(qv, t.M, 1, 1, CHFSI_F64, ctx->stream));
+  HxLaunch L = make_hx(op, CHFSI_F64, u, 1, nullptr, 0, qv, 1, 1, 2.0, 0.0, 0.0, false, nullptr, 0);
+  L.vdiag = op->scf_tab + 4 * t.M;
+  L.pair_ptr = nullptr;
+  L.pair_atom = nullptr;
+  L.pair_re = nullptr;
+  L.pair_im = nullptr;
+  L.hP = nullptr;
+  HIP_TRY(ctx, launch_cell_hx(L, CHFSI_F64, ctx->stream));
+  return 0;
+}
+
+// Hartree potential: D K D u = 4 pi M^1/2 (rho - rho_bar), v_H = D u, by
+// Jacobi-preconditioned CG with the null vector M^1/2 1 projected out.
+// w: 6 M scratch values.
+int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int maxit, double* w, int* iters,
+                  double* relres) {
+  chfsi_ctx* ctx = op->ctx;
+  const int64_t M = op->t.M;
+  hipStream_t st = ctx->stream;
+  CHECK(scf_tables(op));
+  const double* sqm = op->scf_tab + M;
+  const double* mm = op->scf_tab + 2 * M;
+  const double* kd = op->scf_tab + 3 * M;
+  double *u = w, *r = w + M, *z = w + 2 * M, *pv = w + 3 * M, *qv = w + 4 * M, *b = w + 5 * M;
+  double q_tot = 0.0, m_tot = 0.0, zz = 0.0;
+  CHECK(dot_host(ctx, mm, rho, M, &q_tot));
+  CHECK(dot_host(ctx, sqm, sqm, M, &zz));   // = sum M
+  m_tot = zz;
+  HIP_TRY(ctx, launch_hartree_rhs(rho, q_tot / m_tot, sqm, b, M, st));
+  auto project = [&](double* x) -> int {   // x -= (x . n) n, n = M^1/2 1 / |.|
+    double xn = 0.0;
+    CHECK(dot_host(ctx, x, sqm, M, &xn));
+    HIP_TRY(ctx, launch_axpby(-xn / zz, sqm, 1.0, x, M, st));
+    return 0;
+  };
+  CHECK(project(b));
+  double bb = 0.0;
+  CHECK(dot_host(ctx, b, b, M, &bb));
+  HIP_TRY(ctx, launch_fill(u, M, 1, 1, CHFSI_F64, st));
+  HIP_TRY(ctx, launch_convert(r, 1, CHFSI_F64, b, 1, CHFSI_F64, M, 1, st));
+  HIP_TRY(ctx, launch_ediv(r, kd, z, M, st));
+  CHECK(project(z));
+  HIP_TRY(ctx, launch_convert(pv, 1, CHFSI_F64, z, 1, CHFSI_F64, M, 1, st));
+  double rz = 0.0, rr = bb;
+  CHECK(dot_host(ctx, r, z, M, &rz));
+  int it = 0;
+  const double stop = tol * tol * bb;
+  while (it < maxit && rr > stop && bb > 0.0) {
+    CHECK(apply_stiffness(op, pv, qv));
+    double pq = 0.0;
+    CHECK(dot_host(ctx, pv, qv, M, &pq));
+    if (!(pq > 0.0)) break;
+    const double al = rz / pq;
+    HIP_TRY(ctx, launch_axpby(al, pv, 1.0, u, M, st));
+    HIP_TRY(ctx, launch_axpby(-al, qv, 1.0, r, M, st));
+    CHECK(dot_host(ctx, r, r, M, &rr));
+    ++it;
+    if (rr <= stop) break;
+    HIP_TRY(ctx, launch_ediv(r, kd, z, M, st));
+    CHECK(project(z));
+    double rz1 = 0.0;
+    CHECK(dot_host(ctx, r, z, M, &rz1));
+    HIP_TRY(ctx, launch_axpby(1.0, z, rz1 / rz, pv, M, st));   // p = z + (rz1 / rz) p
+    rz = rz1;
+  }
+  HIP_TRY(ctx, launch_ediv(u, sqm, vh, M, st));   // v = D u
+  if (iters) *iters = it;
+  if (relres) *relres = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+  return 0;
+}
+
 void record_hist(const chfsi_params& p, int i, double t_ms, double maxr, int prec, const double* th, int64_t N) {
   if (i < 0 || i >= p.hist_len) return;
   if (p.hist_time_ms) p.hist_time_ms[i] = t_ms;
@@ -1437,6 +1567,205 @@ int chfsi_density(chfsi_op* op, const void* X, int64_t ncols, int64_t ld, const 
   d.interp = t.interp.data();
   HIP_TRY(ctx, launch_density(d, ctx->stream));
   return 0;
+}
+
+int chfsi_op_set_potential(chfsi_op* op, const double* V) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  if (!V) return fail(ctx, CHFSI_EINVAL, "null potential");
+  if (op->astride != 0) return fail(ctx, CHFSI_EINVAL, "the operator integrates its potential per cell");
+  const HostTables& t = op->t;
+  const double k2 = 0.5 * (t.k[0] * t.k[0] + t.k[1] * t.k[1] + t.k[2] * t.k[2]);
+  HIP_TRY(ctx, launch_convert(op->vdiag, 1, CHFSI_F64, V, 1, CHFSI_F64, t.M, 1, ctx->stream));
+  if (k2 != 0.0) {
+    void* one;
+    CHECK(ws_get(ctx, WS_VEC, static_cast<size_t>(t.M) * 8, &one));
+    std::vector<double> h(static_cast<size_t>(t.M), k2);
+    HIP_TRY(ctx, hipMemcpyAsync(one, h.data(), h.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, launch_axpby(1.0, static_cast<double*>(one), 1.0, op->vdiag, t.M, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return 0;
+}
+
+int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32_t maxit, int32_t* iters,
+                  double* relres) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  if (!rho || !vH) return fail(ctx, CHFSI_EINVAL, "null density or output");
+  if (op->t.cplx || op->astride != 0)
+    return fail(ctx, CHFSI_EINVAL, "the Hartree solve uses a real operator with a nodal potential");
+  if (!(tol > 0.0) || maxit < 1) return fail(ctx, CHFSI_EINVAL, "need tol > 0 and maxit >= 1");
+  void* w;
+  CHECK(ws_get(ctx, WS_SCF, static_cast<size_t>(op->t.M) * 6 * 8, &w));
+  int it = 0;
+  double rr = 0.0;
+  CHECK(hartree_solve(op, rho, vH, tol, maxit, static_cast<double*>(w), &it, &rr));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return rr <= tol ? 0 : CHFSI_NOTCONV;
+}
+
+int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
+              double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit, double* rho,
+              double* theta, double* mu_out, double* res_hist, int32_t* iters) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  const HostTables& t = op->t;
+  const int64_t N = static_cast<int64_t>(nwanted) + n_buf;
+  CHECK(check_block(op, Xv, N, ld));
+  if (t.cplx || op->astride != 0)
+    return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on a real operator with a nodal potential");
+  if (!rho || !theta) return fail(ctx, CHFSI_EINVAL, "null density or theta");
+  if (nwanted < 1 || n_buf < 0 || m < 1 || maxit < 1 || depth < 0 || depth > 16 || !(beta > 0.0) ||
+      !(kT > 0.0) || !(tol > 0.0) || !(n_electrons > 0.0) || !(n_electrons < 2.0 * nwanted))
+    return fail(ctx, CHFSI_EINVAL, "bad SCF parameters");
+  const int64_t M = t.M;
+  hipStream_t st = ctx->stream;
+  CHECK(scf_tables(op));
+  const double* vext = op->scf_tab;
+  const double* sqm = op->scf_tab + M;
+  const double* mm = op->scf_tab + 2 * M;
+  const int H = depth + 1;
+  // work: CG 6 M, vH, V, rho_in, rho_out, F, weighted F, 2 H history, 2 depth differences
+  const int64_t nvec = 6 + 6 + 2 * H + 2 * std::max(1, depth);
+  void* wv;
+  CHECK(ws_get(ctx, WS_SCF, static_cast<size_t>(M) * nvec * 8, &wv));
+  double* w = static_cast<double*>(wv);
+  double* cg = w;
+  double* vh = w + 6 * M;
+  double* V = vh + M;
+  double* rin = V + M;
+  double* rout = rin + M;
+  double* F = rout + M;
+  double* WF = F + M;
+  std::vector<double*> xs(H), fs(H), dX(std::max(1, depth)), dF(std::max(1, depth));
+  for (int i = 0; i < H; ++i) {
+    xs[i] = WF + M + static_cast<int64_t>(i) * M;
+    fs[i] = WF + M + static_cast<int64_t>(H + i) * M;
+  }
+  for (int i = 0; i < std::max(1, depth); ++i) {
+    dX[i] = WF + M + static_cast<int64_t>(2 * H + i) * M;
+    dF[i] = WF + M + static_cast<int64_t>(2 * H + std::max(1, depth) + i) * M;
+  }
+  HIP_TRY(ctx, launch_convert(rin, 1, CHFSI_F64, rho, 1, CHFSI_F64, M, 1, st));
+  chfsi_params prm{};
+  prm.nwanted = nwanted;
+  prm.n_buf = n_buf;
+  prm.m = m;
+  prm.block = block > 0 ? block : static_cast<int32_t>(N);
+  prm.filter_prec = CHFSI_F64;
+  std::vector<double> th(N), f(nwanted), occ(nwanted);
+  int hist = 0, it = 0;
+  bool conv = false;
+  double mu = 0.0;
+  for (it = 0; it < maxit; ++it) {
+    // potential of the input density
+    int cgit = 0;
+    double cgr = 0.0;
+    CHECK(hartree_solve(op, rin, vh, 1e-10, 5000, cg, &cgit, &cgr));
+    HIP_TRY(ctx, launch_veff(vext, vh, rin, V, M, st));
+    CHECK(chfsi_op_set_potential(op, V));
+    // eigensolver: the first step orthonormalises the start block and runs
+    // four passes, later steps one pass from the previous subspace
+    double b = 0.0;
+    CHECK(do_bounds(op, 20, nullptr, nullptr, 12345, &b, nullptr));
+    if (it == 0) {
+      CHECK(chfsi_orthonormalize(op, Xv, N, ld, nullptr));
+      CHECK(chfsi_rayleigh_ritz(op, Xv, N, ld, th.data(), nullptr));
+    }
+    const int passes = it == 0 ? 4 : 1;
+    for (int ps = 0; ps < passes; ++ps) {
+      const double a = th[N - 1], aL = th[0];
+      if (!(a < b)) return fail(ctx, CHFSI_EDIVERGE, "Ritz values above the spectrum bound");
+      CHECK(chfsi_pass(op, &prm, Xv, ld, a, b, aL, th.data(), nullptr));
+    }
+    // occupations and the output density
+    CHECK(chfsi_fermi_level(th.data(), nwanted, nullptr, n_electrons, kT, &mu, occ.data()));
+    for (int i = 0; i < nwanted; ++i) f[i] = 2.0 * occ[i];
+    CHECK(chfsi_density(op, Xv, nwanted, ld, f.data(), CHFSI_RHO_NODES, 0, rout));
+    // residual F = rho_out - rho_in in the M-weighted norm
+    HIP_TRY(ctx, launch_convert(F, 1, CHFSI_F64, rout, 1, CHFSI_F64, M, 1, st));
+    HIP_TRY(ctx, launch_axpby(-1.0, rin, 1.0, F, M, st));
+    HIP_TRY(ctx, launch_emul(F, mm, WF, M, st));
+    double r2 = 0.0;
+    CHECK(dot_host(ctx, F, WF, M, &r2));
+    const double res = std::sqrt(std::max(r2, 0.0));
+    if (res_hist) res_hist[it] = res;
+    if (res < tol) {
+      conv = true;
+      ++it;
+      break;
+    }
+    // Anderson mixing over the last `depth` differences
+    if (hist == H) {
+      std::rotate(xs.begin(), xs.begin() + 1, xs.end());
+      std::rotate(fs.begin(), fs.begin() + 1, fs.end());
+      --hist;
+    }
+    HIP_TRY(ctx, launch_convert(xs[hist], 1, CHFSI_F64, rin, 1, CHFSI_F64, M, 1, st));
+    HIP_TRY(ctx, launch_convert(fs[hist], 1, CHFSI_F64, F, 1, CHFSI_F64, M, 1, st));
+    ++hist;
+    const int nd = hist - 1;
+    std::vector<double> g(nd, 0.0);
+    if (nd > 0) {
+      for (int i = 0; i < nd; ++i) {
+        HIP_TRY(ctx, launch_convert(dX[i], 1, CHFSI_F64, xs[i + 1], 1, CHFSI_F64, M, 1, st));
+        HIP_TRY(ctx, launch_axpby(-1.0, xs[i], 1.0, dX[i], M, st));
+        HIP_TRY(ctx, launch_convert(dF[i], 1, CHFSI_F64, fs[i + 1], 1, CHFSI_F64, M, 1, st));
+        HIP_TRY(ctx, launch_axpby(-1.0, fs[i], 1.0, dF[i], M, st));
+      }
+      std::vector<double> A(static_cast<size_t>(nd) * nd), rv(nd);
+      for (int i = 0; i < nd; ++i) {
+        HIP_TRY(ctx, launch_emul(dF[i], mm, cg, M, st));   // M-weighted copy
+        CHECK(dot_host(ctx, cg, F, M, &rv[i]));
+        for (int j = 0; j <= i; ++j) {
+          CHECK(dot_host(ctx, cg, dF[j], M, &A[static_cast<size_t>(i) * nd + j]));
+          A[static_cast<size_t>(j) * nd + i] = A[static_cast<size_t>(i) * nd + j];
+        }
+      }
+      // least squares by Gaussian elimination with a tiny ridge
+      double tr = 0.0;
+      for (int i = 0; i < nd; ++i) tr += A[static_cast<size_t>(i) * nd + i];
+      for (int i = 0; i < nd; ++i) A[static_cast<size_t>(i) * nd + i] += 1e-12 * tr / nd;
+      g = rv;
+      for (int c = 0; c < nd; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < nd; ++r)
+          if (std::fabs(A[static_cast<size_t>(r) * nd + c]) > std::fabs(A[static_cast<size_t>(pr) * nd + c])) pr = r;
+        if (pr != c) {
+          for (int k = 0; k < nd; ++k) std::swap(A[static_cast<size_t>(c) * nd + k], A[static_cast<size_t>(pr) * nd + k]);
+          std::swap(g[c], g[pr]);
+        }
+        const double piv = A[static_cast<size_t>(c) * nd + c];
+        if (piv == 0.0) continue;
+        for (int r = c + 1; r < nd; ++r) {
+          const double fct = A[static_cast<size_t>(r) * nd + c] / piv;
+          for (int k = c; k < nd; ++k) A[static_cast<size_t>(r) * nd + k] -= fct * A[static_cast<size_t>(c) * nd + k];
+          g[r] -= fct * g[c];
+        }
+      }
+      for (int c = nd - 1; c >= 0; --c) {
+        double sacc = g[c];
+        for (int k = c + 1; k < nd; ++k) sacc -= A[static_cast<size_t>(c) * nd + k] * g[k];
+        const double piv = A[static_cast<size_t>(c) * nd + c];
+        g[c] = piv != 0.0 ? sacc / piv : 0.0;
+      }
+    }
+    // rho_in <- (x - dX g) + beta (F - dF g)
+    for (int i = 0; i < nd; ++i) {
+      HIP_TRY(ctx, launch_axpby(-g[i], dX[i], 1.0, rin, M, st));
+      HIP_TRY(ctx, launch_axpby(-g[i], dF[i], 1.0, F, M, st));
+    }
+    HIP_TRY(ctx, launch_axpby(beta, F, 1.0, rin, M, st));
+  }
+  HIP_TRY(ctx, launch_convert(rho, 1, CHFSI_F64, conv ? rout : rin, 1, CHFSI_F64, M, 1, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  std::memcpy(theta, th.data(), N * 8);
+  if (mu_out) *mu_out = mu;
+  if (iters) *iters = it;
+  return conv ? 0 : CHFSI_NOTCONV;
 }
 
 int chfsi_set_timing(chfsi_ctx* ctx, int32_t enable) {

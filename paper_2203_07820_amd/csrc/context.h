@@ -22,6 +22,7 @@ enum Slot {
   WS_DENS,                         // density weights
   WS_RR_G, WS_RR_S, WS_RR_H, WS_RR_Z, // split Rayleigh-Ritz: lower Gram, S, H^, rotation
   WS_X32, WS_W32, WS_C32,          // FP32 copies of X, H X and the FP32 rotation
+  WS_SCF,                          // SCF vectors (potentials, densities, CG, mixing history)
   WS_COUNT
 };
 
@@ -65,6 +66,7 @@ struct chfsi_op {
   double* vdiag = nullptr;
   double* dscale = nullptr;     // M^-1/2 per node (density)
   int64_t astride = 0;          // per-cell real cell matrices (quadrature potential): elements per cell
+  double* scf_tab = nullptr;    // SCF tables, 5 x M: V_ext, M^1/2, M, diag(D K D), zeros
   int64_t* atom_ptr = nullptr;
   int32_t* atom_node = nullptr;
   double* atom_val = nullptr;

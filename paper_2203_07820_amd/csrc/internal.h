@@ -147,6 +147,14 @@ hipError_t launch_gauss_potential(const double* atoms, int natoms, double L, int
 hipError_t launch_assemble_cell_matrices(const double* Ash, const double* Kloc, int64_t msym, const double* Dl,
                                          int mcell, int mpad, int64_t E, double* Ae, hipStream_t s);
 
+// SCF loop helpers (kernels_scf.hip), n values each.
+hipError_t launch_hartree_rhs(const double* rho, double rho_bar, const double* sqm, double* b, int64_t n,
+                              hipStream_t s);
+hipError_t launch_ediv(const double* x, const double* d, double* y, int64_t n, hipStream_t s);
+hipError_t launch_emul(const double* x, const double* d, double* y, int64_t n, hipStream_t s);
+hipError_t launch_veff(const double* vext, const double* vh, const double* rho, double* V, int64_t n,
+                       hipStream_t s);
+
 // Elementwise helpers on row-major blocks (real view).
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);
 // dst (type dprec) <- src (type sprec), rows x cols (real view)

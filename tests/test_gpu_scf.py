@@ -1,0 +1,95 @@
+"""Parity of the SCF pieces (chfsi_op_set_potential, chfsi_hartree,
+chfsi_scf) with the oracle's SCF loop.
+
+Tolerances.  Hartree: CG to a relative residual of 1e-12 on a problem with
+condition number ~1e3, so 1e-9 relative on v_H.  H~X after a potential
+change: FP64 products, 1e-12.  SCF: the fixed point does not depend on the
+eigensolver or the mixing path; both loops stop at an M-norm residual of
+1e-9, the GPU one with ChFSI subspaces converged alongside, so densities
+agree to 1e-6 of max rho, Ritz values and the Fermi level to 1e-6 Ha.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fe
+from oracle import scf as oscf
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2203_07820_amd as lib  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("nc,p,L", [(2, 4, 6.0), (3, 5, 7.5)])
+def test_hartree_matches_oracle(ctx, nc, p, L):
+    s = workloads.small_system(nc, p, 2, seed=3, L=L)
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    rho = np.random.default_rng(4).uniform(0.01, 0.5, op.M)
+    vh = torch.empty(op.M, dtype=torch.float64, device="cuda")
+    it, rr = op.hartree(dev(rho), vh, tol=1e-12, maxit=5000)
+    assert rr <= 1e-12
+    want = oscf.hartree(ref, rho)
+    got = vh.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want))
+    assert abs(float(np.sum(ref.Mdiag * got))) < 1e-9 * float(np.sum(ref.Mdiag * np.abs(got)))
+
+
+def test_set_potential_changes_the_operator(ctx):
+    s = workloads.small_system(3, 4, 2, seed=5, has_proj=True)
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    V = np.random.default_rng(6).uniform(-1.0, 1.0, op.M)
+    op.set_potential(dev(V))
+    H = oscf.hamiltonian(ref, V)
+    X = np.random.default_rng(7).standard_normal((op.M, 9))
+    Y = torch.zeros(op.M, 9, dtype=torch.float64, device="cuda")
+    op.apply(dev(X), Y)
+    want = H @ X
+    assert np.max(np.abs(Y.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_scf_reaches_the_oracle_fixed_point(ctx):
+    s = workloads.small_system(2, 4, 2, seed=7, L=6.0)
+    ref = oscf.scf(s, nstates=8, n_electrons=6.0, kT=0.01, beta=0.3, depth=4, tol=1e-9, maxit=80)
+    assert ref.converged
+    op = lib.Operator(ctx, s)
+    M = op.M
+    X = dev(workloads.start_block(M, 12, seed=8))
+    m = fe.build_operator(s).Mdiag
+    rho = dev(np.full(M, 6.0 / np.sum(m)))
+    out = op.scf(X, rho, nwanted=8, n_buf=4, n_electrons=6.0, kT=0.01, m=20, beta=0.3, depth=4, tol=1e-9,
+                 maxit=120)
+    assert out["converged"], out["residuals"][-5:]
+    got = rho.cpu().numpy()
+    assert abs(float(np.sum(m * got)) - 6.0) < 1e-9
+    assert np.max(np.abs(got - ref.rho)) <= 1e-6 * np.max(ref.rho)
+    assert np.max(np.abs(out["theta"][:8] - ref.theta)) < 1e-6
+    assert abs(out["mu"] - ref.mu) < 1e-6
+
+
+def test_scf_rejects_bad_arguments(ctx):
+    s = workloads.small_system(2, 3, 1, seed=9)
+    op = lib.Operator(ctx, s)
+    X = torch.randn(op.M, 6, dtype=torch.float64, device="cuda")
+    rho = torch.full((op.M,), 0.01, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.ChfsiError):
+        op.scf(X, rho, nwanted=4, n_buf=2, n_electrons=9.0, kT=0.01)     # more electrons than 2 nwanted
+    opq = lib.Operator(ctx, s, potential="quadrature")
+    with pytest.raises(lib.ChfsiError):
+        opq.set_potential(rho)
