@@ -267,16 +267,17 @@ int chfsi_rayleigh_ritz(chfsi_op* op, void* X, int64_t ncols, int64_t ld, double
 /* Rayleigh-Ritz through the generalised eigenproblem with spectrum splitting
  * (Algorithm 2 of Section 3.2: RRGEP-O, -P, -D, -ST-F, -ST-O), with the
  * mixed-precision scheme of Sections 3.2 and 4.4 when mixed != 0.
- * X: device, M x ld FP64, the filtered block Psi_f (ncols = N columns, not
- * orthonormal); on return it holds the orthonormal basis Psi_o = Psi_f L^-T
- * (S = Psi_f^T Psi_f = L L^T).  Psi_fr: device, M x ld_fr FP64, receives the
- * nfr highest Ritz vectors Psi_f Q_fr of H^ Q = S Q D (H^ = Psi_f^T H~ Psi_f),
- * in ascending order.  theta: host, N, all generalised eigenvalues
+ * X: device, M x ld, FP64 (complex double for a complex operator), the
+ * filtered block Psi_f (ncols = N columns, not orthonormal); on return it
+ * holds the orthonormal basis Psi_o = Psi_f L^-H (S = Psi_f^H Psi_f = L L^H).
+ * Psi_fr: device, M x ld_fr of the same type, receives the nfr highest Ritz
+ * vectors Psi_f Q_fr of H^ Q = S Q D (H^ = Psi_f^H H~ Psi_f), in ascending
+ * order.  theta: host, N, all generalised eigenvalues
  * ascending.  mixed: S's off-diagonal 128 x 128 blocks and H^ outside its
  * trailing nfr x nfr block are formed from FP32 copies in FP32 arithmetic
  * (FP64 between row chunks); Psi_o = FP32[Psi_f (L^-T without its diagonal)]
- * + FP64[Psi_f diag(L^-T)].  Real operators only (CHFSI_EINVAL for a complex
- * one).  1 <= nfr <= N.  CHFSI_ECHOL if S is not positive definite.
+ * + FP64[Psi_f diag(L^-T)] (L^-H for complex data, handled through the
+ * real views of the Gram and rotation kernels).  1 <= nfr <= N.  CHFSI_ECHOL if S is not positive definite.
  * Synchronous. */
 int chfsi_rayleigh_ritz_split(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int32_t nfr, int32_t mixed,
                               double* theta, void* Psi_fr, int64_t ld_fr);

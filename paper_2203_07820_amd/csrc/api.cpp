@@ -404,30 +404,34 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
 }
 
 // Rayleigh-Ritz through the generalised eigenproblem with spectrum splitting
-// (Algorithm 2), real operators.  X (M x N, ldx) holds the filtered block on
-// entry and Psi_o = X L^-T on exit; Pfr (M x nfr, ldfr) receives the nfr
-// highest Ritz vectors X Q_fr; theta (host, N) all generalised eigenvalues.
-// mixed: S off-diagonal 128-blocks and H^ outside its fr-fr block from FP32
-// copies in FP32 arithmetic, Psi_o = FP32[X L^-T without diagonal] +
-// FP64[X diag(L^-T)].
+// (Algorithm 2).  X (M x N, ldx; complex interleaved for a complex operator)
+// holds the filtered block on entry and Psi_o = X L^-H on exit; Pfr (M x nfr,
+// ldfr) receives the nfr highest Ritz vectors X Q_fr; theta (host, N) all
+// generalised eigenvalues.  mixed: S off-diagonal 128-column blocks and H^
+// outside its fr-fr block from FP32 copies in FP32 arithmetic, Psi_o =
+// FP32[X L^-H without diagonal] + FP64[X diag(L^-H)].  Complex data goes
+// through the real views (2N real columns) of the Gram and rotation kernels.
 int rrgep_split(chfsi_op* op, double* X, int64_t ldx, int64_t N, int nfr, bool mixed, double* theta, double* Pfr,
                 int64_t ldfr) {
   chfsi_ctx* ctx = op->ctx;
   const HostTables& t = op->t;
-  const int64_t M = t.M;
-  const int n = static_cast<int>(N);
+  const bool cplx = t.cplx;
+  const int cf = cplx ? 2 : 1;
+  const int64_t M = t.M, nr = N * cf, ldxr = ldx * cf;
+  const int n = static_cast<int>(N), nrr = static_cast<int>(nr);
+  const int prec = cplx ? CHFSI_C128 : CHFSI_F64;
   hipStream_t st = ctx->stream;
   void *W, *part, *G, *S, *Hh, *Zb, *dinfo, *eig;
-  CHECK(ws_get(ctx, WS_W, static_cast<size_t>(M) * N * 8, &W));
+  CHECK(ws_get(ctx, WS_W, static_cast<size_t>(M) * nr * 8, &W));
   // the partial buffer serves the full Gram and the 128-wide and fr-wide ones
-  const int64_t ldm = std::max<int64_t>(ldx, N);
-  const size_t pbytes = std::max({gram_partial_bytes(M, n, ldm), gram_partial_bytes(M, std::min(n, 128), ldm),
-                                  gram_partial_bytes(M, nfr, ldm)});
+  const int64_t ldm = std::max<int64_t>(ldxr, nr);
+  const size_t pbytes = std::max({gram_partial_bytes(M, nrr, ldm), gram_partial_bytes(M, std::min(n, 128) * cf, ldm),
+                                  gram_partial_bytes(M, nfr * cf, ldm)});
   CHECK(ws_get(ctx, WS_GPART, pbytes, &part));
-  CHECK(ws_get(ctx, WS_RR_G, static_cast<size_t>(N) * N * 8, &G));
-  CHECK(ws_get(ctx, WS_RR_S, static_cast<size_t>(N) * N * 8, &S));
-  CHECK(ws_get(ctx, WS_RR_H, static_cast<size_t>(N) * N * 8, &Hh));
-  CHECK(ws_get(ctx, WS_RR_Z, static_cast<size_t>(N) * N * 8 + static_cast<size_t>(N) * 8, &Zb));
+  CHECK(ws_get(ctx, WS_RR_G, static_cast<size_t>(nr) * nr * 8 + static_cast<size_t>(nr) * 8, &G));
+  CHECK(ws_get(ctx, WS_RR_S, static_cast<size_t>(N) * N * 8 * cf, &S));
+  CHECK(ws_get(ctx, WS_RR_H, static_cast<size_t>(N) * N * 8 * cf, &Hh));
+  CHECK(ws_get(ctx, WS_RR_Z, static_cast<size_t>(nr) * nr * 8, &Zb));
   CHECK(ws_get(ctx, WS_INFO, 64, &dinfo));
   CHECK(ws_get(ctx, WS_EIG, static_cast<size_t>(N) * 3 * 8, &eig));
   double* Gd = static_cast<double*>(G);
@@ -438,83 +442,112 @@ int rrgep_split(chfsi_op* op, double* X, int64_t ldx, int64_t N, int nfr, bool m
   double* Ework = D + N;
   double* Wd = static_cast<double*>(W);
   double* partd = static_cast<double*>(part);
+  auto hermitian = [&](double* dst) -> int {   // dst (N x N, column-major) from the lower real-view Gram
+    if (cplx) HIP_TRY(ctx, launch_gram_combine_complex(Gd, nr, dst, n, st));
+    else HIP_TRY(ctx, launch_sym_from_lower(Gd, nr, dst, n, st));
+    return 0;
+  };
   // RRGEP-P needs W = H~ X
-  HIP_TRY(ctx, launch_fill(W, M, N, N, CHFSI_F64, st));
-  CHECK(hx_step(op, CHFSI_F64, X, ldx, nullptr, 0, W, N, N, 1.0, 0.0, 0.0, false));
+  HIP_TRY(ctx, launch_fill(W, M, nr, nr, prec, st));
+  CHECK(hx_step(op, prec, X, ldx, nullptr, 0, W, N, N, 1.0, 0.0, 0.0, false));
   float *X32 = nullptr, *W32 = nullptr;
   if (mixed) {
     void *a, *b;
-    CHECK(ws_get(ctx, WS_X32, static_cast<size_t>(M) * N * 4, &a));
-    CHECK(ws_get(ctx, WS_W32, static_cast<size_t>(M) * N * 4, &b));
+    CHECK(ws_get(ctx, WS_X32, static_cast<size_t>(M) * nr * 4, &a));
+    CHECK(ws_get(ctx, WS_W32, static_cast<size_t>(M) * nr * 4, &b));
     X32 = static_cast<float*>(a);
     W32 = static_cast<float*>(b);
-    HIP_TRY(ctx, launch_convert(X32, N, CHFSI_F32, X, ldx, CHFSI_F64, M, N, st));
-    HIP_TRY(ctx, launch_convert(W32, N, CHFSI_F32, W, N, CHFSI_F64, M, N, st));
+    HIP_TRY(ctx, launch_convert(X32, nr, CHFSI_F32, X, ldxr, CHFSI_F64, M, nr, st));
+    HIP_TRY(ctx, launch_convert(W32, nr, CHFSI_F32, W, nr, CHFSI_F64, M, nr, st));
   }
   // RRGEP-O: lower tiles of S; with mixed, FP32 everywhere, then the
-  // diagonal 128-blocks again in FP64
+  // diagonal blocks of 128 columns again in FP64
   if (mixed) {
-    HIP_TRY(ctx, launch_gram(X32, N, X32, N, M, n, partd, Gd, N, st));
+    HIP_TRY(ctx, launch_gram(X32, nr, X32, nr, M, nrr, partd, Gd, nr, st));
     for (int64_t c0 = 0; c0 < N; c0 += 128) {
-      const int nb = static_cast<int>(std::min<int64_t>(128, N - c0));
-      HIP_TRY(ctx, launch_gram(X + c0, ldx, X + c0, ldx, M, nb, partd, Gd + c0 * N + c0, N, st, c0, c0));
+      const int nb = static_cast<int>(std::min<int64_t>(128, N - c0)) * cf;
+      const int64_t o = c0 * cf;
+      HIP_TRY(ctx, launch_gram(X + o, ldxr, X + o, ldxr, M, nb, partd, Gd + o * nr + o, nr, st, o, o));
     }
   } else {
-    HIP_TRY(ctx, launch_gram(X, ldx, X, ldx, M, n, partd, Gd, N, st));
+    HIP_TRY(ctx, launch_gram(X, ldxr, X, ldxr, M, nrr, partd, Gd, nr, st));
   }
-  HIP_TRY(ctx, launch_sym_from_lower(Gd, N, Sd, n, st));
-  // RRGEP-P: H^ = X^T W; with mixed, FP32 except the fr-fr block
-  const int64_t f0 = N - nfr;
+  CHECK(hermitian(Sd));
+  // RRGEP-P: H^ = X^H W; with mixed, FP32 except the fr-fr block
+  const int64_t f0 = N - nfr, fo = f0 * cf;
   if (mixed) {
-    HIP_TRY(ctx, launch_gram(X32, N, W32, N, M, n, partd, Gd, N, st));
-    HIP_TRY(ctx, launch_gram(X + f0, ldx, Wd + f0, N, M, nfr, partd, Gd + f0 * N + f0, N, st, f0, f0));
+    HIP_TRY(ctx, launch_gram(X32, nr, W32, nr, M, nrr, partd, Gd, nr, st));
+    HIP_TRY(ctx, launch_gram(X + fo, ldxr, Wd + fo, nr, M, nfr * cf, partd, Gd + fo * nr + fo, nr, st, fo, fo));
   } else {
-    HIP_TRY(ctx, launch_gram(X, ldx, Wd, N, M, n, partd, Gd, N, st));
+    HIP_TRY(ctx, launch_gram(X, ldxr, Wd, nr, M, nrr, partd, Gd, nr, st));
   }
-  HIP_TRY(ctx, launch_sym_from_lower(Gd, N, Hd, n, st));
-  // RRGEP-D: S = L L^T, H' = L^-1 H^ L^-T, eigenpairs, Q_fr = L^-T Q'_fr
-  const rocblas_int rn = static_cast<rocblas_int>(N);
-  RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, rn, Sd, rn, static_cast<rocblas_int*>(dinfo)));
+  CHECK(hermitian(Hd));
+  // RRGEP-D: S = L L^H, H' = L^-1 H^ L^-H, eigenpairs, Q_fr = L^-H Q'_fr
+  const rocblas_int rn = static_cast<rocblas_int>(N), rf = static_cast<rocblas_int>(nfr);
+  rocblas_int* di = static_cast<rocblas_int*>(dinfo);
+  auto zc = [](double* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
+  if (cplx) RB_TRY(ctx, rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, rn, zc(Sd), rn, di));
+  else RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, rn, Sd, rn, di));
   int info = 0;
-  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  CHECK(read_info(ctx, di, &info));
   if (info != 0)
     return fail(ctx, CHFSI_ECHOL, "overlap matrix is not positive definite (leading minor " + std::to_string(info) +
                                       ")");
   const double one = 1.0;
-  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                            rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
-  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                            rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
-  RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, rn, Hd, rn, D, Ework,
-                               static_cast<rocblas_int*>(dinfo)));
-  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  const rocblas_double_complex zone(1.0, 0.0);
+  if (cplx) {
+    RB_TRY(ctx, rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                              rocblas_diagonal_non_unit, rn, rn, &zone, zc(Sd), rn, zc(Hd), rn));
+    RB_TRY(ctx, rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                              rocblas_diagonal_non_unit, rn, rn, &zone, zc(Sd), rn, zc(Hd), rn));
+    RB_TRY(ctx, rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, rn, zc(Hd), rn, D, Ework, di));
+  } else {
+    RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                              rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
+    RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                              rocblas_diagonal_non_unit, rn, rn, &one, Sd, rn, Hd, rn));
+    RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, rn, Hd, rn, D, Ework, di));
+  }
+  CHECK(read_info(ctx, di, &info));
   if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
-  double* Qfr = Hd + f0 * N;  // column-major N x nfr
-  RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                            rocblas_diagonal_non_unit, rn, static_cast<rocblas_int>(nfr), &one, Sd, rn, Qfr, rn));
-  // RRGEP-ST-F: Psi^R_fr = X Q_fr (row-major N x nfr rotation)
-  HIP_TRY(ctx, launch_transpose_rect(Qfr, N, nfr, n, Zd, nfr, st));
-  HIP_TRY(ctx, launch_rotate(X, ldx, Zd, nfr, Pfr, ldfr, M, n, nfr, false, st));
-  // RRGEP-ST-O: Psi_o = X L^-T; the column-major lower L^-1 read row-major is
-  // the upper L^-T once its other triangle is cleared
-  RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, rn, Sd, rn,
-                               static_cast<rocblas_int*>(dinfo)));
-  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+  double* Qfr = Hd + f0 * N * cf;  // column-major N x nfr
+  if (cplx)
+    RB_TRY(ctx, rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                              rocblas_diagonal_non_unit, rn, rf, &zone, zc(Sd), rn, zc(Qfr), rn));
+  else
+    RB_TRY(ctx, rocblas_dtrsm(ctx->blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                              rocblas_diagonal_non_unit, rn, rf, &one, Sd, rn, Qfr, rn));
+  // RRGEP-ST-F: Psi^R_fr = X Q_fr through a row-major real-view (nr x nfr cf) Z
+  if (cplx) HIP_TRY(ctx, launch_expand_complex(Qfr, n, nfr, 2, Zd, st));
+  else HIP_TRY(ctx, launch_transpose_rect(Qfr, N, nfr, n, Zd, nfr, st));
+  HIP_TRY(ctx, launch_rotate(X, ldxr, Zd, nfr * cf, Pfr, ldfr * cf, M, nrr, nfr * cf, false, st));
+  // RRGEP-ST-O: Psi_o = X L^-H.  Real: the column-major lower L^-1 read
+  // row-major is L^-T once its other triangle is cleared; complex: expanded
+  // into the real-view upper block-triangular matrix
+  if (cplx) RB_TRY(ctx, rocsolver_ztrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, rn, zc(Sd), rn, di));
+  else RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, rn, Sd, rn, di));
+  CHECK(read_info(ctx, di, &info));
   if (info != 0) return fail(ctx, CHFSI_ECHOL, "Cholesky factor is singular");
-  HIP_TRY(ctx, launch_zero_strict_lower(Sd, n, N, st));
+  const double* Zr = Sd;
+  if (cplx) {
+    HIP_TRY(ctx, launch_expand_complex(Sd, n, n, 1, Zd, st));
+    Zr = Zd;
+  } else {
+    HIP_TRY(ctx, launch_zero_strict_lower(Sd, n, N, st));
+  }
   if (mixed) {
     void* c32;
-    CHECK(ws_get(ctx, WS_C32, static_cast<size_t>(M) * N * 4, &c32));
-    float* Z32 = reinterpret_cast<float*>(Zd);  // N x N floats, then N doubles of the diagonal
-    double* dg = Zd + (static_cast<int64_t>(N) * N + 1) / 2;
-    HIP_TRY(ctx, launch_split_diag(Sd, N, n, Z32, dg, st));
-    HIP_TRY(ctx, launch_rotate(X32, N, Z32, N, static_cast<float*>(c32), N, M, n, n, true, st));
-    HIP_TRY(ctx, launch_add_scaled_cols(static_cast<float*>(c32), N, dg, X, ldx, M, n, st));
+    CHECK(ws_get(ctx, WS_C32, static_cast<size_t>(M) * nr * 4, &c32));
+    float* Z32 = reinterpret_cast<float*>(Gd);  // nr x nr floats, then nr doubles of the diagonal
+    double* dg = Gd + (nr * nr + 1) / 2;
+    HIP_TRY(ctx, launch_split_diag(Zr, nr, nrr, Z32, dg, st));
+    HIP_TRY(ctx, launch_rotate(X32, nr, Z32, nr, static_cast<float*>(c32), nr, M, nrr, nrr, true, st));
+    HIP_TRY(ctx, launch_add_scaled_cols(static_cast<float*>(c32), nr, dg, X, ldxr, M, nrr, st));
   } else {
     void* X2;
-    CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(M) * N * 8, &X2));
-    HIP_TRY(ctx, launch_rotate(X, ldx, Sd, N, static_cast<double*>(X2), N, M, n, n, true, st));
-    HIP_TRY(ctx, launch_convert(X, ldx, CHFSI_F64, X2, N, CHFSI_F64, M, N, st));
+    CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(M) * nr * 8, &X2));
+    HIP_TRY(ctx, launch_rotate(X, ldxr, Zr, nr, static_cast<double*>(X2), nr, M, nrr, nrr, true, st));
+    HIP_TRY(ctx, launch_convert(X, ldxr, CHFSI_F64, X2, nr, CHFSI_F64, M, nr, st));
   }
   HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -1457,7 +1490,6 @@ int chfsi_rayleigh_ritz_split(chfsi_op* op, void* X, int64_t ncols, int64_t ld, 
   if (!op) return CHFSI_EINVAL;
   chfsi_ctx* ctx = op->ctx;
   CHECK(check_block(op, X, ncols, ld));
-  if (op->t.cplx) return fail(ctx, CHFSI_EINVAL, "the split Rayleigh-Ritz step is implemented for real operators");
   if (!theta || !Psi_fr) return fail(ctx, CHFSI_EINVAL, "null theta or Psi_fr");
   if (nfr < 1 || nfr > ncols) return fail(ctx, CHFSI_EINVAL, "need 1 <= nfr <= ncols");
   if (ld_fr < nfr) return fail(ctx, CHFSI_EINVAL, "ld_fr < nfr");

@@ -121,13 +121,40 @@ def test_split_rr_feeds_spectrum_split_density(ctx):
     assert np.max(np.abs(host(rho) - full)) < 1e-9 * np.max(full)
 
 
-def test_split_rr_rejects_complex_and_bad_nfr(ctx):
-    s = workloads.small_system(2, 3, 1, seed=41, has_proj=True, k=(0.1, 0.0, 0.0))
+@pytest.mark.parametrize("N,nfr,mixed", [(24, 5, False), (150, 12, False), (150, 12, True)])
+def test_split_rr_complex_matches_oracle(ctx, N, nfr, mixed):
+    s = workloads.small_system(2, 5, 2, seed=43, has_proj=True, k=(0.2, -0.1, 0.3))
     op = lib.Operator(ctx, s)
-    X = torch.randn(op.M, 8, dtype=torch.complex128, device="cuda")
-    P = torch.empty(op.M, 2, dtype=torch.complex128, device="cuda")
-    with pytest.raises(lib.ChfsiError):
-        op.rayleigh_ritz_split(X, 2, P)
+    ref_op = fe.build_operator(s)
+    Hd = fe.dense(ref_op)
+    lam, V = np.linalg.eigh(Hd)
+    rng = np.random.default_rng(44)
+    if mixed:   # nearly converged, unnormalised columns
+        E = rng.standard_normal((op.M, N)) + 1j * rng.standard_normal((op.M, N))
+        Psi = (V[:, :N] + 1e-4 * E) @ np.diag(rng.uniform(0.5, 2.0, N))
+    else:
+        Psi = rng.standard_normal((op.M, N)) + 1j * rng.standard_normal((op.M, N))
+    ref = rrgep.rrgep(lambda X: Hd @ X, Psi, nfr)
+    X = torch.from_numpy(Psi.copy()).cuda()
+    Pfr = torch.zeros(op.M, nfr, dtype=torch.complex128, device="cuda")
+    th = op.rayleigh_ritz_split(X, nfr, Pfr, mixed=mixed)
+    scale = np.max(np.abs(ref.theta))
+    Xo = host(X)
+    if mixed:
+        assert np.max(np.abs(th[N - nfr:] - ref.theta[N - nfr:])) < 1e-8 * scale
+        assert np.max(np.abs(th - ref.theta)) < 1e-5 * scale
+        assert np.max(np.abs(Xo.conj().T @ Xo - np.eye(N))) < 1e-5
+    else:
+        assert np.max(np.abs(th - ref.theta)) < 1e-10 * scale
+        assert np.max(np.abs(Xo - ref.psi_o)) < 1e-9 * np.max(np.abs(ref.psi_o))
+        # top Ritz vectors up to a phase per column
+        got = host(Pfr)
+        ph = np.sum(np.conj(got) * ref.psi_fr, axis=0)
+        got = got * (ph / np.abs(ph))[None, :]
+        assert np.max(np.abs(got - ref.psi_fr)) < 1e-9 * np.max(np.abs(ref.psi_fr))
+
+
+def test_split_rr_rejects_bad_nfr(ctx):
     s2 = workloads.small_system(2, 3, 1, seed=42)
     op2 = lib.Operator(ctx, s2)
     X2 = torch.randn(op2.M, 8, dtype=torch.float64, device="cuda")
