@@ -381,7 +381,9 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
  * host, nwanted + n_buf Ritz values of the last step; mu_out, res_hist
  * (host, maxit values: the residual norm of every step) and iters nullable.
  * m, block: filter degree and column block as in chfsi_params.  Real
- * operators with a nodal potential; 0 < n_electrons < 2 nwanted.  Returns
+ * operators with a nodal potential; 0 < n_electrons < 2 nwanted.  On
+ * return the operator holds the last step's effective potential (restore
+ * the original with chfsi_op_set_potential if needed).  Returns
  * CHFSI_NOTCONV if tol was not met.  Synchronous. */
 int chfsi_scf(chfsi_op* op, void* X, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
               double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit, double* rho,
