@@ -1001,20 +1001,14 @@ int scf_tables(chfsi_op* op) {
   return 0;
 }
 
-// q = (D K D) u on the operator's mesh: the cell kernel with alpha = 2 on a
-// zero diagonal and no projectors (H~ without potential is D (K/2) D).
+// q = (D K D) u on the operator's mesh, one vector: the cell stiffness by sum
+// factorisation of its 1D factors (a 64-column MFMA tile would waste 63/64
+// of its work on a single column).
 int apply_stiffness(chfsi_op* op, const double* u, double* qv) {
   chfsi_ctx* ctx = op->ctx;
   const HostTables& t = op->t;
   HIP_TRY(ctx, launch_fill(qv, t.M, 1, 1, CHFSI_F64, ctx->stream));
-  HxLaunch L = make_hx(op, CHFSI_F64, u, 1, nullptr, 0, qv, 1, 1, 2.0, 0.0, 0.0, false, nullptr, 0);
-  L.vdiag = op->scf_tab + 4 * t.M;
-  L.pair_ptr = nullptr;
-  L.pair_atom = nullptr;
-  L.pair_re = nullptr;
-  L.pair_im = nullptr;
-  L.hP = nullptr;
-  HIP_TRY(ctx, launch_cell_hx(L, CHFSI_F64, ctx->stream));
+  HIP_TRY(ctx, launch_stiffness(u, op->dscale, qv, t.p, t.ncell, t.K1d.data(), t.M1d.data(), ctx->stream));
   return 0;
 }
 

@@ -33,6 +33,7 @@ struct HostTables {
   std::vector<double> cell_im;      // mcell x mcell (complex only)
   std::vector<double> dscale;       // per node M^-1/2 (M)
   std::vector<double> interp;       // (p+1) x (p+1): interp[q*(p+1)+a] = l_a(g_q)
+  std::vector<double> K1d, M1d;     // 1D stiffness and consistent mass, (p+1) x (p+1)
   std::vector<double> vdiag;        // V + |k|^2/2 (M)
   int natoms = 0;
   bool has_proj = false;
@@ -154,6 +155,10 @@ hipError_t launch_ediv(const double* x, const double* d, double* y, int64_t n, h
 hipError_t launch_emul(const double* x, const double* d, double* y, int64_t n, hipStream_t s);
 hipError_t launch_veff(const double* vext, const double* vh, const double* rho, double* V, int64_t n,
                        hipStream_t s);
+// q += D K D u on the structured mesh by sum factorisation (K1, M1: the 1D
+// stiffness and consistent mass, host, (p+1)^2 values each)
+hipError_t launch_stiffness(const double* u, const double* dscale, double* q, int p, int nc, const double* K1,
+                            const double* M1, hipStream_t s);
 
 // Elementwise helpers on row-major blocks (real view).
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);

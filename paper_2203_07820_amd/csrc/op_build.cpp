@@ -186,6 +186,8 @@ std::string build_tables(const chfsi_system& sys, HostTables& t) {
         G1[a * q + b] += gw[iq] * l[a] * dl[b];
       }
   }
+  t.K1d = K1;
+  t.M1d = Mc;
   // Loewdin scale per 1D index: shared (vertex-type) nodes collect the lumped
   // mass w_0 h/2 from both neighbouring cells.
   std::vector<double> dd_loc(q), dd_glob(p);
