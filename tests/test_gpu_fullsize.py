@@ -3,8 +3,10 @@ benchmark times (one 128-column block per launch), checked on sampled rows
 that the oracle computes one by one from the cells containing them.
 
 * c1 (24^3 cells, p = 6, M = 2,985,984, 64 atoms with projectors): H~X and
-  one fused filter step (m = 1, alpha (H~X - cX)) in FP64 and FP32.
-* the largest c3 operator (20^3 cells, p = 5) at its first k-point, complex128.
+  one fused filter step (m = 1, alpha (H~X - cX)) in FP64 and FP32, and H~X
+  in the BF16 scheme against the oracle's identically rounded products.
+* the largest c3 operator (20^3 cells, p = 5) at its first k-point, complex128
+  and complex64.
 * c1 with the per-cell Gauss-quadrature potential: H~X.
 
 Tolerances as in the small-size parity tests: FP64 1e-12 and FP32 2e-5
@@ -114,3 +116,47 @@ def test_c1_quadrature_potential_apply_sampled(ctx):
     want += np.real(ref.C[rows] @ P)
     got = _gather_rows(Y, rows)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_c1_bf16_apply_sampled(ctx):
+    # the BF16 scheme at full size: cell products on bf16-rounded scaled cell
+    # matrices and bf16-rounded cell blocks, FP32 accumulation; potential and
+    # projector terms on X as given (tolerance 2e-5 as in the small tests)
+    s = workloads.config("c1")
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    g = torch.Generator(device="cuda").manual_seed(107)
+    X = torch.randn(op.M, B, dtype=torch.float32, device="cuda", generator=g)
+    Y = torch.zeros_like(X)
+    op.apply(X, Y, prec=lib.BF16)
+    rows = _rows(op.M, 30, 108)
+    Xh = X.cpu().numpy().astype(np.float64)
+    A0 = ref.cell_matrix()
+    want = np.zeros((rows.size, B))
+    for i, j in enumerate(rows):
+        ce, lo = np.nonzero(ref.cells == j)
+        acc = np.zeros(B)
+        for c, l in zip(ce, lo):
+            nodes = ref.cells[c]
+            Ac = fe.bf16_round(ref.D[nodes[l]] * A0[l] * ref.D[nodes])
+            acc += Ac @ fe.bf16_round(Xh[nodes])
+        want[i] = acc + ref.V[j] * Xh[j]
+    P = ref.hvec[:, None] * (ref.C.conj().T @ Xh)
+    want += np.real(ref.C[rows] @ P)
+    got = _gather_rows(Y, rows).astype(np.float64)
+    assert np.max(np.abs(got - want)) <= 2e-5 * np.max(np.abs(want))
+
+
+def test_c3_largest_complex64_apply_sampled(ctx):
+    s3 = workloads.config("c3", 7)
+    s = s3.with_k(workloads.kpoints_mp4(s3.L)[0])
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    g = torch.Generator(device="cuda").manual_seed(109)
+    X = torch.randn(op.M, B, dtype=torch.complex64, device="cuda", generator=g)
+    Y = torch.zeros_like(X)
+    op.apply(X, Y, prec=lib.C64)
+    rows = _rows(op.M, 30, 110)
+    want = fe.apply_rows(ref, X.cpu().numpy().astype(np.complex128), rows)
+    got = _gather_rows(Y, rows).astype(np.complex128)
+    assert np.max(np.abs(got - want)) <= 2e-5 * np.max(np.abs(want))
