@@ -1252,6 +1252,8 @@ int build_quadrature_potential(chfsi_op* op, const chfsi_system* sys) {
   HostTables& t = op->t;
   const int p = t.p, q = p + 1, nq = q * q * q, mc = t.mcell, mp = t.mpad;
   const int64_t E = t.E, msym = static_cast<int64_t>(mc) * (mc + 1) / 2;
+  if (msym * E >= (int64_t{1} << 31) || static_cast<int64_t>(nq) * E >= (int64_t{1} << 31))
+    return fail(ctx, CHFSI_EINVAL, "mesh too large for the per-cell potential GEMM (32-bit dimensions)");
   // basis products at the Gauss points, pairs j <= k (j-major) by points
   std::vector<double> Nq(static_cast<size_t>(nq) * mc);
   for (int qp = 0; qp < nq; ++qp) {
