@@ -1,7 +1,8 @@
-// Elementwise kernels of the self-consistent field loop (Section 3,
-// Algorithm 1): the right-hand side of the Hartree problem, the Jacobi
-// preconditioner, the effective potential with LDA exchange, and the
-// weighted vectors of the mixing.  All are single passes over M values.
+// Kernels of the self-consistent field loop (Section 3, Algorithm 1): the
+// stiffness operator of the Hartree problem applied to one vector by sum
+// factorisation, and single passes over M values for its right-hand side,
+// the Jacobi preconditioner, the effective potential with LDA exchange and
+// the weighted vectors of the mixing.
 #include <cmath>
 
 #include "internal.h"
