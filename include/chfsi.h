@@ -208,7 +208,9 @@ int chfsi_op_destroy(chfsi_op* op);
  * FP64 and FP32 (E x mpad^2 each: 13.7 + 6.9 GB at 24^3 cells, p = 6); the
  * diagonal keeps |k|^2/2.  All functions accept the result; the filter
  * precisions are F64 and F32 (C128 and C64 for k != 0): BF16 returns
- * CHFSI_EINVAL.  Same arguments and ownership as chfsi_op_build(). */
+ * CHFSI_EINVAL, as does a mesh whose packed product (mcell (mcell + 1) / 2
+ * rows by E cells) reaches 2^31 entries.  Same arguments and ownership as
+ * chfsi_op_build(). */
 int chfsi_op_build_quadrature(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
 /* M nodes, E cells, mcell = (p+1)^3 nodes per cell, nproj = 4 * natoms (0
  * without projectors), npairs = number of (cell, atom) pairs, is_complex. */
@@ -358,7 +360,8 @@ int chfsi_op_set_potential(chfsi_op* op, const double* V);
  * K v = 4 pi M (rho - rho_bar) with rho_bar the mean charge and
  * sum_j M_jj v_j = 0, solved as D K D u = 4 pi M^1/2 (rho - rho_bar),
  * v = D u, by Jacobi-preconditioned CG (the paper's Poisson solver) to a
- * relative residual tol, at most maxit iterations.  vH: device, M values.
+ * relative residual tol, at most maxit iterations; the stiffness is applied
+ * cell by cell by sum factorisation of its 1D factors.  vH: device, M values.
  * iters / relres (nullable) receive the iteration count and the final
  * relative residual.  Real operators with a nodal potential only.  Returns
  * CHFSI_NOTCONV if tol was not reached.  Synchronous. */
