@@ -362,9 +362,12 @@ int chfsi_op_set_potential(chfsi_op* op, const double* V);
  * v = D u, by Jacobi-preconditioned CG (the paper's Poisson solver) to a
  * relative residual tol, at most maxit iterations; the stiffness is applied
  * cell by cell by sum factorisation of its 1D factors.  vH: device, M values.
- * iters / relres (nullable) receive the iteration count and the final
- * relative residual.  Real operators with a nodal potential only.  Returns
- * CHFSI_NOTCONV if tol was not reached.  Synchronous. */
+ * The CG scalars stay on the device and the residual is checked every 8
+ * iterations, so the count is a multiple of 8 (or maxit) and the solve may
+ * run up to 7 iterations past tol.  iters / relres (nullable) receive the
+ * iteration count and the final relative residual.  Real operators with a
+ * nodal potential only.  Returns CHFSI_NOTCONV if tol was not reached,
+ * CHFSI_EDIVERGE on a non-finite residual.  Synchronous. */
 int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32_t maxit, int32_t* iters,
                   double* relres);
 

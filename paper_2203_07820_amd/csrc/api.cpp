@@ -1046,25 +1046,31 @@ int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int m
   HIP_TRY(ctx, launch_convert(pv, 1, CHFSI_F64, z, 1, CHFSI_F64, M, 1, st));
   double rz = 0.0, rr = bb;
   CHECK(dot_host(ctx, r, z, M, &rz));
+  // the iterations keep their scalars on the device (launch_cg_iteration);
+  // the host reads the residual history once per kCheck iterations, so a
+  // solve runs up to kCheck - 1 iterations past the stopping point
+  constexpr int kCheck = 8;
+  void* scv;
+  CHECK(ws_get(ctx, WS_CG, (8 + kCheck) * 8, &scv));
+  double* sc = static_cast<double*>(scv);
+  double* hist = sc + 8;
+  const double sc0[8] = {rz, 0.0, 0.0, 0.0, 0.0, zz, 0.0, 0.0};
+  HIP_TRY(ctx, hipMemcpyAsync(sc, sc0, sizeof(sc0), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
   int it = 0;
   const double stop = tol * tol * bb;
+  double hh[kCheck];
   while (it < maxit && rr > stop && bb > 0.0) {
-    CHECK(apply_stiffness(op, pv, qv));
-    double pq = 0.0;
-    CHECK(dot_host(ctx, pv, qv, M, &pq));
-    if (!(pq > 0.0)) break;
-    const double al = rz / pq;
-    HIP_TRY(ctx, launch_axpby(al, pv, 1.0, u, M, st));
-    HIP_TRY(ctx, launch_axpby(-al, qv, 1.0, r, M, st));
-    CHECK(dot_host(ctx, r, r, M, &rr));
-    ++it;
-    if (rr <= stop) break;
-    HIP_TRY(ctx, launch_ediv(r, kd, z, M, st));
-    CHECK(project(z));
-    double rz1 = 0.0;
-    CHECK(dot_host(ctx, r, z, M, &rz1));
-    HIP_TRY(ctx, launch_axpby(1.0, z, rz1 / rz, pv, M, st));   // p = z + (rz1 / rz) p
-    rz = rz1;
+    const int k = std::min(kCheck, maxit - it);
+    for (int j = 0; j < k; ++j) {
+      CHECK(apply_stiffness(op, pv, qv));
+      HIP_TRY(ctx, launch_cg_iteration(u, r, z, pv, qv, kd, sqm, sc, hist, j, M, st));
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(hh, hist, k * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    it += k;
+    rr = hh[k - 1];
+    if (!(rr == rr)) return fail(ctx, CHFSI_EDIVERGE, "Hartree CG produced NaN");
   }
   HIP_TRY(ctx, launch_ediv(u, sqm, vh, M, st));   // v = D u
   if (iters) *iters = it;

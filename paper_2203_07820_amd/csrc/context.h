@@ -23,6 +23,7 @@ enum Slot {
   WS_RR_G, WS_RR_S, WS_RR_H, WS_RR_Z, // split Rayleigh-Ritz: lower Gram, S, H^, rotation
   WS_X32, WS_W32, WS_C32,          // FP32 copies of X, H X and the FP32 rotation
   WS_SCF,                          // SCF vectors (potentials, densities, CG, mixing history)
+  WS_CG,                           // CG scalars and the residual history of one check interval
   WS_COUNT
 };
 

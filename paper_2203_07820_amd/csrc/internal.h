@@ -155,6 +155,11 @@ hipError_t launch_ediv(const double* x, const double* d, double* y, int64_t n, h
 hipError_t launch_emul(const double* x, const double* d, double* y, int64_t n, hipStream_t s);
 hipError_t launch_veff(const double* vext, const double* vh, const double* rho, double* V, int64_t n,
                        hipStream_t s);
+// One preconditioned CG iteration after q = A p: with the device scalars
+// sc (6 values: r.z, p.q, r.r, z.n, new r.z, n.n) it updates u, r, z (Jacobi,
+// then projected off the null vector nv) and p, and stores r.r in hist[it].
+hipError_t launch_cg_iteration(double* u, double* r, double* z, double* p, const double* q, const double* kd,
+                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s);
 // q += D K D u on the structured mesh by sum factorisation (K1, M1: the 1D
 // stiffness and consistent mass, host, (p+1)^2 values each)
 hipError_t launch_stiffness(const double* u, const double* dscale, double* q, int p, int nc, const double* K1,

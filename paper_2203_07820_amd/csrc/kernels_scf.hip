@@ -139,6 +139,110 @@ hipError_t launch_stiffness(const double* u, const double* dscale, double* q, in
   return hipGetLastError();
 }
 
+namespace {
+
+// ---- preconditioned CG with its scalars on the device ------------------------
+// sc[0] = r.z, sc[1] = p.q, sc[2] = r.r, sc[3] = z.n, sc[4] = r.z (new),
+// sc[5] = |n|^2 (n = M^1/2 1, the null vector); dot products accumulate by
+// one atomic add per block.
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return t;   // valid in thread 0
+}
+
+__global__ void __launch_bounds__(256) cg_pq_kernel(const double* __restrict__ p, const double* __restrict__ q,
+                                                    double* __restrict__ sc, int64_t n) {
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) v += p[i] * q[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) atomicAdd(sc + 1, v);
+}
+
+// u += a p, r -= a q, z = r / kd; sums r.r, z.n, r.n
+__global__ void __launch_bounds__(256) cg_update_kernel(double* __restrict__ u, double* __restrict__ r,
+                                                        double* __restrict__ z, const double* __restrict__ p,
+                                                        const double* __restrict__ q, const double* __restrict__ kd,
+                                                        const double* __restrict__ nv, double* __restrict__ sc,
+                                                        int64_t n) {
+  const double pq = sc[1];
+  const double al = pq > 0.0 ? sc[0] / pq : 0.0;
+  double rr = 0.0, zn = 0.0;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    u[i] += al * p[i];
+    const double ri = r[i] - al * q[i];
+    r[i] = ri;
+    const double zi = ri / kd[i];
+    z[i] = zi;
+    rr += ri * ri;
+    zn += zi * nv[i];
+  }
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) atomicAdd(sc + 2, rr);
+  zn = block_sum(zn);
+  if (threadIdx.x == 0) atomicAdd(sc + 3, zn);
+}
+
+// z -= (z.n / n.n) n; sum r.z
+__global__ void __launch_bounds__(256) cg_project_kernel(const double* __restrict__ r, double* __restrict__ z,
+                                                         const double* __restrict__ nv, double* __restrict__ sc,
+                                                         int64_t n) {
+  const double c = sc[3] / sc[5];
+  double rz = 0.0;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const double zi = z[i] - c * nv[i];
+    z[i] = zi;
+    rz += r[i] * zi;
+  }
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) atomicAdd(sc + 4, rz);
+}
+
+// p = z + (rz_new / rz) p
+__global__ void __launch_bounds__(256) cg_direction_kernel(const double* __restrict__ z, double* __restrict__ p,
+                                                           const double* __restrict__ sc, int64_t n) {
+  const double be = sc[0] > 0.0 ? sc[4] / sc[0] : 0.0;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) p[i] = z[i] + be * p[i];
+}
+
+// scalar bookkeeping between iterations: keep r.r of iteration `it`, move the
+// new r.z into place, clear the sums
+__global__ void cg_scalars_kernel(double* __restrict__ sc, double* __restrict__ hist, int it) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hist[it] = sc[2];
+    sc[0] = sc[4];
+    sc[1] = 0.0;
+    sc[2] = 0.0;
+    sc[3] = 0.0;
+    sc[4] = 0.0;
+  }
+}
+
+unsigned cg_grid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return static_cast<unsigned>(b < 2048 ? b : 2048);
+}
+
+}  // namespace
+
+hipError_t launch_cg_iteration(double* u, double* r, double* z, double* p, const double* q, const double* kd,
+                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s) {
+  const dim3 g(cg_grid(n)), b(256);
+  hipLaunchKernelGGL(cg_pq_kernel, g, b, 0, s, p, q, sc, n);
+  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, s, u, r, z, p, q, kd, nv, sc, n);
+  hipLaunchKernelGGL(cg_project_kernel, g, b, 0, s, r, z, nv, sc, n);
+  hipLaunchKernelGGL(cg_direction_kernel, g, b, 0, s, z, p, sc, n);
+  hipLaunchKernelGGL(cg_scalars_kernel, dim3(1), dim3(64), 0, s, sc, hist, it);
+  return hipGetLastError();
+}
+
 hipError_t launch_hartree_rhs(const double* rho, double rho_bar, const double* sqm, double* b, int64_t n,
                               hipStream_t s) {
   if (n <= 0) return hipSuccess;
