@@ -142,7 +142,7 @@ template <int MP, typename T> struct RowTables {
 // BF selects the bf16 cell products (FP32 iterates): a 32-wide k step needs
 // 8 cell rows per lane; the FP32 values are rounded to bf16 (to nearest even)
 // in registers.
-template <int P, typename T, bool CPLX, int WAVES, bool BF>
+template <int P, typename T, bool CPLX, int WAVES, bool BF, int ED>
 __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
                                           RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
   constexpr int Q = P + 1;
@@ -447,17 +447,19 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
       }
     }
   };
+  // the operands of stage h + ED - 1 are in flight while stage h is
+  // finished (ED = 3 fits for 8-byte values, whose main-loop operand
+  // registers are free by now, except in the item loop of the chunked
+  // batched kernel)
+  static_assert(ED == 2 || ED == 3, "epilogue depth");
   constexpr int NH = (4 / SR) * RPW;   // stages (odd when SR = 4 and RPW is odd)
-  Ops o0, o1;
-  fetch(0, o0);
+  Ops o[ED];
 #pragma unroll
-  for (int h = 0; h < NH; h += 2) {
-    if (h + 1 < NH) fetch(h + 1, o1);
-    finish(h, o0);
-    if (h + 1 < NH) {
-      if (h + 2 < NH) fetch(h + 2, o0);
-      finish(h + 1, o1);
-    }
+  for (int h = 0; h < ED - 1 && h < NH; ++h) fetch(h, o[h]);
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    if (h + ED - 1 < NH) fetch(h + ED - 1, o[(h + ED - 1) % ED]);
+    finish(h, o[h % ED]);
   }
 }
 
@@ -465,6 +467,8 @@ template <int P> constexpr int waves_for() {
   return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 > 24 ? 8 : 4;
 }
 template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16; }
+// epilogue stages in flight + 1
+template <typename T> constexpr int epilogue_depth() { return sizeof(T) == 8 ? 3 : 2; }
 
 // Single problem: one workgroup per (cell, column tile), cells fastest.
 template <int P, typename T, bool CPLX, int WAVES, int OCC, bool BF>
@@ -473,7 +477,7 @@ cell_hx_kernel(const HxArgs<T> a) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, BF>(a, bid % E, (bid / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, BF, epilogue_depth<T>()>(a, bid % E, (bid / E) * kNT, tab);
 }
 
 // Many problems in one persistent launch: the work list is the concatenation
@@ -501,7 +505,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const HxArgs<T> d = descs[q];
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
-    cell_item<P, T, CPLX, WAVES, false>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
+    cell_item<P, T, CPLX, WAVES, false, 2>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
   }
 }
 
@@ -522,7 +526,7 @@ cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __re
   const HxArgs<T> d = descs[lo];
   const int local = it - static_cast<int>(item_off[lo]);
   const int E = d.nc * d.nc * d.nc;
-  cell_item<P, T, CPLX, WAVES, false>(d, local % E, (local / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, false, epilogue_depth<T>()>(d, local % E, (local / E) * kNT, tab);
 }
 
 // Waves per SIMD: two for real and complex FP64, complex FP32 and bf16 (one
