@@ -1,8 +1,9 @@
 // Kernels of the self-consistent field loop (Section 3, Algorithm 1): the
 // stiffness operator of the Hartree problem applied to one vector by sum
-// factorisation, and single passes over M values for its right-hand side,
-// the Jacobi preconditioner, the effective potential with LDA exchange and
-// the weighted vectors of the mixing.
+// factorisation, the iterations of its preconditioned CG with the scalars
+// kept on the device, and single passes over M values for its right-hand
+// side, the Jacobi preconditioner, the effective potential with LDA
+// exchange and the weighted vectors of the mixing.
 #include <cmath>
 
 #include "internal.h"
@@ -225,9 +226,11 @@ __global__ void cg_scalars_kernel(double* __restrict__ sc, double* __restrict__ 
   }
 }
 
+// at most one block per compute unit: every block adds its partial sums
+// into the same few scalars, and those atomics serialise in L2
 unsigned cg_grid(int64_t n) {
   const int64_t b = (n + 255) / 256;
-  return static_cast<unsigned>(b < 2048 ? b : 2048);
+  return static_cast<unsigned>(b < 256 ? b : 256);
 }
 
 }  // namespace

@@ -2,7 +2,8 @@
 chfsi_scf) with the oracle's SCF loop.
 
 Tolerances.  Hartree: CG to a relative residual of 1e-12 on a problem with
-condition number ~1e3, so 1e-9 relative on v_H.  H~X after a potential
+condition number ~1e3, so 1e-9 relative on v_H; two solves of the same
+density differ only in the order of the atomic dot-product sums (1e-11).  H~X after a potential
 change: FP64 products, 1e-12.  SCF: the fixed point does not depend on the
 eigensolver or the mixing path; both loops stop at an M-norm residual of
 1e-9, the GPU one with ChFSI subspaces converged alongside, so densities
@@ -48,6 +49,27 @@ def test_hartree_matches_oracle(ctx, nc, p, L):
     got = vh.cpu().numpy()
     assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want))
     assert abs(float(np.sum(ref.Mdiag * got))) < 1e-9 * float(np.sum(ref.Mdiag * np.abs(got)))
+
+
+def test_hartree_iteration_cap_and_repeat(ctx):
+    # the device-side CG checks its residual every 8 iterations: a cap below
+    # that stops at the cap unconverged; a converged solve reports a multiple
+    # of 8; a repeated solve on the reused workspace gives the same potential
+    s = workloads.small_system(3, 5, 2, seed=3, L=7.5)
+    op = lib.Operator(ctx, s)
+    ref = fe.build_operator(s)
+    rho = np.random.default_rng(4).uniform(0.01, 0.5, op.M)
+    vh = torch.empty(op.M, dtype=torch.float64, device="cuda")
+    it, rr = op.hartree(dev(rho), vh, tol=1e-12, maxit=3)
+    assert it == 3 and rr > 1e-12
+    it, rr = op.hartree(dev(rho), vh, tol=1e-12, maxit=5000)
+    assert it % 8 == 0 and rr <= 1e-12
+    v1 = vh.cpu().numpy()
+    it2, rr2 = op.hartree(dev(rho), vh, tol=1e-12, maxit=5000)
+    assert it2 % 8 == 0 and rr2 <= 1e-12
+    want = oscf.hartree(ref, rho)
+    assert np.max(np.abs(vh.cpu().numpy() - v1)) <= 1e-11 * np.max(np.abs(want))
+    assert np.max(np.abs(v1 - want)) <= 1e-9 * np.max(np.abs(want))
 
 
 def test_set_potential_changes_the_operator(ctx):
