@@ -120,8 +120,8 @@ def main():
     ap.add_argument("--c4-epochs", type=int, default=40, help="c4: passes over the training set")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(sharding over several GPUs is not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if args.workload == "c2":
         return run_c2(args)
