@@ -279,8 +279,10 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     int soff[RPW];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KS * 64 * static_cast<int>(sizeof(T)));
+    // both loaders clamp the k step to the last one, so that the pipeline's
+    // loads past the end (never used) read valid memory without a branch
     auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
-      const int vo = (kg * 64 + lane) * static_cast<int>(sizeof(T));
+      const int vo = ((kg < KS ? kg : KS - 1) * 64 + lane) * static_cast<int>(sizeof(T));
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
         av[r] = buf_load<T>(ra, vo, soff[r]);
@@ -288,7 +290,7 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
       }
     };
     auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
-      const int l = kg * 4 + lane / 16;
+      const int l = (kg < KS ? kg : KS - 1) * 4 + lane / 16;
       const int64_t off = tab.xoff[l];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -326,26 +328,27 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
           if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
         }
     };
-    T a0[RPW], a1[RPW], ai0[RI], ai1[RI];
-    T b0[CPW], b1[CPW], b2[CPW], b3[CPW], o0[CI], o1[CI], o2[CI], o3[CI];
-    load_b(b0, o0, 0);
-    load_a(a0, ai0, 0);
-    load_b(b1, o1, 1);
-    for (int kg = 0; kg < KS; kg += 2) {
-      load_a(a1, ai1, kg + 1);
-      if (kg + 2 < KS) load_b(b2, o2, kg + 2);
-      compute(a0, ai0, b0, o0, kg);
-      if (kg + 2 < KS) load_a(a0, ai0, kg + 2);
-      if (kg + 3 < KS) load_b(b3, o3, kg + 3);
-      compute(a1, ai1, b1, o1, kg + 1);
+    // Pipeline: the A fragments of step s + 1 and the B rows of step s + 2
+    // are in flight while step s multiplies.  The loop is unrolled by 4 so
+    // that every buffer keeps a fixed role (A period 2, B period 4): a copy
+    // between buffers would make the compiler wait for the loads in flight
+    // into the source buffer, draining the pipeline every iteration.
+    static_assert(KS % 4 == 0, "k steps come in groups of 4");
+    T aq[2][RPW], aiq[2][RI];
+    T bq[4][CPW], oq[4][CI];
+    load_b(bq[0], oq[0], 0);
+    load_a(aq[0], aiq[0], 0);
+    load_b(bq[1], oq[1], 1);
+    for (int kg = 0; kg < KS; kg += 4) {
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        b0[c] = b2[c];
-        b1[c] = b3[c];
-        if constexpr (CPLX) {
-          o0[c] = o2[c];
-          o1[c] = o3[c];
-        }
+      for (int j = 0; j < 4; ++j) {
+        const int s = kg + j;
+        load_a(aq[(j + 1) % 2], aiq[(j + 1) % 2], s + 1);
+        load_b(bq[(j + 2) % 4], oq[(j + 2) % 4], s + 2);
+        compute(aq[j % 2], aiq[j % 2], bq[j], oq[j], s);
+        // keep each step's loads behind the previous step's MFMAs: hoisted
+        // further, they would hold a third A buffer and spill at FP64
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
