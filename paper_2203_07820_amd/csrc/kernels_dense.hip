@@ -137,18 +137,22 @@ gram_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mma(xv[a], yv[b], acc[a][b]);
   };
-  T x0[4], y0[4], x1[4], y1[4], x2[4], y2[4];
-  if (KS > 0) load(x0, y0, 0);
-  if (KS > 1) load(x1, y1, 1);
-  for (int s = 0; s < KS; ++s) {
-    if (s + 2 < KS) load(x2, y2, s + 2);
-    compute(x0, y0, s);
+  // Three register stages with fixed roles (the loop is unrolled by 3): the
+  // rows of step s + 2 are in flight while step s multiplies.  A copy between
+  // stages would make the compiler wait for the loads in flight into the
+  // source.  Loads past the last step read the chunk's last row (the row
+  // index is clamped) and the steps past KS contribute zero.
+  T xq[3][4], yq[3][4];
+  if (KS > 0) {
+    load(xq[0], yq[0], 0);
+    load(xq[1], yq[1], 1);
+  }
+  for (int s = 0; s < KS; s += 3) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      x0[a] = x1[a];
-      y0[a] = y1[a];
-      x1[a] = x2[a];
-      y1[a] = y2[a];
+    for (int j = 0; j < 3; ++j) {
+      load(xq[(j + 2) % 3], yq[(j + 2) % 3], s + j + 2);
+      compute(xq[j], yq[j], s + j);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   double* out = part + static_cast<int64_t>(chunk) * npad * npad;

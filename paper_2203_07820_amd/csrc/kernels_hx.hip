@@ -241,32 +241,27 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
             if (l0 + j >= MC) bp[c][j] = static_cast<__bf16>(0.f);
       }
     };
-    // Pipeline: the raw FP32 rows of step kg + 2 are in flight while step kg
-    // multiplies; those of step kg + 1 are rounded to bf16 right after, so
-    // only one raw stage occupies registers.
-    bf8 a0[RPW], a1[RPW], p0[CPW];
-    float braw[CPW][8], bnext[CPW][8];
-    load_b(braw, 0);
-    load_a(a0, 0);
-    if (KB > 1) load_b(bnext, 1);
-    pack(braw, p0, 0);
-#pragma unroll 1
+    // Pipeline: the A fragments of step kg + 1 and the raw FP32 rows of step
+    // kg + 2 are in flight while step kg multiplies; the rows of step kg + 1
+    // are rounded to bf16 right after.  The loop is unrolled in full (KB is
+    // small) so that every buffer keeps a fixed role: a copy between buffers
+    // would make the compiler wait for the loads in flight into the source.
+    bf8 aq[2][RPW], pq[2][CPW];
+    float braw[2][CPW][8];
+    load_b(braw[0], 0);
+    load_a(aq[0], 0);
+    if (KB > 1) load_b(braw[1], 1);
+    pack(braw[0], pq[0], 0);
+#pragma unroll
     for (int kg = 0; kg < KB; ++kg) {
-      if (kg + 1 < KB) load_a(a1, kg + 1);
-      if (kg + 2 < KB) load_b(braw, kg + 2);
+      if (kg + 1 < KB) load_a(aq[(kg + 1) % 2], kg + 1);
+      if (kg + 2 < KB) load_b(braw[kg % 2], kg + 2);   // step kg's rows were packed one step ago
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(a0[r], p0[c], acc[r][c]);
-      if (kg + 1 < KB) {
-        pack(bnext, p0, kg + 1);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) a0[r] = a1[r];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) bnext[c][j] = braw[c][j];
-      }
+        for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(aq[kg % 2][r], pq[kg % 2][c], acc[r][c]);
+      if (kg + 1 < KB) pack(braw[(kg + 1) % 2], pq[(kg + 1) % 2], kg + 1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     // A fragments of this wave: tile (rt0 + r, k step kg) at element
