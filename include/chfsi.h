@@ -55,7 +55,8 @@ extern "C" {
 #define CHFSI_ENOMEM    (-2) /* device allocation failed                    */
 #define CHFSI_EHIP      (-3) /* HIP runtime or library error                */
 #define CHFSI_ECHOL     (-4) /* overlap matrix not positive definite        */
-#define CHFSI_EDIVERGE  (-5) /* non-finite values (e.g. b below lambda_max) */
+#define CHFSI_EDIVERGE  (-5) /* non-finite values, or a Ritz value above the
+                                 upper bound b (b below lambda_max)          */
 
 /* ---- arithmetic / storage precision ------------------------------------ */
 typedef enum {
@@ -174,6 +175,10 @@ typedef struct {
 /* Create a context on HIP device `device`; all work goes to `hip_stream`
  * (a hipStream_t; NULL means the legacy default stream). */
 int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream);
+/* Destroys the context.  It keeps a registry of the operators and networks
+ * built on it; while any of them is alive the call returns CHFSI_EINVAL,
+ * leaves the context untouched and usable, and names the count in
+ * chfsi_last_error(ctx): destroy them first.  NULL is a no-op. */
 int chfsi_ctx_destroy(chfsi_ctx* ctx);
 /* Text of the last error of this context ("" if none).  Valid until the next
  * call on the context.  ctx may be NULL (errors of chfsi_ctx_create). */
@@ -194,8 +199,11 @@ int chfsi_abi_sizes(int64_t* system, int64_t* params, int64_t* stats);
  * D = M^-1/2 of the GLL-lumped overlap, the nodal potential V + |k|^2/2 and
  * the projector tables (per atom node lists and per (cell, atom) cell
  * matrices split by node multiplicity).  Then uploads them.  The operator
- * keeps a pointer to ctx, which must outlive it.  CHFSI_EINVAL for p outside
- * [2, 7] or a mesh of 2^29 nodes or more.  Synchronous. */
+ * keeps a pointer to ctx, which refuses to be destroyed while the operator
+ * is alive.  CHFSI_EINVAL for p outside [2, 7], a mesh of 2^29 nodes or
+ * more, or a NaN or infinity anywhere in sys.  Synchronous.
+ * chfsi_op_destroy() also drops a batched-filter graph the context captured
+ * with this operator in it. */
 int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out);
 int chfsi_op_destroy(chfsi_op* op);
 

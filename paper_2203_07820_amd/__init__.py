@@ -192,7 +192,7 @@ class Context:
         if getattr(self, "h", None):
             for op in list(getattr(self, "_ops", ())):
                 op.close()
-            self.lib.chfsi_ctx_destroy(self.h)
+            self.check(self.lib.chfsi_ctx_destroy(self.h))
             self.h = None
 
     def __del__(self):

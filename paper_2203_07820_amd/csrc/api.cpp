@@ -149,6 +149,17 @@ double hx_flops(const chfsi_op* op, int64_t ncols) {
   return fl;
 }
 
+// the part of hx_flops that the cell kernel itself does: the cell products
+// and C (h P) per (cell, atom) pair, without the projection P = C^H X, which
+// the nonlocal kernels do before it
+double cell_kernel_flops(const chfsi_op* op, int64_t ncols) {
+  const HostTables& t = op->t;
+  const double cfl = t.cplx ? 4.0 : 1.0;
+  double fl = 2.0 * t.mcell * static_cast<double>(t.mcell) * static_cast<double>(ncols) * t.E * cfl;
+  if (t.has_proj) fl += 2.0 * t.mcell * 4.0 * static_cast<double>(ncols) * op->npairs * cfl;
+  return fl;
+}
+
 // Y = alpha (H~ Xk - c Xk) - beta Xp  accumulated into T (which must hold 0
 // on entry).  Xk, Xp, T are in the storage type of prec, logical ld.
 int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp, int64_t ldp, void* T,
@@ -178,7 +189,7 @@ int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp,
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     ctx->pending.emplace_back(e0, e1);
-    ctx->pending_flops.push_back(hx_flops(op, ncols));
+    ctx->pending_flops.push_back(cell_kernel_flops(op, ncols));
   }
   return 0;
 }
@@ -868,7 +879,9 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   // the graph is keyed by everything its nodes point at
   std::ostringstream key;
   key << m << ":" << prec << ":" << block << ":" << wsb << ":" << tab << ":" << tu.grid_per_cu << ":" << tu.contiguous;
-  for (const BItem& it : items) key << ":" << it.op << "," << it.X << "," << it.ncols << "," << it.ld;
+  // operators by id (never reused within the context), so that an operator
+  // built at a destroyed one's address cannot match a stale graph
+  for (const BItem& it : items) key << ":op" << it.op->id << "," << it.X << "," << it.ncols << "," << it.ld;
   if (key.str() != ctx->gkey || !ctx->gexec) {
     drop_graph(ctx);
     // Capture on the context's private stream (the caller's stream may be the
@@ -1078,6 +1091,22 @@ int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int m
   return 0;
 }
 
+// Checks the Ritz values of a pass: they must be finite and, since every Ritz
+// value lies in [lambda_min, lambda_max] (Cauchy interlacing), none may lie
+// above a valid upper bound b of the spectrum.  A Ritz value above b shows
+// that b is below lambda_max: the filter then amplifies the unwanted top of
+// the spectrum instead of damping it (Section 3.1), and the iteration
+// diverges.
+int check_ritz(chfsi_ctx* ctx, const double* th, const double* r, int64_t N, double b) {
+  for (int64_t i = 0; i < N; ++i)
+    if (!std::isfinite(th[i]) || (r && !std::isfinite(r[i])))
+      return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values or residuals");
+  for (int64_t i = 0; i < N; ++i)
+    if (b > 0.0 && th[i] > b + 1e-9 * std::fabs(b))
+      return fail(ctx, CHFSI_EDIVERGE, "a Ritz value lies above the upper bound b: b is below lambda_max");
+  return 0;
+}
+
 void record_hist(const chfsi_params& p, int i, double t_ms, double maxr, int prec, const double* th, int64_t N) {
   if (i < 0 || i >= p.hist_len) return;
   if (p.hist_time_ms) p.hist_time_ms[i] = t_ms;
@@ -1131,6 +1160,10 @@ int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
 
 int chfsi_ctx_destroy(chfsi_ctx* ctx) {
   if (!ctx) return 0;
+  if (!ctx->live_ops.empty() || !ctx->live_mlps.empty())
+    return fail(ctx, CHFSI_EINVAL,
+                std::to_string(ctx->live_ops.size()) + " operator(s) and " + std::to_string(ctx->live_mlps.size()) +
+                    " network(s) of this context are still alive: destroy them first");
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& pr : ctx->pending) {
     (void)hipEventDestroy(pr.first);
@@ -1166,6 +1199,19 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   if (sys->natoms > 0 && (!sys->pos || !sys->Z || !sys->s)) return fail(ctx, CHFSI_EINVAL, "null atom arrays");
   if (sys->has_proj && sys->natoms > 0 && (!sys->w || !sys->h_s || !sys->h_p))
     return fail(ctx, CHFSI_EINVAL, "null projector arrays");
+  // every floating-point input must be finite: a NaN or an infinity would
+  // reach every table built from it
+  {
+    bool fin = std::isfinite(sys->L) && std::isfinite(sys->k[0]) && std::isfinite(sys->k[1]) &&
+               std::isfinite(sys->k[2]);
+    for (int i = 0; i < sys->natoms && fin; ++i) {
+      fin = std::isfinite(sys->pos[3 * i]) && std::isfinite(sys->pos[3 * i + 1]) &&
+            std::isfinite(sys->pos[3 * i + 2]) && std::isfinite(sys->Z[i]) && std::isfinite(sys->s[i]);
+      if (fin && sys->has_proj)
+        fin = std::isfinite(sys->w[i]) && std::isfinite(sys->h_s[i]) && std::isfinite(sys->h_p[i]);
+    }
+    if (!fin) return fail(ctx, CHFSI_EINVAL, "non-finite value (NaN or infinity) in the system description");
+  }
   for (int i = 0; i < sys->natoms; ++i) {
     if (!(sys->s[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "Gaussian widths must be positive");
     if (sys->has_proj && !(sys->w[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "projector widths must be positive");
@@ -1245,6 +1291,8 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   std::vector<int32_t>().swap(t.atom_node);
   std::vector<double>().swap(t.pair_re);
   std::vector<double>().swap(t.pair_im);
+  op->id = ctx->next_op_id++;
+  ctx->live_ops.insert(op.get());
   *out = op.release();
   return 0;
 }
@@ -1389,7 +1437,11 @@ int chfsi_op_build_quadrature(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op*
 
 int chfsi_op_destroy(chfsi_op* op) {
   if (!op) return 0;
-  (void)hipStreamSynchronize(op->ctx->stream);
+  chfsi_ctx* ctx = op->ctx;
+  (void)hipStreamSynchronize(ctx->stream);
+  // a captured batched graph may point at this operator's tables
+  if (ctx->gkey.find(":op" + std::to_string(op->id) + ",") != std::string::npos) drop_graph(ctx);
+  ctx->live_ops.erase(op);
   for (void* p : op->allocs) (void)hipFree(p);
   delete op;
   return 0;
@@ -1520,10 +1572,7 @@ int chfsi_pass(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, doub
   std::vector<double> r(N);
   CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N, X, ld, N, theta, r.data()));
   if (resid) std::memcpy(resid, r.data(), N * 8);
-  for (int64_t i = 0; i < N; ++i)
-    if (!std::isfinite(theta[i]) || !std::isfinite(r[i]))
-      return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
-  return 0;
+  return check_ritz(ctx, theta, r.data(), N, b);
 }
 
 int chfsi_fermi_level(const double* theta, int32_t n, const double* weights, double n_electrons, double kT,
@@ -1908,9 +1957,7 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
     st.t_rr += event_ms(ev[4], ev[5]);
     st.hx_columns += static_cast<int64_t>(N) * prm->m + N;
     ++passes;
-    for (int64_t i = 0; i < N; ++i)
-      if (!std::isfinite(th[i]) || !std::isfinite(r[i]))
-        return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values (upper bound below lambda_max?)");
+    CHECK(check_ritz(ctx, th.data(), r.data(), N, b));
     rhist.push_back(max_r());
     record_hist(*prm, passes, event_ms(ev[0], ev[5]), rhist.back(), fprec, th.data(), N);
     st.final_prec = fprec;
@@ -2060,9 +2107,7 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
       trr[q] += event_ms(e0, e1);
       tfilt[q] += tf;
       ++passes[q];
-      for (int64_t i = 0; i < N[q]; ++i)
-        if (!std::isfinite(th[q][i]) || !std::isfinite(r[q][i]))
-          return fail(ctx, CHFSI_EDIVERGE, "non-finite Ritz values");
+      CHECK(check_ritz(ctx, th[q].data(), r[q].data(), N[q], bq[q]));
       record_hist(params[q], passes[q], event_ms(es, e1), maxr_of(q), prec, th[q].data(), N[q]);
     }
   }

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -54,10 +55,16 @@ struct chfsi_ctx {
   hipGraph_t graph = nullptr;       // captured batched filter
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  // live operators and networks: the context refuses to be destroyed while
+  // any is alive (they hold its stream and scratch), and a captured graph is
+  // keyed by operator ids, which are never reused, instead of addresses
+  std::set<const void*> live_ops, live_mlps;
+  uint64_t next_op_id = 1;
 };
 
 struct chfsi_op {
   chfsi_ctx* ctx = nullptr;
+  uint64_t id = 0;                   // unique within the context
   HostTables t;                      // host copies (large projector arrays dropped)
   int64_t npairs = 0;
   // device tables

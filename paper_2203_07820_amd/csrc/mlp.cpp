@@ -249,6 +249,7 @@ int chfsi_mlp_create(chfsi_ctx* ctx, int32_t din, int32_t hidden, int32_t dout, 
     *bufs[i] = static_cast<float*>(p);
     HIP_TRY(ctx, hipMemcpy(p, init[i], sizes[i] * 4, hipMemcpyHostToDevice));
   }
+  ctx->live_mlps.insert(n.get());
   *out = n.release();
   return 0;
 }
@@ -256,6 +257,7 @@ int chfsi_mlp_create(chfsi_ctx* ctx, int32_t din, int32_t hidden, int32_t dout, 
 int chfsi_mlp_destroy(chfsi_mlp* n) {
   if (!n) return 0;
   (void)hipStreamSynchronize(n->ctx->stream);
+  n->ctx->live_mlps.erase(n);
   float* bufs[6] = {n->params, n->grads, n->m, n->v, n->mean, n->stdv};
   for (float* b : bufs) if (b) (void)hipFree(b);
   for (int i = 0; i < M_COUNT; ++i) if (n->ws[i]) (void)hipFree(n->ws[i]);

@@ -9,6 +9,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
 import workloads
 from oracle import chfsi as ochfsi
@@ -144,3 +145,70 @@ def test_autotune_writes_cache_and_is_used(ctx, tmp_path):
     assert (t2["grid_per_cu"], t2["contiguous"]) == (t["grid_per_cu"], t["contiguous"])
     assert abs(t2["ms"] - t["ms"]) <= 1e-4 * t["ms"]
     c2.close()
+
+
+def _c3_like():
+    """Uneven p = 5 boxes with atoms and projectors, each at the 4 k-points of
+    the reduced shifted Monkhorst-Pack grid: the shape of the batched k-point
+    workload, at sizes the oracle filters in seconds."""
+    out = []
+    for (nc, na, seed) in [(2, 2, 21), (3, 3, 22)]:
+        base = workloads.small_system(nc, 5, na, seed=seed, has_proj=True)
+        for k in workloads.kpoints_mp4(base.L):
+            out.append(base.with_k(k))
+    return out
+
+
+_C3_COLS = [24, 9, 40, 17, 33, 48, 12, 29]
+
+
+@pytest.fixture(scope="module")
+def c3_like_refs():
+    """Oracle filters (degree 8, block 16) of every problem of the batch."""
+    systems = _c3_like()
+    refs, params, X0 = [], [], []
+    for q, s in enumerate(systems):
+        H = fe.assemble(fe.build_operator(s))
+        lmax = float(spla.eigsh(H, k=1, which="LA", return_eigenvectors=False)[0])
+        n = _C3_COLS[q]
+        # any aL < a < b gives a well-defined filter to compare
+        a, b, aL = 0.05 * lmax, lmax * 1.05, -0.1 * lmax
+        X = workloads.start_block(s.M, n, seed=300 + q, complex_=True)
+        refs.append(ochfsi.cheb_filter(lambda v: H @ v, X, 8, a, b, aL))
+        params.append((a, b, aL))
+        X0.append(X)
+    return systems, refs, params, X0
+
+
+# every launch shape of the batched cell kernel: one workgroup per item
+# (grid_per_cu = 0), and persistent grids of 1, 2 and 4 workgroups per CU
+# with contiguous or strided item assignment
+TUNINGS = [(0, 1), (1, 1), (1, 0), (2, 1), (2, 0), (4, 1), (4, 0)]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_batched_p5_kpoints_every_launch_shape(c3_like_refs, tmp_path, tuning, prec):
+    systems, refs, params, X0 = c3_like_refs
+    P = lib.C128 if prec == "c128" else lib.C64
+    block = 16
+    path = tmp_path / "tune.json"
+    path.write_text('[\n{"key": "gfx950:p5:prec%d:B%d", "grid_per_cu": %d, "contiguous": %d, "ms": 1.0}\n]\n'
+                    % (P, block, tuning[0], tuning[1]))
+    c = lib.Context(0)
+    c.load_tuning(str(path))
+    assert c.get_tuning(5, P, block)["grid_per_cu"] == tuning[0]
+    ops = [lib.Operator(c, s) for s in systems]
+    Xd = [dev(X) for X in X0]
+    c.filter_batched(ops, Xd, 8, [p[0] for p in params], [p[1] for p in params], [p[2] for p in params], P,
+                     block=block, use_graph=True)
+    tol_oracle, tol_alone = (1e-11, 1e-12) if prec == "c128" else (5e-5, 2e-5)
+    for q in range(len(ops)):
+        got = host(Xd[q])
+        assert relerr(got, refs[q]) < tol_oracle, q
+        Xi = dev(X0[q])
+        ops[q].filter(Xi, 8, *params[q], prec=P, block=block)
+        assert relerr(got, host(Xi)) < tol_alone, q
+    for op in ops:
+        op.close()
+    c.close()

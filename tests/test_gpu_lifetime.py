@@ -1,0 +1,150 @@
+"""Lifetime rules and failure paths of the C ABI (include/chfsi.h).
+
+* The context keeps a registry of its operators and networks and refuses to
+  be destroyed while any is alive (CHFSI_EINVAL, context left usable).
+* A batched-filter graph captured with an operator in it is never replayed
+  after that operator is destroyed, even when a new operator of the same
+  size lands at the same host address.
+* A NaN or infinity in the system description is rejected (CHFSI_EINVAL).
+* An upper bound b below lambda_max makes the filter amplify the top of the
+  spectrum (Section 3.1): a Ritz value then exceeds b, which no valid bound
+  allows (Cauchy interlacing), and the solve stops with CHFSI_EDIVERGE.
+"""
+import ctypes as C
+import os
+import subprocess
+import sys
+import textwrap
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fe
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2203_07820_amd as lib  # noqa: E402
+from paper_2203_07820_amd import _lib  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EINVAL, EDIVERGE = -1, -5
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_ctx_destroy_refused_while_operator_alive_and_process_exits_cleanly():
+    # raw C ABI in a child process, so that its exit status is observed
+    code = textwrap.dedent(f"""
+        import ctypes as C, sys
+        sys.path.insert(0, {ROOT!r})
+        import numpy as np, torch
+        import workloads
+        from paper_2203_07820_amd import _lib
+        lib = _lib.load()
+        torch.cuda.init()
+        ctx = C.c_void_p()
+        assert lib.chfsi_ctx_create(C.byref(ctx), 0, None) == 0
+        s = workloads.small_system(2, 3, 1, seed=5, has_proj=True)
+        keep = [np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (s.pos, s.Z, s.s, s.w, s.h_s, s.h_p)]
+        sy = _lib.System()
+        sy.L, sy.ncell, sy.p, sy.natoms, sy.has_proj = s.L, s.ncell, s.p, s.natoms, 1
+        ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        sy.pos, sy.Z, sy.s, sy.w, sy.h_s, sy.h_p = [ptr(a) for a in keep]
+        op = C.c_void_p()
+        assert lib.chfsi_op_build(ctx, C.byref(sy), C.byref(op)) == 0
+        net = C.c_void_p()
+        assert lib.chfsi_mlp_create(ctx, 32, 16, 8, 1, C.byref(net)) == 0
+        rc = lib.chfsi_ctx_destroy(ctx)
+        msg = lib.chfsi_last_error(ctx).decode()
+        print("refused", rc, msg, flush=True)
+        assert rc == {EINVAL} and "alive" in msg, (rc, msg)
+        assert lib.chfsi_op_destroy(op) == 0
+        assert lib.chfsi_ctx_destroy(ctx) == {EINVAL}       # the network is still alive
+        assert lib.chfsi_mlp_destroy(net) == 0
+        assert lib.chfsi_sync(ctx) == 0                    # still a valid context
+        assert lib.chfsi_ctx_destroy(ctx) == 0
+        print("clean", flush=True)
+    """)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "refused -1" in r.stdout and "clean" in r.stdout
+
+
+def test_context_close_releases_operators_first():
+    ctx = lib.Context(0)
+    ops = [lib.Operator(ctx, workloads.small_system(2, 3, 1, seed=6, has_proj=True)) for _ in range(2)]
+    ctx.close()
+    assert all(op.h is None for op in ops)
+
+
+def test_batched_graph_not_replayed_after_operator_destroyed():
+    ctx = lib.Context(0)
+    systems = [workloads.small_system(2, 3, 2, seed=31 + i, has_proj=True) for i in range(2)]
+    ncols, m = 12, 6
+
+    def block(op, seed):
+        return torch.from_numpy(workloads.start_block(op.M, ncols, seed=seed)).cuda()
+
+    ops = [lib.Operator(ctx, s) for s in systems]
+    ab = [(0.5, 30.0, -2.0)] * 2
+    X = [block(op, 40 + i) for i, op in enumerate(ops)]
+    ctx.filter_batched(ops, X, m, [t[0] for t in ab], [t[1] for t in ab], [t[2] for t in ab], lib.F64,
+                       block=ncols, use_graph=True)
+    old_addr = ops[1].h.value
+    ops[1].close()
+    # a different system of the same size: its tables differ from the destroyed one's
+    s_new = workloads.small_system(2, 3, 2, seed=99, has_proj=True)
+    ops[1] = lib.Operator(ctx, s_new)
+    X = [block(op, 40 + i) for i, op in enumerate(ops)]
+    ctx.filter_batched(ops, X, m, [t[0] for t in ab], [t[1] for t in ab], [t[2] for t in ab], lib.F64,
+                       block=ncols, use_graph=True)
+    for i, op in enumerate(ops):
+        Xi = block(op, 40 + i)
+        op.filter(Xi, m, *ab[i], prec=lib.F64, block=ncols)
+        got, ref = host(X[i]), host(Xi)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), (i, ops[1].h.value == old_addr)
+    ctx.close()
+
+
+def test_non_finite_system_rejected():
+    ctx = lib.Context(0)
+    s = workloads.small_system(2, 3, 2, seed=7, has_proj=True)
+    for field, idx in (("pos", (1, 2)), ("Z", 0), ("s", 1), ("w", 0), ("h_p", 1), ("k", 0), ("L", None)):
+        bad = workloads.System(**{f: (np.array(getattr(s, f), dtype=np.float64).copy()
+                                      if isinstance(getattr(s, f), np.ndarray) else getattr(s, f))
+                                  for f in ("L", "ncell", "p", "pos", "Z", "s", "has_proj", "w", "h_s", "h_p",
+                                            "k", "seed")})
+        if idx is None:
+            bad.L = float("nan")
+        else:
+            getattr(bad, field)[idx] = np.inf if field == "h_p" else np.nan
+        with pytest.raises(lib.ChfsiError) as ei:
+            lib.Operator(ctx, bad)
+        assert ei.value.code == EINVAL and "non-finite" in str(ei.value), field
+    ctx.close()
+
+
+def test_bound_below_lambda_max_returns_ediverge():
+    ctx = lib.Context(0)
+    s = workloads.small_system(2, 3, 2, seed=8, has_proj=True)
+    op = lib.Operator(ctx, s)
+    lam = np.linalg.eigvalsh(fe.assemble(fe.build_operator(s)).toarray())
+    N = 8
+    X = torch.from_numpy(workloads.start_block(op.M, N, seed=9)).cuda()
+    # a valid bound converges
+    th, r, st = op.solve(X, N, m=10, block=N, fixed_passes=3, b_upper=1.01 * lam[-1])
+    assert np.all(th <= lam[-1] + 1e-9)
+    # half of lambda_max: the filter grows the top of the spectrum
+    X = torch.from_numpy(workloads.start_block(op.M, N, seed=9)).cuda()
+    with pytest.raises(lib.ChfsiError) as ei:
+        op.solve(X, N, m=10, block=N, fixed_passes=3, b_upper=0.5 * lam[-1])
+    assert ei.value.code == EDIVERGE, str(ei.value)
+    ctx.close()
