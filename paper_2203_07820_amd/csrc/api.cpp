@@ -1193,9 +1193,6 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   if (!sys || !out) return fail(ctx, CHFSI_EINVAL, "null argument");
   *out = nullptr;
   if (sys->p < kMinOrder || sys->p > kMaxOrder) return fail(ctx, CHFSI_EINVAL, "order p must be in [2, 7]");
-  if (sys->ncell < 1 || !(sys->L > 0.0) || sys->natoms < 0) return fail(ctx, CHFSI_EINVAL, "bad mesh size");
-  const int64_t n = static_cast<int64_t>(sys->ncell) * sys->p;
-  if (n * n * n >= (1LL << 29)) return fail(ctx, CHFSI_EINVAL, "mesh too large (node ids must stay below 2^29)");
   if (sys->natoms > 0 && (!sys->pos || !sys->Z || !sys->s)) return fail(ctx, CHFSI_EINVAL, "null atom arrays");
   if (sys->has_proj && sys->natoms > 0 && (!sys->w || !sys->h_s || !sys->h_p))
     return fail(ctx, CHFSI_EINVAL, "null projector arrays");
@@ -1212,6 +1209,9 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
     }
     if (!fin) return fail(ctx, CHFSI_EINVAL, "non-finite value (NaN or infinity) in the system description");
   }
+  if (sys->ncell < 1 || !(sys->L > 0.0) || sys->natoms < 0) return fail(ctx, CHFSI_EINVAL, "bad mesh size");
+  const int64_t n = static_cast<int64_t>(sys->ncell) * sys->p;
+  if (n * n * n >= (1LL << 29)) return fail(ctx, CHFSI_EINVAL, "mesh too large (node ids must stay below 2^29)");
   for (int i = 0; i < sys->natoms; ++i) {
     if (!(sys->s[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "Gaussian widths must be positive");
     if (sys->has_proj && !(sys->w[i] > 0.0)) return fail(ctx, CHFSI_EINVAL, "projector widths must be positive");
