@@ -239,6 +239,23 @@ int chfsi_op_tables(const chfsi_op* op, double* xyz, double* cell_re, double* ce
  * Asynchronous. */
 int chfsi_apply(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld, int32_t prec);
 
+/* ---- H~.X without allocation ----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Y = H~ X as chfsi_apply(), same arguments, layouts and kernels, but the
+ * projector partials and coefficients live in a fixed file-scope device
+ * scratch of 64 MiB per device (held until the process ends) instead of
+ * context workspace, and the call makes no hipMalloc, hipFree or allocating
+ * library call.  The scratch need is align256(nchunks * 4 * ldhp * s) +
+ * natoms * 4 * ldhp * s bytes with ldhp = ncols (x2 if complex) rounded up
+ * to 64 and s = 8 (F64, C128) or 4 bytes; a call that needs more returns
+ * CHFSI_EINVAL before any work is enqueued (c1-size operators fit 128 FP64
+ * columns).  Every call on one device shares that device's scratch, and
+ * every entry a call reads it writes first, so nothing is carried over
+ * between calls; calls that overlap in time on one device (different
+ * streams or contexts) race.  Asynchronous. */
+int chfsi_apply_noalloc(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld, int32_t prec);
+
 /* ---- upper bound of the spectrum ----------------------------------------
  * `steps`-step Lanczos run without reorthogonalisation from v0 (device, M
  * real or M complex values; NULL draws one from `seed`):

@@ -16,7 +16,7 @@ RHO_NODES, RHO_GAUSS = 0, 1
 EXPORTS = [
     "chfsi_ctx_create", "chfsi_ctx_destroy", "chfsi_last_error", "chfsi_sync", "chfsi_version", "chfsi_abi_sizes",
     "chfsi_op_build", "chfsi_op_destroy", "chfsi_op_info", "chfsi_op_tables",
-    "chfsi_apply", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
+    "chfsi_apply", "chfsi_apply_noalloc", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_kernel_time",
     "chfsi_filter_batched", "chfsi_solve_batched", "chfsi_autotune", "chfsi_load_tuning", "chfsi_get_tuning",
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
@@ -87,6 +87,7 @@ def load() -> C.CDLL:
                                     C.POINTER(i64), C.POINTER(i32)]),
         "chfsi_op_tables": (C.c_int, [vp, pd, pd, pd, pd, pd]),
         "chfsi_apply": (C.c_int, [vp, vp, vp, i64, i64, i32]),
+        "chfsi_apply_noalloc": (C.c_int, [vp, vp, vp, i64, i64, i32]),
         "chfsi_bounds": (C.c_int, [vp, i32, vp, u64, pd, pd]),
         "chfsi_filter": (C.c_int, [vp, vp, i64, i64, i32, dbl, dbl, dbl, i32, i32]),
         "chfsi_orthonormalize": (C.c_int, [vp, vp, i64, i64, pd]),

@@ -1150,6 +1150,15 @@ int chfsi_ctx_create(chfsi_ctx** out, int device, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, CHFSI_EHIP, "hipGetDeviceProperties failed");
   c->ncu = prop.multiProcessorCount;
+  // the fixed scratch of chfsi_apply_noalloc(): its address on this device
+  // (device current), kept for the context's lifetime
+  {
+    const hipError_t e = scratch_address(&c->scratch);
+    if (e != hipSuccess) {
+      c->scratch = nullptr;
+      c->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    }
+  }
   if (rocblas_create_handle(&c->blas) != rocblas_status_success)
     return fail(nullptr, CHFSI_EHIP, "rocblas_create_handle failed");
   if (rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
@@ -1492,6 +1501,39 @@ int chfsi_apply(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld,
   const int sp = storage_of(prec);
   HIP_TRY(ctx, launch_fill(Y, op->t.M, ncols * cf, ld * cf, sp, ctx->stream));
   return hx_step(op, prec, X, ld, nullptr, ld, Y, ld, ncols, 1.0, 0.0, 0.0, false);
+}
+
+int chfsi_apply_noalloc(chfsi_op* op, const void* X, void* Y, int64_t ncols, int64_t ld, int32_t prec) {
+  if (!op) return CHFSI_EINVAL;
+  chfsi_ctx* ctx = op->ctx;
+  CHECK(check_block(op, X, ncols, ld));
+  if (!Y) return fail(ctx, CHFSI_EINVAL, "null output");
+  if (!prec_valid_for(op, prec)) return fail(ctx, CHFSI_EINVAL, "precision does not match the operator");
+  if (X == Y) return fail(ctx, CHFSI_EINVAL, "X and Y must not overlap");
+  const HostTables& t = op->t;
+  const int cf = t.cplx ? 2 : 1;
+  const int sp = storage_of(prec);
+  // scratch layout: chunk partials (nchunks*4 x ldhp), then h P (natoms*4 x ldhp)
+  const size_t eb = is_single(prec) ? 4 : 8;
+  const int64_t ldhp = t.has_proj ? hp_ld(op, ncols) : 0;
+  const size_t part_bytes = t.has_proj ? align256(static_cast<size_t>(op->nchunks) * 4 * ldhp * eb) : 0;
+  const size_t need = t.has_proj ? part_bytes + static_cast<size_t>(t.natoms) * 4 * ldhp * eb : 0;
+  if (need > kScratchBytes)
+    return fail(ctx, CHFSI_EINVAL,
+                "chfsi_apply_noalloc needs " + std::to_string(need) + " bytes of scratch for " +
+                    std::to_string(ncols) + " columns; the fixed scratch holds " + std::to_string(kScratchBytes) +
+                    " (use fewer columns per call, or chfsi_apply)");
+  if (t.has_proj && !ctx->scratch) return fail(ctx, CHFSI_EHIP, "fixed scratch unavailable: " + ctx->scratch_err);
+  HIP_TRY(ctx, launch_fill(Y, t.M, ncols * cf, ld * cf, sp, ctx->stream));
+  void* hP = nullptr;
+  if (t.has_proj) {
+    char* base = static_cast<char*>(ctx->scratch);
+    hP = base + part_bytes;
+    CHECK(nl_project(op, prec, X, ld, ncols, base, hP, ldhp));
+  }
+  const HxLaunch L = make_hx(op, prec, X, ld, nullptr, ld, Y, ld, ncols, 1.0, 0.0, 0.0, false, hP, ldhp);
+  HIP_TRY(ctx, launch_cell_hx(L, prec, ctx->stream));
+  return 0;
 }
 
 int chfsi_bounds(chfsi_op* op, int32_t steps, const void* v0, uint64_t seed, double* b_upper, double* lmin_est) {

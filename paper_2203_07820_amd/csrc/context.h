@@ -59,6 +59,10 @@ struct chfsi_ctx {
   // any is alive (they hold its stream and scratch), and a captured graph is
   // keyed by operator ids, which are never reused, instead of addresses
   std::set<const void*> live_ops, live_mlps;
+  // device address of this device's fixed scratch (chfsi_apply_noalloc),
+  // resolved once at context creation, or null with the reason
+  void* scratch = nullptr;
+  std::string scratch_err;
   uint64_t next_op_id = 1;
 };
 

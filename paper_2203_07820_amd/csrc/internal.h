@@ -124,6 +124,12 @@ struct NlLaunch {
 };
 hipError_t launch_nl_project(const NlLaunch& a, int prec, hipStream_t s);
 
+// Size of the fixed device scratch of chfsi_apply_noalloc() (kernels_nl.hip),
+// and its device address on the current device (call with that device
+// current; each device has its own copy).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(void** out);
+
 // Electron density (kernels_density.hip).  points 0: at the nodes (M
 // values); 1: at the (p+1)^3 Gauss points of every cell (E x (p+1)^3).
 struct DensityLaunch {

@@ -199,4 +199,18 @@ hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, in
   return hipGetLastError();
 }
 
+// ---- fixed scratch for the allocation-free H~.X ------------------------------
+// The projector partials and coefficients of chfsi_apply_noalloc() live in
+// this file-scope device array instead of context workspace.  Each device the
+// library runs on holds its own copy (kScratchBytes) until the process ends.
+// Host code must never pass the array's name to a kernel: in host code it is
+// a host-side stand-in, not a device address.  scratch_address() resolves the
+// address for the current device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out) {
+  *out = nullptr;
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 }  // namespace chfsi
