@@ -137,6 +137,7 @@ HxLaunch make_hx(const chfsi_op* op, int prec, const void* Xk, int64_t ldx, cons
   L.hP = hP;
   L.ldhp = ldhp;
   L.Abf = op->Abf;
+  L.ncu = op->ctx->ncu;
   return L;
 }
 
@@ -216,7 +217,9 @@ void cheb_coeffs(int m, double a, double b, double aL, double* c, std::vector<do
 
 // Filter one block already converted into R0 (storage of prec, ld = ncols).
 // Returns the index of the buffer holding the result.
-int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int m, double a, double b,
+// Filters the block held in R[0] (ncols columns, leading dimension ldr) with
+// the buffers R[1..3]; the result is in R[*out_idx].
+int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int64_t ldr, int m, double a, double b,
                  double aL, int* out_idx) {
   chfsi_ctx* ctx = op->ctx;
   const int cf = op->t.cplx ? 2 : 1;
@@ -225,10 +228,10 @@ int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int m,
   std::vector<double> al, be;
   cheb_coeffs(m, a, b, aL, &c, al, be);
   const int sp = storage_of(prec);
-  for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R[i], M, ncols * cf, ncols * cf, sp, ctx->stream));
-  CHECK(hx_step(op, prec, R[0], ncols, nullptr, ncols, R[1], ncols, ncols, al[0], c, 0.0, false));
+  for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R[i], M, ncols * cf, ldr * cf, sp, ctx->stream));
+  CHECK(hx_step(op, prec, R[0], ldr, nullptr, ldr, R[1], ldr, ncols, al[0], c, 0.0, false));
   for (int i = 2; i <= m; ++i) {
-    CHECK(hx_step(op, prec, R[(i - 1) % 4], ncols, R[(i - 2) % 4], ncols, R[i % 4], ncols, ncols, al[i - 1], c,
+    CHECK(hx_step(op, prec, R[(i - 1) % 4], ldr, R[(i - 2) % 4], ldr, R[i % 4], ldr, ncols, al[i - 1], c,
                   be[i - 1], true));
   }
   *out_idx = m % 4;
@@ -244,15 +247,19 @@ int do_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int m, double a,
   const int sp = storage_of(prec);
   if (block <= 0 || block > ncols) block = ncols;
   const size_t eb = prec_bytes(sp);
+  // the work buffers' rows are padded to a multiple of 4 columns (16-byte
+  // aligned rows for the bf16 kernel's block loads)
+  const int64_t ldmax = (block + 3) / 4 * 4;
   void* R[4];
-  for (int i = 0; i < 4; ++i) CHECK(ws_get(ctx, WS_R0 + i, static_cast<size_t>(t.M) * block * eb, &R[i]));
+  for (int i = 0; i < 4; ++i) CHECK(ws_get(ctx, WS_R0 + i, static_cast<size_t>(t.M) * ldmax * eb, &R[i]));
   for (int64_t c0 = 0; c0 < ncols; c0 += block) {
     const int64_t nb = std::min<int64_t>(block, ncols - c0);
+    const int64_t ldr = (nb + 3) / 4 * 4;
     double* Xb = static_cast<double*>(X) + c0 * cf;
-    HIP_TRY(ctx, launch_convert(R[0], nb * cf, sp, Xb, ld * cf, xprec, t.M, nb * cf, ctx->stream));
+    HIP_TRY(ctx, launch_convert(R[0], ldr * cf, sp, Xb, ld * cf, xprec, t.M, nb * cf, ctx->stream));
     int idx = 0;
-    CHECK(filter_block(op, prec, R, nb, m, a, b, aL, &idx));
-    HIP_TRY(ctx, launch_convert(Xb, ld * cf, xprec, R[idx], nb * cf, sp, t.M, nb * cf, ctx->stream));
+    CHECK(filter_block(op, prec, R, nb, ldr, m, a, b, aL, &idx));
+    HIP_TRY(ctx, launch_convert(Xb, ld * cf, xprec, R[idx], ldr * cf, sp, t.M, nb * cf, ctx->stream));
   }
   return 0;
 }

@@ -88,6 +88,7 @@ struct HxLaunch {
   const void* hP; int64_t ldhp;    // scaled projector coefficients (real view)
   const void* Abf = nullptr;       // bf16 cell matrix in 16x16x32 operand order
   int64_t astride = 0;             // per-cell real matrices: elements per cell (0: shared)
+  int ncu = 0;                     // compute units (persistent launches)
 };
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).

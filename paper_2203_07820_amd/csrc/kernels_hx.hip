@@ -18,14 +18,17 @@
 //      contributor).  The owner cell of each node (local indices all < p) adds
 //      alpha (V_j - c) X_k[j] - beta X_{k-1}[j], so the target ends up holding
 //      X_{k+1} = alpha (H~ X_k - c X_k) - beta X_{k-1} without a separate pass;
-//      the owner then zeroes X_{k-1}[j], which becomes the target two steps on.
+//      the owner then zeroes X_{k-1}[j], which becomes the target two steps on
+//      (nodes interior to the cell excepted: their value is stored, not added).
 //
 // Node numbering: n = ncell * p nodes per direction, node (ix, iy, iz) has id
 // ix + n (iy + n iz); cell (cx, cy, cz) local node (a, b, c) is global node
 // ((cx p + a) mod n, ...).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -123,50 +126,16 @@ template <int MP, typename T> struct RowTables {
   T wv[MP];     // alpha (V_j - c) for owned rows, 0 otherwise
 };
 
-// One work item: cell `cell`, columns [col0, col0 + 64).
-//
-// Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
-// number of 16-row tiles is even for every order p in [2, 7], so each wave
-// owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
-// B fragments are read straight from global memory into registers (no LDS
-// staging of X, no barriers in the loop): in a 4-wide k step, lanes
-// 16 q .. 16 q + 15 read 16 consecutive columns of cell row 4 kg + q, one
-// cache line per 16 lanes, at the row offset kept in the LDS table.  A
-// fragments come through buffer loads whose per-row-tile offsets live in
-// scalar registers; they are loaded one k step ahead and B fragments two
-// (HBM latency), the A load of the next step issued before the B load two
-// steps ahead, so that the in-order vector-memory counter never makes an MFMA
-// wait on HBM.  Column lanes beyond ncols read a valid column and are never
-// stored; padding rows (l >= mcell) are zeroed.
-//
-// BF selects the bf16 cell products (FP32 iterates): a 32-wide k step needs
-// 8 cell rows per lane; the FP32 values are rounded to bf16 (to nearest even)
-// in registers.
-template <int P, typename T, bool CPLX, int WAVES, bool BF, int ED>
-__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
-                                          RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
+// Fills the per-cell row tables of `cell` (threads tid, tid + nthr, ...).
+template <int P, typename T>
+__device__ __forceinline__ void row_tables(const HxArgs<T>& a, const int cell, const int tid, const int nthr,
+                                           RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
   constexpr int Q = P + 1;
   constexpr int MC = Q * Q * Q;
   constexpr int MP = (MC + 15) / 16 * 16;
-  constexpr int RT = MP / 16;           // row tiles
-  constexpr int KS = MP / 4;            // 4-wide k steps
-  constexpr int RG = WAVES / 2;         // row groups
-  constexpr int RPW = RT / RG;          // row tiles per wave
-  constexpr int CPW = kNT / 32;         // column tiles per wave (2 column groups)
-  static_assert(RT % RG == 0 && KS % 2 == 0, "tiling");
-  static_assert(!BF || (MP % 32 == 0 && !CPLX && sizeof(T) == 4), "bf16 variant: real FP32 iterates");
-  using acc_t = typename Mma<T>::acc_t;
-
-  const int tid = threadIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
-  const int lane = tid % 64;
-  const int rt0 = (wave / 2) * RPW, ct0 = (wave % 2) * CPW;
   const int nc = a.nc, n = nc * P;
   const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
-
-  // row tables (the barrier in front protects the previous item's readers)
-  __syncthreads();
-  for (int l = tid; l < MP; l += 64 * WAVES) {
+  for (int l = tid; l < MP; l += nthr) {
     int32_t g = -1;
     int64_t off = 0;
     T w = T(0);
@@ -186,170 +155,22 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     tab.gid[l] = g;
     tab.wv[l] = w;
   }
-  __syncthreads();
+}
 
-  acc_t acc[RPW][CPW];
-#pragma unroll
-  for (int r = 0; r < RPW; ++r)
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
-
-  // per-lane column pointers, clamped to a valid column; complex blocks keep
-  // the lane's parity (re/im) so that the partner column cc ^ 1 stays valid
-  // (their ncols, counted in reals, is even)
-  const T* xcol[CPW];
-#pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    int cc = col0 + (ct0 + c) * 16 + lane % 16;
-    if (cc >= a.ncols) cc = CPLX ? a.ncols - 2 + (lane & 1) : a.ncols - 1;
-    xcol[c] = a.Xk + cc;
-  }
-
-  if constexpr (BF) {
-    constexpr int KB = MP / 32;         // 32-wide k steps
-    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.Ab, static_cast<uint32_t>(RT) * KB * 64 * 16);
-    int soff[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KB * 64 * 16);
-    auto load_a = [&](bf8 (&av)[RPW], int kg) {
-      const int vo = (kg * 64 + lane) * 16;
-#pragma unroll
-      for (int r = 0; r < RPW; ++r) av[r] = buf_load<bf8>(ra, vo, soff[r]);
-    };
-    auto load_b = [&](float (&bv)[CPW][8], int kg) {
-      const int l0 = kg * 32 + 8 * (lane / 16);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t off = tab.xoff[l0 + j];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) bv[c][j] = xcol[c][off];
-      }
-    };
-    // rounds the rows of step kg to bf16; padding rows (>= mcell) become 0
-    // here, at use, so that no wait is forced at the load
-    auto pack = [&](const float (&bv)[CPW][8], bf8 (&bp)[CPW], int kg) {
-      const int l0 = kg * 32 + 8 * (lane / 16);
-#pragma unroll
-      for (int c = 0; c < CPW; ++c)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bp[c][j] = static_cast<__bf16>(bv[c][j]);
-      if ((kg + 1) * 32 > MC) {
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (l0 + j >= MC) bp[c][j] = static_cast<__bf16>(0.f);
-      }
-    };
-    // Pipeline: the A fragments of step kg + 1 and the raw FP32 rows of step
-    // kg + 2 are in flight while step kg multiplies; the rows of step kg + 1
-    // are rounded to bf16 right after.  The loop is unrolled in full (KB is
-    // small) so that every buffer keeps a fixed role: a copy between buffers
-    // would make the compiler wait for the loads in flight into the source.
-    bf8 aq[2][RPW], pq[2][CPW];
-    float braw[2][CPW][8];
-    load_b(braw[0], 0);
-    load_a(aq[0], 0);
-    if (KB > 1) load_b(braw[1], 1);
-    pack(braw[0], pq[0], 0);
-#pragma unroll
-    for (int kg = 0; kg < KB; ++kg) {
-      if (kg + 1 < KB) load_a(aq[(kg + 1) % 2], kg + 1);
-      if (kg + 2 < KB) load_b(braw[kg % 2], kg + 2);   // step kg's rows were packed one step ago
-#pragma unroll
-      for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(aq[kg % 2][r], pq[kg % 2][c], acc[r][c]);
-      if (kg + 1 < KB) pack(braw[(kg + 1) % 2], pq[(kg + 1) % 2], kg + 1);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  } else {
-    // A fragments of this wave: tile (rt0 + r, k step kg) at element
-    // ((rt0 + r) KS + kg) 64 + lane
-    constexpr int RI = CPLX ? RPW : 1;
-    constexpr int CI = CPLX ? CPW : 1;
-    const uint32_t abytes = static_cast<uint32_t>(RT) * KS * 64 * sizeof(T);
-    const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.A + static_cast<int64_t>(cell) * a.astride, abytes);
-    const __amdgpu_buffer_rsrc_t rai = make_rsrc(CPLX ? a.Ai : a.A, abytes);
-    int soff[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KS * 64 * static_cast<int>(sizeof(T)));
-    // both loaders clamp the k step to the last one, so that the pipeline's
-    // loads past the end (never used) read valid memory without a branch
-    auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
-      const int vo = ((kg < KS ? kg : KS - 1) * 64 + lane) * static_cast<int>(sizeof(T));
-#pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        av[r] = buf_load<T>(ra, vo, soff[r]);
-        if constexpr (CPLX) avi[r] = buf_load<T>(rai, vo, soff[r]);
-      }
-    };
-    auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
-      const int l = (kg < KS ? kg : KS - 1) * 4 + lane / 16;
-      const int64_t off = tab.xoff[l];
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        bv[c] = xcol[c][off];
-        // the partner (re <-> im) of column cc is cc ^ 1, one element away
-        if constexpr (CPLX) bo[c] = xcol[c][off + ((lane & 1) ? -1 : 1)];
-      }
-    };
-    // padding rows (>= mcell) of step kg are zeroed here, at use, so that no
-    // wait is forced at the load
-    auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bin)[CPW], const T (&boin)[CI], int kg) {
-      T bv[CPW], bo[CI], bs[CPW];
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        bv[c] = bin[c];
-        if constexpr (CPLX) bo[c] = boin[c];
-      }
-      if ((kg + 1) * 4 > MC) {
-        const bool ok = kg * 4 + lane / 16 < MC;
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          bv[c] = ok ? bv[c] : T(0);
-          if constexpr (CPLX) bo[c] = ok ? bo[c] : T(0);
-        }
-      }
-      if constexpr (CPLX) {
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
-      }
-#pragma unroll
-      for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          acc[r][c] = Mma<T>::run(av[r], bv[c], acc[r][c]);
-          if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
-        }
-    };
-    // Pipeline: the A fragments of step s + 1 and the B rows of step s + 2
-    // are in flight while step s multiplies.  The loop is unrolled by 4 so
-    // that every buffer keeps a fixed role (A period 2, B period 4): a copy
-    // between buffers would make the compiler wait for the loads in flight
-    // into the source buffer, draining the pipeline every iteration.
-    static_assert(KS % 4 == 0, "k steps come in groups of 4");
-    T aq[2][RPW], aiq[2][RI];
-    T bq[4][CPW], oq[4][CI];
-    load_b(bq[0], oq[0], 0);
-    load_a(aq[0], aiq[0], 0);
-    load_b(bq[1], oq[1], 1);
-    for (int kg = 0; kg < KS; kg += 4) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int s = kg + j;
-        load_a(aq[(j + 1) % 2], aiq[(j + 1) % 2], s + 1);
-        load_b(bq[(j + 2) % 4], oq[(j + 2) % 4], s + 2);
-        compute(aq[j % 2], aiq[j % 2], bq[j], oq[j], s);
-        // keep each step's loads behind the previous step's MFMAs: hoisted
-        // further, they would hold a third A buffer and spill at FP64
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-
-  // nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell, one
-  // 4-wide k step per (cell, atom) pair
+// The part of a work item after the cell products, shared by the cell
+// kernels: the nonlocal term C^{c,a} (h P_a) of every (cell, atom) pair as
+// extra 4-wide k steps into the accumulators, then the epilogue (scaling, the
+// owner's diagonal and recurrence terms, assembly).  The wave owns row tiles
+// rt0 .. rt0 + RPW - 1 and column tiles ct0 .. ct0 + CPW - 1 (16 x 16 each)
+// of the item's columns [col0, col0 + 64); acc holds its accumulators in the
+// 16x16x4 layout.
+// nonlocal: Y^c += C^{c,a} (h P_a) for the atoms touching this cell, one
+// 4-wide k step per (cell, atom) pair
+template <int MP, typename T, bool CPLX, int RPW, int CPW>
+__device__ __forceinline__ void cell_nonlocal(const HxArgs<T>& a, typename Mma<T>::acc_t (&acc)[RPW][CPW],
+                                              const int cell, const int col0, const int rt0, const int ct0,
+                                              const int lane) {
+  constexpr int RT = MP / 16;
   if (a.pair_ptr != nullptr) {
     const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
     for (int pr = p0; pr < p1; ++pr) {
@@ -379,6 +200,50 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
         }
     }
   }
+}
+
+// The nonlocal term for real operators with the operands of the next pair in
+// flight while the current pair multiplies (loop unrolled by 2 so that each
+// operand buffer keeps a fixed role).  `first` holds the first pair's
+// operands, loaded by the caller (before its k loop) with nl_load.
+template <typename T, int RPW, int CPW> struct NlOps { T b[CPW], cv[RPW]; };
+template <int MP, typename T, int RPW, int CPW>
+__device__ __forceinline__ void nl_load(const HxArgs<T>& a, const int pr, const int col0, const int rt0,
+                                        const int ct0, const int lane, NlOps<T, RPW, CPW>& o) {
+  constexpr int RT = MP / 16;
+  const int at = a.pair_atom[pr];
+  const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) o.b[c] = hrow[(ct0 + c) * 16 + lane % 16];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) o.cv[r] = a.pair_re[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
+}
+template <int MP, typename T, int RPW, int CPW>
+__device__ __forceinline__ void cell_nonlocal_pf(const HxArgs<T>& a, typename Mma<T>::acc_t (&acc)[RPW][CPW],
+                                                 const int p0, const int p1, const int col0, const int rt0,
+                                                 const int ct0, const int lane, NlOps<T, RPW, CPW>& first) {
+  auto mma = [&](const NlOps<T, RPW, CPW>& o) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[r][c] = Mma<T>::run(o.cv[r], o.b[c], acc[r][c]);
+  };
+  NlOps<T, RPW, CPW> second;
+  for (int pr = p0; pr < p1; pr += 2) {
+    if (pr + 1 < p1) nl_load<MP, T, RPW, CPW>(a, pr + 1, col0, rt0, ct0, lane, second);
+    mma(first);
+    if (pr + 1 < p1) {
+      if (pr + 2 < p1) nl_load<MP, T, RPW, CPW>(a, pr + 2, col0, rt0, ct0, lane, first);
+      mma(second);
+    }
+  }
+}
+
+template <int MP, typename T, bool CPLX, int RPW, int CPW, int ED, int SR = (sizeof(T) == 8 ? 2 : 4)>
+__device__ __forceinline__ void cell_tail(const HxArgs<T>& a, typename Mma<T>::acc_t (&acc)[RPW][CPW], const int cell,
+                                          const int col0, const int rt0, const int ct0, const int lane,
+                                          RowTables<MP, T>& tab) {
+  cell_nonlocal<MP, T, CPLX, RPW, CPW>(a, acc, cell, col0, rt0, ct0, lane);
 
   // epilogue: scale, owner terms, atomic assembly.  Per row tile, every
   // lane loads its owner operands (X_k, X_{k-1}) without branches, at
@@ -400,10 +265,10 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     colok[c] = col < a.ncols;
     colc[c] = colok[c] ? col : a.ncols - 1;
   }
-  // stages of SR of the 4 accumulator rows of each lane: half a row tile for
-  // 8-byte values (whole tiles would not fit next to the FP64 accumulators),
-  // a whole tile for 4-byte values
-  constexpr int SR = sizeof(T) == 8 ? 2 : 4;
+  // stages of SR of the 4 accumulator rows of each lane: by default half a
+  // row tile for 8-byte values (whole tiles would not fit next to the FP64
+  // accumulators), a whole tile for 4-byte values
+  static_assert(SR == 2 || SR == 4, "epilogue stage rows");
   struct Ops {
     int32_t g[SR];
     T xk[SR][CPW], xp[SR][CPW];
@@ -437,7 +302,10 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const T v = a.alpha * acc[r][c][i] + vc * o.xk[k][c] - bp * o.xp[k][c];
-        if (own && has_prev && a.zero_prev && colok[c]) Xp[gn * a.ldp + colc[c]] = T(0);
+        // the owner clears X_{k-1}[j] for the step that targets this buffer
+        // two steps on; an interior node needs no clearing, since its single
+        // contributor will store (not add) its value there
+        if (own && !inner && has_prev && a.zero_prev && colok[c]) Xp[gn * a.ldp + colc[c]] = T(0);
         // the target starts at zero and an interior node has no other
         // contributor: a plain store is the sum
         if (inner && colok[c]) Tg[gn * a.ldt + colc[c]] = v;
@@ -461,6 +329,148 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   }
 }
 
+// One work item: cell `cell`, columns [col0, col0 + 64).
+//
+// Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
+// number of 16-row tiles is even for every order p in [2, 7], so each wave
+// owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
+// B fragments are read straight from global memory into registers (no LDS
+// staging of X, no barriers in the loop): in a 4-wide k step, lanes
+// 16 q .. 16 q + 15 read 16 consecutive columns of cell row 4 kg + q, one
+// cache line per 16 lanes, at the row offset kept in the LDS table.  A
+// fragments come through buffer loads whose per-row-tile offsets live in
+// scalar registers; they are loaded one k step ahead and B fragments two
+// (HBM latency), the A load of the next step issued before the B load two
+// steps ahead, so that the in-order vector-memory counter never makes an MFMA
+// wait on HBM.  Column lanes beyond ncols read a valid column and are never
+// stored; padding rows (l >= mcell) are zeroed.
+template <int P, typename T, bool CPLX, int WAVES, int ED>
+__device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
+                                          RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
+  constexpr int Q = P + 1;
+  constexpr int MC = Q * Q * Q;
+  constexpr int MP = (MC + 15) / 16 * 16;
+  constexpr int RT = MP / 16;           // row tiles
+  constexpr int KS = MP / 4;            // 4-wide k steps
+  constexpr int RG = WAVES / 2;         // row groups
+  constexpr int RPW = RT / RG;          // row tiles per wave
+  constexpr int CPW = kNT / 32;         // column tiles per wave (2 column groups)
+  static_assert(RT % RG == 0 && KS % 2 == 0, "tiling");
+  using acc_t = typename Mma<T>::acc_t;
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int lane = tid % 64;
+  const int rt0 = (wave / 2) * RPW, ct0 = (wave % 2) * CPW;
+
+  // row tables (the barrier in front protects the previous item's readers)
+  __syncthreads();
+  row_tables<P, T>(a, cell, tid, 64 * WAVES, tab);
+  __syncthreads();
+
+  acc_t acc[RPW][CPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[r][c] = acc_t{0, 0, 0, 0};
+
+  // per-lane column pointers, clamped to a valid column; complex blocks keep
+  // the lane's parity (re/im) so that the partner column cc ^ 1 stays valid
+  // (their ncols, counted in reals, is even)
+  const T* xcol[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    int cc = col0 + (ct0 + c) * 16 + lane % 16;
+    if (cc >= a.ncols) cc = CPLX ? a.ncols - 2 + (lane & 1) : a.ncols - 1;
+    xcol[c] = a.Xk + cc;
+  }
+
+  // A fragments of this wave: tile (rt0 + r, k step kg) at element
+  // ((rt0 + r) KS + kg) 64 + lane
+  constexpr int RI = CPLX ? RPW : 1;
+  constexpr int CI = CPLX ? CPW : 1;
+  const uint32_t abytes = static_cast<uint32_t>(RT) * KS * 64 * sizeof(T);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.A + static_cast<int64_t>(cell) * a.astride, abytes);
+  const __amdgpu_buffer_rsrc_t rai = make_rsrc(CPLX ? a.Ai : a.A, abytes);
+  int soff[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KS * 64 * static_cast<int>(sizeof(T)));
+  // both loaders clamp the k step to the last one, so that the pipeline's
+  // loads past the end (never used) read valid memory without a branch
+  auto load_a = [&](T (&av)[RPW], T (&avi)[RI], int kg) {
+    const int vo = ((kg < KS ? kg : KS - 1) * 64 + lane) * static_cast<int>(sizeof(T));
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      av[r] = buf_load<T>(ra, vo, soff[r]);
+      if constexpr (CPLX) avi[r] = buf_load<T>(rai, vo, soff[r]);
+    }
+  };
+  auto load_b = [&](T (&bv)[CPW], T (&bo)[CI], int kg) {
+    const int l = (kg < KS ? kg : KS - 1) * 4 + lane / 16;
+    const int64_t off = tab.xoff[l];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      bv[c] = xcol[c][off];
+      // the partner (re <-> im) of column cc is cc ^ 1, one element away
+      if constexpr (CPLX) bo[c] = xcol[c][off + ((lane & 1) ? -1 : 1)];
+    }
+  };
+  // padding rows (>= mcell) of step kg are zeroed here, at use, so that no
+  // wait is forced at the load
+  auto compute = [&](const T (&av)[RPW], const T (&avi)[RI], const T (&bin)[CPW], const T (&boin)[CI], int kg) {
+    T bv[CPW], bo[CI], bs[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      bv[c] = bin[c];
+      if constexpr (CPLX) bo[c] = boin[c];
+    }
+    if ((kg + 1) * 4 > MC) {
+      const bool ok = kg * 4 + lane / 16 < MC;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        bv[c] = ok ? bv[c] : T(0);
+        if constexpr (CPLX) bo[c] = ok ? bo[c] : T(0);
+      }
+    }
+    if constexpr (CPLX) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) bs[c] = (lane & 1) ? bo[c] : -bo[c];
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        acc[r][c] = Mma<T>::run(av[r], bv[c], acc[r][c]);
+        if constexpr (CPLX) acc[r][c] = Mma<T>::run(avi[r], bs[c], acc[r][c]);
+      }
+  };
+  // Pipeline: the A fragments of step s + 1 and the B rows of step s + 2
+  // are in flight while step s multiplies.  The loop is unrolled by 4 so
+  // that every buffer keeps a fixed role (A period 2, B period 4): a copy
+  // between buffers would make the compiler wait for the loads in flight
+  // into the source buffer, draining the pipeline every iteration.
+  static_assert(KS % 4 == 0, "k steps come in groups of 4");
+  T aq[2][RPW], aiq[2][RI];
+  T bq[4][CPW], oq[4][CI];
+  load_b(bq[0], oq[0], 0);
+  load_a(aq[0], aiq[0], 0);
+  load_b(bq[1], oq[1], 1);
+  for (int kg = 0; kg < KS; kg += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int s = kg + j;
+      load_a(aq[(j + 1) % 2], aiq[(j + 1) % 2], s + 1);
+      load_b(bq[(j + 2) % 4], oq[(j + 2) % 4], s + 2);
+      compute(aq[j % 2], aiq[j % 2], bq[j], oq[j], s);
+      // keep each step's loads behind the previous step's MFMAs: hoisted
+      // further, they would hold a third A buffer and spill at FP64
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  cell_tail<MP, T, CPLX, RPW, CPW, ED>(a, acc, cell, col0, rt0, ct0, lane, tab);
+}
+
 template <int P> constexpr int waves_for() {
   return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 > 24 ? 8 : 4;
 }
@@ -469,13 +479,195 @@ template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 
 template <typename T> constexpr int epilogue_depth() { return sizeof(T) == 8 ? 3 : 2; }
 
 // Single problem: one workgroup per (cell, column tile), cells fastest.
-template <int P, typename T, bool CPLX, int WAVES, int OCC, bool BF>
+template <int P, typename T, bool CPLX, int WAVES, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, BF, epilogue_depth<T>()>(a, bid % E, (bid / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>()>(a, bid % E, (bid / E) * kNT, tab);
+}
+
+// bf16 cell products with FP32 iterates (the BF16 filter precision).  The
+// FP64/FP32 item above streams its B fragments from memory, each wave reading
+// its own; at 16 cycles per bf16 MFMA that leaves the main loop waiting on
+// memory and each A fragment (read from L2) serving only 2 column tiles.
+// Here a workgroup of MP / 32 waves owns one (cell, 64-column) item:
+//   1. the cell block X^c is staged once into LDS, rounded to bf16 (nearest
+//      even) and stored column-major (bt[col * CS + row], CS = MP + 8, so
+//      that the 16 lanes of a 16-byte LDS read hit 16 distinct 4-bank
+//      groups), with every wave's row loads in flight together (lane =
+//      column, 16 row pairs per wave); an FP32 copy (xs, p <= 6) keeps X_k
+//      for the owner's diagonal term;
+//   2. X_{k-1} at the owned rows of each wave's accumulators and the first
+//      (cell, atom) pair's operands are loaded before the k loop, so that
+//      the nonlocal term and the epilogue wait on nothing but their own
+//      later pairs;
+//   3. each wave multiplies 2 row tiles (32 rows) of A by all 4 column tiles,
+//      A fragments from L2 two k steps ahead (each used 4 times), B
+//      fragments from LDS with one 16-byte read per column tile;
+//   4. nonlocal term, then the epilogue (scaling, owner terms, assembly) with
+//      2 row tiles x 4 column tiles per wave.
+// Measured on the c1 operator (128-column filter step): 2.07 ms against
+// 2.94 ms for the bf16 variant of the FP32 item.  Rejected: a persistent
+// form with a loader wave streaming the next item into LDS (2.6-3.2 ms: on
+// gfx9 stores count in the same in-order counter as loads, so the compute
+// waves' first load of an item waited for the previous item's stores);
+// an FP32 output tile in LDS so that every store covers a whole row
+// (2.18 ms); dropping the LDS copy for two workgroups per CU (2.30 ms).
+template <int P> constexpr int bf16_waves() { return rows_padded<P>() / 32; }
+
+template <int P>
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * bf16_waves<P>(), 64 * bf16_waves<P>())))
+cell_hx_bf16_kernel(const HxArgs<float> a) {
+  constexpr int Q = P + 1;
+  constexpr int MC = Q * Q * Q;
+  constexpr int MP = rows_padded<P>();
+  constexpr int RT = MP / 16;           // row tiles
+  constexpr int KB = MP / 32;           // 32-wide k steps
+  constexpr int NW = bf16_waves<P>();   // waves: 2 row tiles each
+  constexpr int RPW = 2, CPW = kNT / 16;
+  constexpr int CS = MP + 8;            // LDS column stride of the bf16 block (elements)
+  constexpr int SB = 8;                 // row pairs per batch of staging loads
+  constexpr int AD = 3;                 // A fragments in flight (k steps ahead + 1)
+  static_assert(MP % 32 == 0 && RT == NW * RPW, "bf16 tiling");
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  // FP32 copy of X^c, row-major with a row stride of 68 floats (the 4 rows of
+  // one accumulator access fall in distinct banks), while it fits (p <= 6)
+  constexpr int XS = kNT + 4;
+  constexpr bool XS_LDS = (MP * XS * 4 + kNT * CS * 2 + MP * 16) <= 160 * 1024;
+  __shared__ RowTables<MP, float> tab;
+  __shared__ __attribute__((aligned(16))) __bf16 bt[kNT * CS];
+  __shared__ float xs[XS_LDS ? MP * XS : 1];
+
+  const int E = a.nc * a.nc * a.nc;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int cell = bid % E, col0 = (bid / E) * kNT;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+  const int lane = tid % 64;
+  row_tables<P, float>(a, cell, tid, 64 * NW, tab);
+  __syncthreads();
+
+  // 1. stage X^c (column col0 + lane, clamped to a valid column); rows >= MC
+  //    read node 0 and are replaced by zeros in bt
+  {
+    int cc = col0 + lane;
+    if (cc >= a.ncols) cc = a.ncols - 1;
+    const float* __restrict__ xcol = a.Xk + cc;
+#pragma unroll
+    for (int h = 0; h < 16; h += SB) {
+      float v[2 * SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        const int l0 = 2 * (wave + NW * (h + i));
+        v[2 * i] = xcol[tab.xoff[l0]];
+        v[2 * i + 1] = xcol[tab.xoff[l0 + 1]];
+      }
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        const int l0 = 2 * (wave + NW * (h + i));
+        bf2 pr;
+        pr[0] = static_cast<__bf16>(l0 < MC ? v[2 * i] : 0.f);
+        pr[1] = static_cast<__bf16>(l0 + 1 < MC ? v[2 * i + 1] : 0.f);
+        *reinterpret_cast<bf2*>(&bt[lane * CS + l0]) = pr;
+        if constexpr (XS_LDS) {
+          xs[l0 * XS + lane] = v[2 * i];
+          xs[(l0 + 1) * XS + lane] = v[2 * i + 1];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // 2. X_{k-1} at the owned rows of this wave's accumulators (16x16x4 layout:
+  //    row 16 (rt0 + r) + 4 (lane / 16) + i, column 16 c + lane % 16); rows
+  //    this cell does not own read node 0's row and are discarded
+  const int rt0 = wave * RPW;
+  int colc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int col = col0 + c * 16 + lane % 16;
+    colc[c] = col < a.ncols ? col : a.ncols - 1;
+  }
+  const bool has_prev = a.Xp != nullptr;
+  float xp[RPW][4][CPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int32_t g = tab.gid[(rt0 + r) * 16 + 4 * (lane / 16) + i];
+      const int64_t go = (has_prev && g >= 0 && (g & (1 << 30))) ? (g & ((1 << 29) - 1)) : 0;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) xp[r][i][c] = has_prev ? a.Xp[go * a.ldp + colc[c]] : 0.f;
+    }
+  const int p0 = a.pair_ptr != nullptr ? a.pair_ptr[cell] : 0;
+  const int p1 = a.pair_ptr != nullptr ? a.pair_ptr[cell + 1] : 0;
+  NlOps<float, RPW, CPW> nl0;
+  if (p0 < p1) nl_load<MP, float, RPW, CPW>(a, p0, col0, rt0, 0, lane, nl0);
+
+  // 3. cell products: rows 32 wave .. 32 wave + 31, all 64 columns
+  f4 acc[RPW][CPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) acc[r][c] = f4{0, 0, 0, 0};
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(a.Ab, static_cast<uint32_t>(RT) * KB * 64 * 16);
+  int soff[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) soff[r] = __builtin_amdgcn_readfirstlane((rt0 + r) * KB * 64 * 16);
+  auto load_a = [&](bf8 (&av)[RPW], int kg) {
+    const int vo = (kg * 64 + lane) * 16;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) av[r] = buf_load<bf8>(ra, vo, soff[r]);
+  };
+  const __bf16* bcol = bt + (lane % 16) * CS + 8 * (lane / 16);
+  bf8 aq[AD][RPW];
+#pragma unroll
+  for (int k = 0; k < AD - 1 && k < KB; ++k) load_a(aq[k], k);
+#pragma unroll
+  for (int kg = 0; kg < KB; ++kg) {
+    if (kg + AD - 1 < KB) load_a(aq[(kg + AD - 1) % AD], kg + AD - 1);
+    bf8 bq[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) bq[c] = *reinterpret_cast<const bf8*>(bcol + c * 16 * CS + kg * 32);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[r][c] = mma_bf16(aq[kg % AD][r], bq[c], acc[r][c]);
+  }
+
+  // 4. nonlocal term, then the epilogue: X_k from the LDS copy (memory for
+  //    p = 7), X_{k-1} from the registers loaded above
+  cell_nonlocal_pf<MP, float, RPW, CPW>(a, acc, p0, p1, col0, rt0, 0, lane, nl0);
+  float* __restrict__ Xp = const_cast<float*>(a.Xp);
+  float* __restrict__ Tg = a.Tg;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = (rt0 + r) * 16 + 4 * (lane / 16) + i;
+      const int32_t g = tab.gid[row];
+      const bool valid = g >= 0;
+      const bool own = valid && (g & (1 << 30));
+      const bool inner = valid && (g & (1 << 29));
+      const int64_t gn = valid ? (g & ((1 << 29) - 1)) : 0;
+      const float vc = tab.wv[row];
+      const float bp = own ? a.beta : 0.f;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const bool ok = col0 + c * 16 + lane % 16 < a.ncols;
+        float xk;
+        if constexpr (XS_LDS) xk = xs[row * XS + c * 16 + lane % 16];
+        else xk = a.Xk[(own ? gn : 0) * a.ldx + colc[c]];
+        const float v = a.alpha * acc[r][c][i] + vc * xk - bp * xp[r][i][c];
+        // as in cell_tail: clear X_{k-1} for reuse as a target (interior
+        // nodes excepted), store interior nodes, add the others
+        if (own && !inner && has_prev && a.zero_prev && ok) Xp[gn * a.ldp + colc[c]] = 0.f;
+        if (inner && ok) Tg[gn * a.ldt + colc[c]] = v;
+        else if (valid && ok) atomic_add(Tg + gn * a.ldt + colc[c], v);
+      }
+    }
 }
 
 // Many problems in one persistent launch: the work list is the concatenation
@@ -503,7 +695,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const HxArgs<T> d = descs[q];
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
-    cell_item<P, T, CPLX, WAVES, false, 2>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
+    cell_item<P, T, CPLX, WAVES, 2>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
   }
 }
 
@@ -524,15 +716,15 @@ cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __re
   const HxArgs<T> d = descs[lo];
   const int local = it - static_cast<int>(item_off[lo]);
   const int E = d.nc * d.nc * d.nc;
-  cell_item<P, T, CPLX, WAVES, false, epilogue_depth<T>()>(d, local % E, (local / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>()>(d, local % E, (local / E) * kNT, tab);
 }
 
-// Waves per SIMD: two for real and complex FP64, complex FP32 and bf16 (one
+// Waves per SIMD: two for real and complex FP64 and complex FP32 (one
 // workgroup's epilogue overlaps the other's MFMAs), three for real FP32
 // (140 VGPRs at p = 6); complex FP64 at p = 6 (11 row tiles per wave, A and
 // B fragments doubled) needs the 512 registers of one wave per SIMD.
-template <int P, typename T, bool CPLX, bool BF> constexpr int occupancy() {
-  return BF ? 2 : ((CPLX && sizeof(T) == 8) ? (P == 6 ? 1 : 2) : ((!CPLX && sizeof(T) == 4) ? 3 : 2));
+template <int P, typename T, bool CPLX> constexpr int occupancy() {
+  return (CPLX && sizeof(T) == 8) ? (P == 6 ? 1 : 2) : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
 }
 
 template <typename T>
@@ -572,10 +764,16 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   const int64_t nblk = E * nct;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  constexpr int WAVES = waves_for<P>();
-  constexpr int OCC = occupancy<P, T, CPLX, BF>();
-  hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, OCC, BF>), dim3(static_cast<unsigned>(nblk)),
-                     dim3(64 * WAVES), 0, s, a);
+  if constexpr (BF) {
+    static_assert(std::is_same<T, float>::value && !CPLX, "bf16 products: real FP32 iterates");
+    hipLaunchKernelGGL((cell_hx_bf16_kernel<P>), dim3(static_cast<unsigned>(nblk)), dim3(64 * bf16_waves<P>()), 0,
+                       s, a);
+  } else {
+    constexpr int WAVES = waves_for<P>();
+    constexpr int OCC = occupancy<P, T, CPLX>();
+    hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, OCC>), dim3(static_cast<unsigned>(nblk)),
+                       dim3(64 * WAVES), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -597,7 +795,7 @@ hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
 template <int P, typename T, bool CPLX>
 hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
   constexpr int WAVES = waves_for<P>();
-  constexpr int OCC = occupancy<P, T, CPLX, false>();
+  constexpr int OCC = occupancy<P, T, CPLX>();
   if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
   if (b.one_per_item)
     hipLaunchKernelGGL((cell_hx_batched1_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
