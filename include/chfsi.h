@@ -411,14 +411,24 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
  * output density, or the last mixed density if not converged, out); theta:
  * host, nwanted + n_buf Ritz values of the last step; mu_out, res_hist
  * (host, maxit values: the residual norm of every step) and iters nullable.
- * m, block: filter degree and column block as in chfsi_params.  Real
+ * m, block: filter degree and column block as in chfsi_params.
+ * rr_mode selects the Rayleigh-Ritz step of the passes after the first SCF
+ * step: 0 = CholGS + Rayleigh-Ritz on all N columns and the density of the
+ * Ritz vectors; 1 = Rayleigh-Ritz through the generalised problem with
+ * spectrum splitting (chfsi_rayleigh_ritz_split, Algorithm 2) and the split
+ * density of Algorithm 3: rho = sum over the orthonormal basis with weight
+ * 2 plus the nfr highest Ritz vectors with weight 2 (f_i - 1) (buffer states
+ * f_i = 0), nfr covering every state whose vacancy 1 - f_i exceeded 1e-14
+ * at the previous step, plus two; 2 = the same with the mixed-precision
+ * blocks of chfsi_rayleigh_ritz_split (the paper's form).  In modes 1 and 2
+ * X holds the orthonormal basis (not Ritz vectors) on return.  Real
  * operators with a nodal potential; 0 < n_electrons < 2 nwanted.  On
  * return the operator holds the last step's effective potential (restore
  * the original with chfsi_op_set_potential if needed).  Returns
  * CHFSI_NOTCONV if tol was not met.  Synchronous. */
 int chfsi_scf(chfsi_op* op, void* X, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
-              double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit, double* rho,
-              double* theta, double* mu_out, double* res_hist, int32_t* iters);
+              int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
+              double* rho, double* theta, double* mu_out, double* res_hist, int32_t* iters);
 
 /* ---- batched filter (many operators, one persistent launch per step) -------
  * Applies the filter of chfsi_filter() to n independent blocks at once:

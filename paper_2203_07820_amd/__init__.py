@@ -317,9 +317,11 @@ class Operator:
         return it.value, rr.value
 
     def scf(self, X, rho, nwanted: int, n_buf: int, n_electrons: float, kT: float, m: int = 20, block: int = 0,
-            beta: float = 0.3, depth: int = 4, tol: float = 1e-8, maxit: int = 60):
-        """chfsi_scf: self-consistent loop; X (start block -> Ritz vectors)
-        and rho (initial -> final density) are device tensors."""
+            beta: float = 0.3, depth: int = 4, tol: float = 1e-8, maxit: int = 60, rr_mode: int = 2):
+        """chfsi_scf: self-consistent loop; X (start block -> last basis) and
+        rho (initial -> final density) are device tensors.  rr_mode: 0 full
+        Rayleigh-Ritz, 1 spectrum splitting in FP64, 2 spectrum splitting with
+        the mixed-precision blocks (default, the paper's form)."""
         ncols, ld = _ld_cols(X)
         if ncols != nwanted + n_buf:
             raise ValueError("X must have nwanted + n_buf columns")
@@ -327,7 +329,7 @@ class Operator:
         hist = np.zeros(maxit)
         mu, it = C.c_double(), C.c_int32()
         rc = self.ctx.check(self.ctx.lib.chfsi_scf(self.h, _tptr(X), ld, int(nwanted), int(n_buf), int(m), int(block),
-                                                   float(n_electrons), float(kT), float(beta), int(depth), float(tol),
+                                                   int(rr_mode), float(n_electrons), float(kT), float(beta), int(depth), float(tol),
                                                    int(maxit), _tptr(rho), _dptr(th), C.byref(mu), _dptr(hist),
                                                    C.byref(it)), allow=(0, 1))
         return {"theta": th, "mu": mu.value, "iters": it.value, "residuals": hist[:it.value],

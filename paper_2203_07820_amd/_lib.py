@@ -119,7 +119,7 @@ def load() -> C.CDLL:
         "chfsi_rayleigh_ritz_split": (C.c_int, [vp, vp, i64, i64, i32, i32, pd, vp, i64]),
         "chfsi_op_set_potential": (C.c_int, [vp, vp]),
         "chfsi_hartree": (C.c_int, [vp, vp, vp, dbl, i32, C.POINTER(i32), pd]),
-        "chfsi_scf": (C.c_int, [vp, vp, i64, i32, i32, i32, i32, dbl, dbl, dbl, i32, dbl, i32, vp, pd, pd, pd,
+        "chfsi_scf": (C.c_int, [vp, vp, i64, i32, i32, i32, i32, i32, dbl, dbl, dbl, i32, dbl, i32, vp, pd, pd, pd,
                                 C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():

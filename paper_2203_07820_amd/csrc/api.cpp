@@ -1740,8 +1740,8 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
 }
 
 int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
-              double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit, double* rho,
-              double* theta, double* mu_out, double* res_hist, int32_t* iters) {
+              int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
+              double* rho, double* theta, double* mu_out, double* res_hist, int32_t* iters) {
   if (!op) return CHFSI_EINVAL;
   chfsi_ctx* ctx = op->ctx;
   const HostTables& t = op->t;
@@ -1751,7 +1751,8 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
     return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on a real operator with a nodal potential");
   if (!rho || !theta) return fail(ctx, CHFSI_EINVAL, "null density or theta");
   if (nwanted < 1 || n_buf < 0 || m < 1 || maxit < 1 || depth < 0 || depth > 16 || !(beta > 0.0) ||
-      !(kT > 0.0) || !(tol > 0.0) || !(n_electrons > 0.0) || !(n_electrons < 2.0 * nwanted))
+      !(kT > 0.0) || !(tol > 0.0) || !(n_electrons > 0.0) || !(n_electrons < 2.0 * nwanted) || rr_mode < 0 ||
+      rr_mode > 2)
     return fail(ctx, CHFSI_EINVAL, "bad SCF parameters");
   const int64_t M = t.M;
   hipStream_t st = ctx->stream;
@@ -1788,10 +1789,20 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   prm.m = m;
   prm.block = block > 0 ? block : static_cast<int32_t>(N);
   prm.filter_prec = CHFSI_F64;
-  std::vector<double> th(N), f(nwanted), occ(nwanted);
+  std::vector<double> th(N), f(nwanted), occ(nwanted), wfr;
   int hist = 0, it = 0;
   bool conv = false;
   double mu = 0.0;
+  // spectrum splitting (rr_mode 1: FP64, 2: mixed precision): the nfr
+  // highest Ritz vectors of each step, the states below them being fully
+  // occupied (chosen from the previous step's occupations)
+  int nfr = static_cast<int>(N);
+  double* Pfr = nullptr;
+  if (rr_mode > 0) {
+    void* pv;
+    CHECK(ws_get(ctx, WS_PFR, static_cast<size_t>(M) * N * 8, &pv));
+    Pfr = static_cast<double*>(pv);
+  }
   for (it = 0; it < maxit; ++it) {
     // potential of the input density
     int cgit = 0;
@@ -1807,16 +1818,47 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
       CHECK(chfsi_orthonormalize(op, Xv, N, ld, nullptr));
       CHECK(chfsi_rayleigh_ritz(op, Xv, N, ld, th.data(), nullptr));
     }
+    const bool split = rr_mode > 0 && it > 0;
     const int passes = it == 0 ? 4 : 1;
     for (int ps = 0; ps < passes; ++ps) {
       const double a = th[N - 1], aL = th[0];
       if (!(a < b)) return fail(ctx, CHFSI_EDIVERGE, "Ritz values above the spectrum bound");
-      CHECK(chfsi_pass(op, &prm, Xv, ld, a, b, aL, th.data(), nullptr));
+      if (!split) {
+        CHECK(chfsi_pass(op, &prm, Xv, ld, a, b, aL, th.data(), nullptr));
+        continue;
+      }
+      // Algorithm 1's eigensolver step in the paper's form: the filter, then
+      // Rayleigh-Ritz through the generalised problem with spectrum
+      // splitting (Algorithm 2): X becomes the orthonormal basis Psi_o,
+      // Pfr the nfr highest Ritz vectors
+      CHECK(do_filter(op, Xv, N, ld, m, a, b, aL, CHFSI_F64, prm.block));
+      CHECK(rrgep_split(op, static_cast<double*>(Xv), ld, N, nfr, rr_mode == 2, th.data(), Pfr, nfr));
+      CHECK(check_ritz(ctx, th.data(), nullptr, N, b));
     }
     // occupations and the output density
     CHECK(chfsi_fermi_level(th.data(), nwanted, nullptr, n_electrons, kT, &mu, occ.data()));
     for (int i = 0; i < nwanted; ++i) f[i] = 2.0 * occ[i];
-    CHECK(chfsi_density(op, Xv, nwanted, ld, f.data(), CHFSI_RHO_NODES, 0, rout));
+    if (!split) {
+      CHECK(chfsi_density(op, Xv, nwanted, ld, f.data(), CHFSI_RHO_NODES, 0, rout));
+    } else {
+      // Algorithm 3's split form: every basis vector counted fully occupied,
+      // then the nfr highest Ritz vectors corrected by 2 (f_i - 1) (buffer
+      // states: f_i = 0); exact when f_i = 1 below the split
+      std::vector<double> two(N, 2.0);
+      CHECK(chfsi_density(op, Xv, N, ld, two.data(), CHFSI_RHO_NODES, 0, rout));
+      wfr.assign(nfr, 0.0);
+      for (int j = 0; j < nfr; ++j) {
+        const int64_t i = N - nfr + j;
+        wfr[j] = 2.0 * ((i < nwanted ? occ[i] : 0.0) - 1.0);
+      }
+      CHECK(chfsi_density(op, Pfr, nfr, nfr, wfr.data(), CHFSI_RHO_NODES, 1, rout));
+    }
+    if (rr_mode > 0) {
+      // next split: all states whose vacancy 1 - f exceeds 1e-14, plus two
+      int full = 0;
+      while (full < nwanted && 1.0 - occ[full] <= 1e-14) ++full;
+      nfr = static_cast<int>(std::min<int64_t>(N, N - full + 2));
+    }
     // residual F = rho_out - rho_in in the M-weighted norm
     HIP_TRY(ctx, launch_convert(F, 1, CHFSI_F64, rout, 1, CHFSI_F64, M, 1, st));
     HIP_TRY(ctx, launch_axpby(-1.0, rin, 1.0, F, M, st));

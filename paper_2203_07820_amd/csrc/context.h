@@ -25,6 +25,7 @@ enum Slot {
   WS_X32, WS_W32, WS_C32,          // FP32 copies of X, H X and the FP32 rotation
   WS_SCF,                          // SCF vectors (potentials, densities, CG, mixing history)
   WS_CG,                           // CG scalars and the residual history of one check interval
+  WS_PFR,                          // SCF: the highest Ritz vectors of the split Rayleigh-Ritz
   WS_COUNT
 };
 

@@ -86,7 +86,11 @@ def test_set_potential_changes_the_operator(ctx):
     assert np.max(np.abs(Y.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(want))
 
 
-def test_scf_reaches_the_oracle_fixed_point(ctx):
+@pytest.mark.parametrize("rr_mode", [0, 1, 2])
+def test_scf_reaches_the_oracle_fixed_point(ctx, rr_mode):
+    # rr_mode 0: full Rayleigh-Ritz and the density of the Ritz vectors;
+    # 1, 2: spectrum-splitting Rayleigh-Ritz (FP64, mixed precision) and the
+    # split density.  The fixed point does not depend on the route.
     s = workloads.small_system(2, 4, 2, seed=7, L=6.0)
     ref = oscf.scf(s, nstates=8, n_electrons=6.0, kT=0.01, beta=0.3, depth=4, tol=1e-9, maxit=80)
     assert ref.converged
@@ -96,7 +100,7 @@ def test_scf_reaches_the_oracle_fixed_point(ctx):
     m = fe.build_operator(s).Mdiag
     rho = dev(np.full(M, 6.0 / np.sum(m)))
     out = op.scf(X, rho, nwanted=8, n_buf=4, n_electrons=6.0, kT=0.01, m=20, beta=0.3, depth=4, tol=1e-9,
-                 maxit=120)
+                 maxit=120, rr_mode=rr_mode)
     assert out["converged"], out["residuals"][-5:]
     got = rho.cpu().numpy()
     assert abs(float(np.sum(m * got)) - 6.0) < 1e-9
