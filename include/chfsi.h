@@ -398,10 +398,13 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
 
 /* A self-consistent field loop around the eigensolver (Algorithm 1 with a
  * synthetic exchange-correlation term): per step, the Hartree potential of
- * the input density (chfsi_hartree, tol 1e-10), V = V_ext + v_H + v_x with
+ * the input density (the solve of chfsi_hartree to tol 1e-10, started from
+ * the previous step's potential after the first step), V = V_ext + v_H + v_x with
  * V_ext the operator's build-time potential and LDA exchange
  * v_x = -(3 rho / pi)^(1/3), one ChFSI pass on X (four on the first step,
- * which starts by orthonormalising X), the Fermi level of the nwanted lowest
+ * which starts by orthonormalising X; the spectrum's upper bound comes from
+ * a Lanczos run on the first step and, later, from Weyl's inequality:
+ * b + max_j (V_j - V_j of the first step)), the Fermi level of the nwanted lowest
  * Ritz values (kT, n_electrons), the nodal output density, and Anderson
  * mixing of the density (weight beta, the last `depth` differences,
  * M-weighted inner products).  Stops when the M-weighted norm of

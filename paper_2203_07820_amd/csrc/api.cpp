@@ -1035,8 +1035,10 @@ int apply_stiffness(chfsi_op* op, const double* u, double* qv) {
 // Hartree potential: D K D u = 4 pi M^1/2 (rho - rho_bar), v_H = D u, by
 // Jacobi-preconditioned CG with the null vector M^1/2 1 projected out.
 // w: 6 M scratch values.
+// warm: start from the potential already in vh (the previous SCF step's)
+// instead of zero; the stopping rule stays relative to the right-hand side.
 int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int maxit, double* w, int* iters,
-                  double* relres) {
+                  double* relres, bool warm = false) {
   chfsi_ctx* ctx = op->ctx;
   const int64_t M = op->t.M;
   hipStream_t st = ctx->stream;
@@ -1059,12 +1061,23 @@ int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int m
   CHECK(project(b));
   double bb = 0.0;
   CHECK(dot_host(ctx, b, b, M, &bb));
-  HIP_TRY(ctx, launch_fill(u, M, 1, 1, CHFSI_F64, st));
   HIP_TRY(ctx, launch_convert(r, 1, CHFSI_F64, b, 1, CHFSI_F64, M, 1, st));
+  double rr = bb;
+  if (warm) {
+    // u = M^1/2 v (v = D u), kept orthogonal to the constant mode; r = b - A u
+    HIP_TRY(ctx, launch_emul(vh, sqm, u, M, st));
+    CHECK(project(u));
+    CHECK(apply_stiffness(op, u, qv));
+    HIP_TRY(ctx, launch_axpby(-1.0, qv, 1.0, r, M, st));
+    CHECK(project(r));
+    CHECK(dot_host(ctx, r, r, M, &rr));
+  } else {
+    HIP_TRY(ctx, launch_fill(u, M, 1, 1, CHFSI_F64, st));
+  }
   HIP_TRY(ctx, launch_ediv(r, kd, z, M, st));
   CHECK(project(z));
   HIP_TRY(ctx, launch_convert(pv, 1, CHFSI_F64, z, 1, CHFSI_F64, M, 1, st));
-  double rz = 0.0, rr = bb;
+  double rz = 0.0;
   CHECK(dot_host(ctx, r, z, M, &rz));
   // the iterations keep their scalars on the device (launch_cg_iteration);
   // the host reads the residual history once per kCheck iterations, so a
@@ -1798,6 +1811,8 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   // occupied (chosen from the previous step's occupations)
   int nfr = static_cast<int>(N);
   double* Pfr = nullptr;
+  std::vector<double> vhost(M), v0;   // effective potentials (host): this step's, the first step's
+  double b0 = 0.0;                    // Lanczos bound of the first step's operator
   if (rr_mode > 0) {
     void* pv;
     CHECK(ws_get(ctx, WS_PFR, static_cast<size_t>(M) * N * 8, &pv));
@@ -1807,13 +1822,28 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
     // potential of the input density
     int cgit = 0;
     double cgr = 0.0;
-    CHECK(hartree_solve(op, rin, vh, 1e-10, 5000, cg, &cgit, &cgr));
+    // from the previous step's potential after the first step
+    CHECK(hartree_solve(op, rin, vh, 1e-10, 5000, cg, &cgit, &cgr, it > 0));
     HIP_TRY(ctx, launch_veff(vext, vh, rin, V, M, st));
     CHECK(chfsi_op_set_potential(op, V));
+    // upper bound of the spectrum: Lanczos on the first step's operator;
+    // later the potential only moves the diagonal, so by Weyl's inequality
+    // lambda_max(H + dV) <= lambda_max(H) + max_j dV_j bounds it without
+    // another Lanczos run
+    HIP_TRY(ctx, hipMemcpyAsync(vhost.data(), V, M * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    double b = 0.0;
+    if (it == 0) {
+      CHECK(do_bounds(op, 20, nullptr, nullptr, 12345, &b0, nullptr));
+      v0 = vhost;
+      b = b0;
+    } else {
+      double dmax = 0.0;
+      for (int64_t j = 0; j < M; ++j) dmax = std::max(dmax, vhost[j] - v0[j]);
+      b = b0 + dmax;
+    }
     // eigensolver: the first step orthonormalises the start block and runs
     // four passes, later steps one pass from the previous subspace
-    double b = 0.0;
-    CHECK(do_bounds(op, 20, nullptr, nullptr, 12345, &b, nullptr));
     if (it == 0) {
       CHECK(chfsi_orthonormalize(op, Xv, N, ld, nullptr));
       CHECK(chfsi_rayleigh_ritz(op, Xv, N, ld, th.data(), nullptr));
