@@ -13,8 +13,12 @@ learned component; this is the spec extension whose readings are:
 * Loss per configuration, with Y the output block and Q the converged
   orthonormal Ritz block (both M x 128):
   l = ||Y - Q Q^T Y||_F^2 / ||Y||_F^2 + 0.1 ||128 Y^T Y / ||Y||_F^2 - I||_F^2 / 128^2
-  (rotation and sign invariant; the second term keeps the columns from
-  collapsing onto one direction).
+      + ||Q - P_Y Q||_F^2 / 128,   P_Y = Y (Y^T Y)^-1 Y^T
+  (rotation, sign and scale invariant).  The first term is the part of the
+  output outside the target subspace, the third the part of the target
+  outside the output's span (so that an output confined to a few target
+  directions is penalised), the second keeps the columns from collapsing
+  onto one direction.
 * Adam (lr, beta1 = 0.9, beta2 = 0.999, eps = 1e-8).
 """
 from __future__ import annotations
@@ -73,9 +77,10 @@ def forward(params, Fn: np.ndarray):
     return Y, (Fn, A1, A2)
 
 
-def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1):
+def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1, mu: float = 1.0):
     """Subspace loss and its gradient with respect to Y."""
     n = Y.shape[1]
+    nq = Q.shape[1]
     s = float(np.sum(Y * Y))
     P = Q.T @ Y
     R = Y - Q @ P
@@ -87,7 +92,12 @@ def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1):
     dY1 = 2.0 * R / s - 2.0 * r2 * Y / s ** 2
     inner = float(np.sum(D * (Y.T @ Y)))
     dY2 = (lam / n ** 2) * ((4.0 * n / s) * (Y @ D) - (4.0 * n / s ** 2) * inner * Y)
-    return t1 + t2, dY1 + dY2
+    # coverage: ||Q - P_Y Q||^2 = nq - tr(P (Y^T Y)^-1 P^T); its gradient
+    # -2 Q P Gi + 2 Y Gi P^T P Gi with Gi = (Y^T Y)^-1
+    X = np.linalg.solve(Y.T @ Y, P.T)          # Gi P^T
+    t3 = mu * (1.0 - float(np.trace(P @ X)) / nq)
+    dY3 = (mu / nq) * (-2.0 * Q @ X.T + 2.0 * Y @ (X @ X.T))
+    return t1 + t2 + t3, dY1 + dY2 + dY3
 
 
 def backward(params, cache, dY: np.ndarray):

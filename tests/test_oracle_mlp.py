@@ -68,11 +68,29 @@ def test_loss_invariances_and_limits():
     Y = rng.standard_normal((M, n))
     l0 = mlp.loss_and_grad_Y(Y, Q)[0]
     assert abs(mlp.loss_and_grad_Y(-2.5 * Y @ R, Q)[0] - l0) < 1e-12
-    # a block orthogonal to span(Q) has first term 1
+    # a block orthogonal to span(Q): nothing of it inside, nothing of span(Q)
+    # covered (first and third terms 1; orthonormal columns: second term 0)
     Yo = rng.standard_normal((M, n))
     Yo -= Q @ (Q.T @ Yo)
     Yo = np.linalg.qr(Yo)[0]
-    assert abs(mlp.loss_and_grad_Y(Yo, Q)[0] - 1.0) < 1e-12
+    assert abs(mlp.loss_and_grad_Y(Yo, Q)[0] - 2.0) < 1e-12
+    # half of span(Q) plus half outside: half of the block outside the
+    # target, half of the target uncovered -> 1/2 + 1/2
+    Yh = np.concatenate([Q[:, : n // 2] @ np.linalg.qr(rng.standard_normal((n // 2, n // 2)))[0],
+                         Yo[:, : n // 2]], axis=1)
+    assert abs(mlp.loss_and_grad_Y(Yh, Q)[0] - 1.0) < 1e-12
+    # the coverage term alone: a block that holds span(Q) and more covers it
+    # fully (third term 0) but lies half outside (first term 1/2)
+    Yc = np.concatenate([Q, Yo], axis=1)
+    Qc = Q
+    l_c = mlp.loss_and_grad_Y(Yc, Qc, lam=0.0)[0]
+    assert abs(l_c - 0.5) < 1e-12
+    # scaling one column leaves the coverage term at 0: the loss is the
+    # first term alone, 1 - ||Q^T Y||^2 / ||Y||^2
+    Ys = Yc.copy()
+    Ys[:, 3] *= 7.0
+    first = 1.0 - float(np.sum((Qc.T @ Ys) ** 2)) / float(np.sum(Ys ** 2))
+    assert abs(mlp.loss_and_grad_Y(Ys, Qc, lam=0.0)[0] - first) < 1e-12
 
 
 def test_features_single_atom_closed_form():
