@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c1",
-                    choices=["c1", "c2", "c3", "c4", "kernels", "density", "rrgep", "scf"],
+                    choices=["c0", "c1", "c2", "c3", "c4", "kernels", "density", "rrgep", "scf"],
                     help="c1: FP64 pass at production size (the headline line); c2: mixed precision "
                          "time-to-accuracy at N=1024; c3: batched k-point solves; c4: learned warm start; "
                          "kernels: one 128-column filter step per precision; density: electron density "
@@ -137,6 +137,8 @@ def main():
         return run_rrgep(args)
     if args.workload == "scf":
         return run_scf(args)
+    if args.workload == "c0":
+        return run_c0(args)
     return run_c1(args)
 
 
@@ -213,6 +215,98 @@ def run_c1(args):
             out["cpu_baseline"] = cpu_baseline(sys_, 64, seed=sys_.seed + 3_000_000)
         except Exception as e:  # the GPU figure stands on its own
             out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+def run_c0(args):
+    """The small plain FP64 workload (4^3 cells, p = 4, M = 4096, 2 atoms, no
+    projectors, N = B = 32, m = 20, 10 passes after the initial
+    Rayleigh-Ritz): launch-bound.  Reports microseconds per pass of
+    chfsi_solve (filter, CholGS, Rayleigh-Ritz, residuals) and of the same
+    solve through chfsi_solve_batched with the filter captured in a hipGraph,
+    the eigenvalues against the oracle's iteration, and the oracle timed on
+    the host: the whole 10-pass solve with all cores and with one thread,
+    and the gather / cell GEMM / scatter split of one 32-column H~X."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    import paper_2203_07820_amd as lib
+    import workloads
+    from oracle import chfsi as ochfsi
+    from oracle import fe
+
+    cfg = workloads.CONFIGS["c0"]
+    s = workloads.config("c0")
+    N, m, passes = cfg.nwanted, cfg.degree, cfg.passes
+    torch.cuda.set_device(0)
+    ctx = lib.Context(0)
+    op = lib.Operator(ctx, s)
+    X0 = workloads.start_block(op.M, N, seed=s.seed + 1_000_000)
+    v0 = workloads.lanczos_start(op.M, seed=s.seed + 2_000_000)
+    b, _ = op.bounds(20, v0=torch.from_numpy(v0).cuda())
+    runs = {}
+    for name, graph in (("solve", False), ("solve_batched_graph", True)):
+        per = []
+        for rep in range(max(2, args.steps)):
+            X = torch.from_numpy(X0).cuda()
+            torch.cuda.synchronize()
+            if graph:
+                th, rs, st = ctx.solve_batched([op], [X], N, m=m, block=N, filter_prec=lib.F64,
+                                               fixed_passes=passes, b_upper=b, use_graph=True, history=True)
+                th, st = th[0], st[0]
+            else:
+                th, r, st = op.solve(X, N, m=m, block=N, fixed_passes=passes, b_upper=b, history=True)
+            t = np.asarray(st["history"]["time_ms"])
+            per.append(np.diff(t))
+            split = {k: st[k] / passes * 1e3 for k in ("t_filter", "t_cholgs", "t_rr") if k in st}
+        per = np.concatenate(per[1:])            # the first repetition warms up
+        runs[name] = {"us_per_pass_median": float(np.median(per) * 1e3),
+                      "us_per_pass_min": float(np.min(per) * 1e3), "passes_timed": int(per.size),
+                      "us_per_pass_by_step": split, "theta": [float(x) for x in th]}
+        log(f"# c0 {name}: {np.median(per) * 1e3:.0f} us per pass")
+    # the oracle's iteration on the same inputs (and its time)
+    ref_op = fe.build_operator(s)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref = ochfsi.solve(lambda v: fe.apply_cellwise(ref_op, v), X0, N, m=m, block=N, v0=v0, passes=passes, b=b)
+    t_all = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ochfsi.solve(lambda v: fe.apply_cellwise(ref_op, v), X0, N, m=m, block=N, v0=v0, passes=passes, b=b)
+        t_one = time.perf_counter() - t0
+    dtheta = max(float(np.max(np.abs(np.asarray(runs[k]["theta"]) - ref.theta))) for k in runs)
+    # gather / GEMM / scatter of the oracle's cell-wise product on one block
+    import scipy.sparse as sp
+    A0 = ref_op.cell_matrix()
+    X = X0.copy()
+    t0 = time.perf_counter()
+    Xc = (ref_op.D[:, None] * X)[ref_op.cells]
+    t_g = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Yc = np.einsum("ij,cjb->cib", A0, Xc, optimize=True)
+    t_m = time.perf_counter() - t0
+    idx = ref_op.cells.ravel()
+    S = sp.csr_matrix((np.ones(idx.size), (idx, np.arange(idx.size))), shape=(ref_op.M, idx.size))
+    t0 = time.perf_counter()
+    S @ Yc.reshape(-1, N)
+    t_s = time.perf_counter() - t0
+    fl_hx = 2.0 * op.mcell ** 2 * op.E * N
+    fl_pass = (m + 1) * fl_hx
+    us = runs["solve"]["us_per_pass_median"]
+    out = {"metric": "ChFSI pass time, small FP64 workload", "value": us, "unit": "us", "n_gpus": 1,
+           "steps": passes, "warmup": 1, "ms_per_step": us / 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "c0: 4^3 cells p=4 (M=4096), 2 Gaussian atoms, N=B=32, m=20, 10 passes",
+                      "M": op.M, "E": op.E, "N": N, "degree": m},
+           "runs": runs, "max_abs_theta_vs_oracle": dtheta,
+           "floor_us_per_pass_fp64_mfma": fl_pass / (PEAK_FP64_TFLOPS * 1e12) * 1e6,
+           "cpu_baseline": {"value": t_all / passes * 1e6, "unit": "us per pass", "cores": cores, "kind": "oracle",
+                            "sample": f"oracle.chfsi.solve, {passes} passes with oracle.fe.apply_cellwise "
+                                      f"({t_all:.2f} s)",
+                            "single_thread_us_per_pass": t_one / passes * 1e6,
+                            "hx_split_ms": {"gather": t_g * 1e3, "cell_gemm": t_m * 1e3, "scatter": t_s * 1e3,
+                                            "gemm_GFLOPs": fl_hx / t_m / 1e9}}}
     print(json.dumps(out), flush=True)
 
 

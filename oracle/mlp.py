@@ -13,12 +13,15 @@ learned component; this is the spec extension whose readings are:
 * Loss per configuration, with Y the output block and Q the converged
   orthonormal Ritz block (both M x 128):
   l = ||Y - Q Q^T Y||_F^2 / ||Y||_F^2 + 0.1 ||128 Y^T Y / ||Y||_F^2 - I||_F^2 / 128^2
-      + ||Q - P_Y Q||_F^2 / 128,   P_Y = Y (Y^T Y)^-1 Y^T
+      + (1 - tr(Q^T Y (Y^T Y + eps I)^-1 Y^T Q) / 128),   eps = 0.01 ||Y||_F^2 / 128
   (rotation, sign and scale invariant).  The first term is the part of the
   output outside the target subspace, the third the part of the target
-  outside the output's span (so that an output confined to a few target
-  directions is penalised), the second keeps the columns from collapsing
-  onto one direction.
+  outside the output's span, ||Q - P_Y Q||_F^2 / 128 with the projector
+  P_Y = Y (Y^T Y)^-1 Y^T regularised by a ridge of 1 % of the mean
+  eigenvalue of Y^T Y (so that an output confined to a few target
+  directions is penalised, and directions the output barely holds count
+  only in proportion); the second keeps the columns from collapsing onto
+  one direction.
 * Adam (lr, beta1 = 0.9, beta2 = 0.999, eps = 1e-8).
 """
 from __future__ import annotations
@@ -77,7 +80,7 @@ def forward(params, Fn: np.ndarray):
     return Y, (Fn, A1, A2)
 
 
-def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1, mu: float = 1.0):
+def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1, mu: float = 1.0, delta: float = 0.01):
     """Subspace loss and its gradient with respect to Y."""
     n = Y.shape[1]
     nq = Q.shape[1]
@@ -92,11 +95,13 @@ def loss_and_grad_Y(Y: np.ndarray, Q: np.ndarray, lam: float = 0.1, mu: float = 
     dY1 = 2.0 * R / s - 2.0 * r2 * Y / s ** 2
     inner = float(np.sum(D * (Y.T @ Y)))
     dY2 = (lam / n ** 2) * ((4.0 * n / s) * (Y @ D) - (4.0 * n / s ** 2) * inner * Y)
-    # coverage: ||Q - P_Y Q||^2 = nq - tr(P (Y^T Y)^-1 P^T); its gradient
-    # -2 Q P Gi + 2 Y Gi P^T P Gi with Gi = (Y^T Y)^-1
-    X = np.linalg.solve(Y.T @ Y, P.T)          # Gi P^T
+    # coverage: 1 - tr(P Ge^-1 P^T) / nq with Ge = Y^T Y + eps I,
+    # eps = delta s / n; with X = Ge^-1 P^T its gradient is
+    # (mu / nq) (-2 Q X^T + 2 Y X X^T + (2 delta / n) ||X||^2 Y)
+    eps = delta * s / n
+    X = np.linalg.solve(Y.T @ Y + eps * np.eye(n), P.T)
     t3 = mu * (1.0 - float(np.trace(P @ X)) / nq)
-    dY3 = (mu / nq) * (-2.0 * Q @ X.T + 2.0 * Y @ (X @ X.T))
+    dY3 = (mu / nq) * (-2.0 * Q @ X.T + 2.0 * Y @ (X @ X.T) + (2.0 * delta / n) * float(np.sum(X * X)) * Y)
     return t1 + t2 + t3, dY1 + dY2 + dY3
 
 

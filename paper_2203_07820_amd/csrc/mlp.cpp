@@ -105,6 +105,47 @@ int forward(chfsi_mlp* net, const float* F, int64_t n, float* Yext) {
   return 0;
 }
 
+// X = (G + eps I)^-1 P^T (D x nq) for the symmetric G (D x D, float,
+// row-major) and P (nq x D), by Cholesky in FP64; captured = tr(P X).
+// False if G + eps I is not positive definite.
+bool coverage_solve(const std::vector<float>& Gf, const std::vector<float>& Pf, int D, int nq, double eps,
+                    std::vector<double>& X, double* captured) {
+  std::vector<double> L(static_cast<size_t>(D) * D, 0.0);
+  const double ridge = eps;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.5 * (static_cast<double>(Gf[static_cast<size_t>(i) * D + j]) + Gf[static_cast<size_t>(j) * D + i]);
+      if (i == j) v += ridge;
+      for (int k = 0; k < j; ++k) v -= L[static_cast<size_t>(i) * D + k] * L[static_cast<size_t>(j) * D + k];
+      if (i == j) {
+        if (!(v > 0.0)) return false;
+        L[static_cast<size_t>(i) * D + i] = std::sqrt(v);
+      } else {
+        L[static_cast<size_t>(i) * D + j] = v / L[static_cast<size_t>(j) * D + j];
+      }
+    }
+  X.assign(static_cast<size_t>(D) * nq, 0.0);
+  for (int q = 0; q < nq; ++q) {
+    // L y = P^T[:, q], then L^T x = y
+    std::vector<double> y(D);
+    for (int i = 0; i < D; ++i) {
+      double v = Pf[static_cast<size_t>(q) * D + i];
+      for (int k = 0; k < i; ++k) v -= L[static_cast<size_t>(i) * D + k] * y[k];
+      y[i] = v / L[static_cast<size_t>(i) * D + i];
+    }
+    for (int i = D - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < D; ++k) v -= L[static_cast<size_t>(k) * D + i] * X[static_cast<size_t>(k) * nq + q];
+      X[static_cast<size_t>(i) * nq + q] = v / L[static_cast<size_t>(i) * D + i];
+    }
+  }
+  double t = 0.0;
+  for (int q = 0; q < nq; ++q)
+    for (int i = 0; i < D; ++i) t += static_cast<double>(Pf[static_cast<size_t>(q) * D + i]) * X[static_cast<size_t>(i) * nq + q];
+  *captured = t;
+  return true;
+}
+
 // subspace loss of the network output against Q (n x nq, ldq, orthonormal);
 // with grads, the gradient of the loss w.r.t. every parameter is written to
 // net->grads.
@@ -139,15 +180,46 @@ int loss_grad(chfsi_mlp* net, const float* F, int64_t n, const float* Q, int64_t
   HIP_TRY(c, mlp_loss_small(G, D, s, Dm, static_cast<double*>(small), c->stream));
   double hs[2];
   HIP_TRY(c, hipMemcpyAsync(hs, small, 16, hipMemcpyDeviceToHost, c->stream));
+  // coverage term mu (1 - tr(P G^-1 P^T) / nq) (P = Q^T Y, G = Y^T Y): the
+  // D x D algebra runs on the host in FP64
+  std::vector<float> hP(static_cast<size_t>(nq) * D), hG(static_cast<size_t>(D) * D), hDm(static_cast<size_t>(D) * D);
+  HIP_TRY(c, hipMemcpyAsync(hP.data(), Pm, hP.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(hG.data(), G, hG.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(hDm.data(), Dm, hDm.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const double lam = 0.1, nn = D;
-  *loss = r2 / s + lam * hs[1] / (nn * nn);
+  // ridge eps = delta s / D (delta = 1 % of the mean eigenvalue of G)
+  const double lam = 0.1, nn = D, mu = 1.0, delta = 0.01;
+  std::vector<double> Xc;   // (G + eps I)^-1 P^T (D x nq, row-major)
+  double captured = 0.0;
+  if (!coverage_solve(hG, hP, D, nq, delta * s / nn, Xc, &captured))
+    return fail(c, CHFSI_EDIVERGE, "network output overlap is not positive definite");
+  *loss = r2 / s + lam * hs[1] / (nn * nn) + mu * (1.0 - captured / nq);
   if (!grads) return 0;
+  double xx = 0.0;
+  for (double v : Xc) xx += v * v;
   // dY = (2/s) R + (-2 r2/s^2 - (lam/n^2)(4n/s^2) inner) Y + (lam/n^2)(4n/s) Y D
-  HIP_TRY(c, mlp_gemm(Y, D, Dm, D, 1, T2, D, n, D, D, 0, nullptr, nullptr, 0, c->stream));
+  //      + (mu / nq) (-2 Q X^T + 2 Y X X^T + (2 delta / n) ||X||^2 Y);
+  // the coverage part is folded into the two products: P -> P + k1 X^T in
+  // R = Y - Q P and D -> D + k2 X X^T in Y D, and into the Y coefficient
   const double c1 = 2.0 / s;
-  const double c2 = -2.0 * r2 / (s * s) - (lam / (nn * nn)) * (4.0 * nn / (s * s)) * hs[0];
+  const double c2 = -2.0 * r2 / (s * s) - (lam / (nn * nn)) * (4.0 * nn / (s * s)) * hs[0] +
+                    (mu / nq) * (2.0 * delta / nn) * xx;
   const double c3 = (lam / (nn * nn)) * (4.0 * nn / s);
+  const double k1 = (2.0 * mu / nq) / c1, k2 = (2.0 * mu / nq) / c3;
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < D; ++j)
+      hP[static_cast<size_t>(i) * D + j] += static_cast<float>(k1 * Xc[static_cast<size_t>(j) * nq + i]);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < nq; ++q) acc += Xc[static_cast<size_t>(i) * nq + q] * Xc[static_cast<size_t>(j) * nq + q];
+      hDm[static_cast<size_t>(i) * D + j] += static_cast<float>(k2 * acc);
+    }
+  HIP_TRY(c, hipMemcpyAsync(Pm, hP.data(), hP.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(Dm, hDm.data(), hDm.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mlp_gemm(Q, ldq, Pm, D, 1, T1, D, n, nq, D, 2, nullptr, Y, D, c->stream));
+  HIP_TRY(c, mlp_gemm(Y, D, Dm, D, 1, T2, D, n, D, D, 0, nullptr, nullptr, 0, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // the host copies above are reused on return
   HIP_TRY(c, mlp_combine(static_cast<float>(c1), T1, static_cast<float>(c2), Y, static_cast<float>(c3), T2, dY,
                          n * D, c->stream));
   // backward through the three layers

@@ -61,9 +61,11 @@ def test_loss_invariances_and_limits():
     rng = np.random.default_rng(4)
     M, n = 80, 8
     Q = np.linalg.qr(rng.standard_normal((M, n)))[0]
-    # a block spanning exactly span(Q) with orthogonal columns scaled equally: loss 0
+    # a block spanning exactly span(Q) with orthogonal columns scaled equally:
+    # first two terms 0, the coverage term only the ridge's d / (1 + d)
     R = np.linalg.qr(rng.standard_normal((n, n)))[0]
-    assert abs(mlp.loss_and_grad_Y(3.0 * Q @ R, Q)[0]) < 1e-24 + 1e-14
+    assert abs(mlp.loss_and_grad_Y(3.0 * Q @ R, Q)[0] - 0.01 / 1.01) < 1e-14
+    assert abs(mlp.loss_and_grad_Y(3.0 * Q @ R, Q, delta=0.0)[0]) < 1e-14
     # rotation / sign / scale invariance
     Y = rng.standard_normal((M, n))
     l0 = mlp.loss_and_grad_Y(Y, Q)[0]
@@ -74,23 +76,26 @@ def test_loss_invariances_and_limits():
     Yo -= Q @ (Q.T @ Yo)
     Yo = np.linalg.qr(Yo)[0]
     assert abs(mlp.loss_and_grad_Y(Yo, Q)[0] - 2.0) < 1e-12
-    # half of span(Q) plus half outside: half of the block outside the
-    # target, half of the target uncovered -> 1/2 + 1/2
+    # half of span(Q) plus half outside, orthonormal: half of the block
+    # outside the target; the ridge eps = 0.01 (Y^T Y = I) leaves half of the
+    # target covered to 1 / 1.01
+    d = 0.01
     Yh = np.concatenate([Q[:, : n // 2] @ np.linalg.qr(rng.standard_normal((n // 2, n // 2)))[0],
                          Yo[:, : n // 2]], axis=1)
-    assert abs(mlp.loss_and_grad_Y(Yh, Q)[0] - 1.0) < 1e-12
-    # the coverage term alone: a block that holds span(Q) and more covers it
-    # fully (third term 0) but lies half outside (first term 1/2)
+    assert abs(mlp.loss_and_grad_Y(Yh, Q)[0] - (0.5 + 1.0 - 0.5 / (1.0 + d))) < 1e-12
+    # a block holding span(Q) and as much outside (2n orthonormal columns,
+    # lam = 0): first term 1/2, third term d / (1 + d)
     Yc = np.concatenate([Q, Yo], axis=1)
-    Qc = Q
-    l_c = mlp.loss_and_grad_Y(Yc, Qc, lam=0.0)[0]
-    assert abs(l_c - 0.5) < 1e-12
-    # scaling one column leaves the coverage term at 0: the loss is the
-    # first term alone, 1 - ||Q^T Y||^2 / ||Y||^2
+    assert abs(mlp.loss_and_grad_Y(Yc, Q, lam=0.0)[0] - (0.5 + d / (1.0 + d))) < 1e-12
+    # one target column scaled by 7: Y^T Y = diag(1, .., 49, .., 1), the
+    # ridge is d ||Y||^2 / 2n, the first term 1 - ||Q^T Y||^2 / ||Y||^2
     Ys = Yc.copy()
     Ys[:, 3] *= 7.0
-    first = 1.0 - float(np.sum((Qc.T @ Ys) ** 2)) / float(np.sum(Ys ** 2))
-    assert abs(mlp.loss_and_grad_Y(Ys, Qc, lam=0.0)[0] - first) < 1e-12
+    s2 = float(np.sum(Ys ** 2))
+    eps = d * s2 / (2 * n)
+    first = 1.0 - float(np.sum((Q.T @ Ys) ** 2)) / s2
+    third = 1.0 - ((n - 1) / (1.0 + eps) + 49.0 / (49.0 + eps)) / n
+    assert abs(mlp.loss_and_grad_Y(Ys, Q, lam=0.0)[0] - (first + third)) < 1e-12
 
 
 def test_features_single_atom_closed_form():
