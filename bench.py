@@ -118,6 +118,10 @@ def main():
     ap.add_argument("--c4-train", type=int, default=200, help="c4: training configurations solved")
     ap.add_argument("--c4-test", type=int, default=40, help="c4: held-out configurations")
     ap.add_argument("--c4-epochs", type=int, default=40, help="c4: passes over the training set")
+    ap.add_argument("--c4-phase", default="all", choices=["all", "train", "eval"],
+                    help="c4: all in one run, or one training chunk / the evaluation (network state in --c4-state)")
+    ap.add_argument("--c4-range", default=None, help="c4 train phase: configurations a:b of this chunk")
+    ap.add_argument("--c4-state", default=None, help="c4: network state file (npz) read and written by the phases")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
@@ -502,8 +506,10 @@ def run_c3(args):
         log(f"# autotune {name}: {tuning[name]} ({time.perf_counter() - t1:.1f}s)")
 
     modes = {}
-    # each problem on its own, complex128
+    # each problem on its own, complex128 (cell-kernel launches timed with HIP events)
     Xs = fill()
+    ctx.set_timing(True)
+    ctx.kernel_time(reset=True)
     seq_ms, seq_filter_ms, seq_theta = 0.0, 0.0, []
     for q, o in enumerate(ops):
         th, r, st = o.solve(Xs[q], Ns[q], m, B, fixed_passes=K, filter_prec=lib.C128, b_upper=bs[q], history=True)
@@ -512,21 +518,33 @@ def run_c3(args):
         seq_theta.append(th)
         if q % 4 == 3:
             log(f"# sequential: system {tags[q][0]} done, running pass time {seq_ms:.0f} ms")
+    kms_seq, n_seq, kfl_seq = ctx.kernel_time(reset=True)
+    ctx.set_timing(False)
     modes["sequential_c128"] = {"pass_ms": seq_ms, "filter_ms_per_pass": seq_filter_ms,
-                                "tflops": total / (seq_ms * 1e-3) / 1e12}
+                                "tflops": total / (seq_ms * 1e-3) / 1e12,
+                                "cell_kernel_ms_per_pass": kms_seq / K, "cell_kernel_launches": n_seq,
+                                "cell_kernel_tflops": kfl_seq / (kms_seq * 1e-3) / 1e12}
     del Xs
     thetas = {}
     for name, prec, graph in (("batched_c128", lib.C128, False), ("batched_graph_c128", lib.C128, True),
                               ("batched_graph_c64", lib.C64, True)):
         Xs = fill()
         t1 = time.perf_counter()
+        timed = not graph   # the graph's launches are not timed one by one
+        ctx.set_timing(timed)
+        ctx.kernel_time(reset=True)
         th, rs, st = ctx.solve_batched(ops, Xs, Ns, m, B, prec, fixed_passes=K, b_upper=bs, use_graph=graph,
                                        history=True)
+        kms_b, n_b, kfl_b = ctx.kernel_time(reset=True)
+        ctx.set_timing(False)
         big = int(np.argmax([o.M * Ns[q] for q, o in enumerate(ops)]))
         pm = per_pass_ms(st[big]["history"])
         modes[name] = {"pass_ms": pm, "filter_ms_per_pass": st[big]["t_filter"] / K,
                        "tflops": total / (pm * 1e-3) / 1e12,
                        "max_resid": float(max(np.max(rs[q][:Ns[q]]) for q in range(len(ops))))}
+        if timed:
+            modes[name].update(cell_kernel_ms_per_pass=kms_b / K, cell_kernel_launches=n_b,
+                               cell_kernel_tflops=kfl_b / (kms_b * 1e-3) / 1e12)
         thetas[name] = th
         log(f"# {name}: {pm:.0f} ms per pass ({time.perf_counter() - t1:.1f}s)")
         del Xs
@@ -545,6 +563,11 @@ def run_c3(args):
                    "pass_flops": total},
         "modes": modes,
         "speedup_batched_graph_vs_sequential": modes["sequential_c128"]["pass_ms"] / pm,
+        # the same cell-kernel work (filter steps and Rayleigh-Ritz products of
+        # all 32 problems) in one launch per step against one launch per
+        # problem and step: > 1 means the batched launch keeps the GPU busier
+        "load_balance_efficiency": (modes["sequential_c128"]["cell_kernel_ms_per_pass"] /
+                                    modes["batched_c128"]["cell_kernel_ms_per_pass"]),
         "speedup_c64_vs_c128": pm / modes["batched_graph_c64"]["pass_ms"],
         "max_dtheta_batched_vs_sequential": d_seq,
         "max_dtheta_c64_vs_c128_after_same_passes": d_c64,
@@ -558,7 +581,15 @@ def run_c4(args):
     box solved by plain FP64 ChFSI from random starts to max r <= 1e-6; the
     network (32 -> 128 -> 128 -> 128, tanh, FP32) is trained on their Ritz
     blocks by the library's own kernels, then held-out configurations are
-    solved from the network's block and from a random block."""
+    solved from the network's block and from a random block.
+
+    --c4-phase all runs everything in one process.  For the full
+    configuration (1800 + 200), which does not fit one run, --c4-phase train
+    --c4-range a:b solves and trains on one chunk of training configurations
+    (kept on the device for the chunk's epochs), continuing from the network
+    state in --c4-state (weights and the feature standardisation, fixed by
+    the first chunk) and writing it back; --c4-phase eval then solves the
+    held-out configurations from both starts."""
     import numpy as np
     import torch
 
@@ -566,7 +597,6 @@ def run_c4(args):
     import workloads
 
     N, nb, B, m, tol = 128, 32, 128, 30, 1e-6
-    n_train, n_test, epochs = args.c4_train, args.c4_test, args.c4_epochs
     torch.cuda.set_device(0)
     ctx = lib.Context(0)
 
@@ -583,39 +613,81 @@ def run_c4(args):
         lib.features(op, F)
         return F
 
-    # 1. training data: converged Ritz blocks of the training configurations
-    t0 = time.perf_counter()
-    feats, targets, gen_passes = [], [], []
-    for j in range(n_train):
-        op = lib.Operator(ctx, workloads.config("c4", j))
-        X = random_block(op, j)
-        th, r, st = solve(op, X, j)
-        feats.append(featurize(op))
-        targets.append(X[:, :N].float().contiguous())
-        gen_passes.append(st["passes"])
-        del X
-        op.close()
-        if j % 10 == 9:
-            log(f"# c4 data: {j + 1}/{n_train} solved, mean passes {np.mean(gen_passes):.1f}, "
-                f"{time.perf_counter() - t0:.0f}s")
-    t_gen = time.perf_counter() - t0
-    # 2. standardisation from a host subsample of the training features
-    sample = np.concatenate([F[::64].cpu().numpy().astype(np.float64) for F in feats])
-    mean, scale = sample.mean(axis=0), sample.std(axis=0) + 1e-6
+    state = {}
+    if args.c4_state and os.path.exists(args.c4_state):
+        with np.load(args.c4_state) as z:
+            state = {k: z[k] for k in z.files}
     net = lib.Network(ctx, 32, 128, N, seed=4242)
-    net.set_norm(mean, scale)
-    # 3. training (Adam, one configuration per step)
-    t0 = time.perf_counter()
-    rng = np.random.default_rng(7)
-    curve = []
-    for ep in range(epochs):
-        losses = [net.train_step(feats[j], targets[j], lr=1e-3) for j in rng.permutation(n_train)]
-        curve.append(float(np.mean(losses)))
-        if ep % 5 == 4 or ep == epochs - 1:
-            log(f"# c4 training epoch {ep + 1}: mean loss {curve[-1]:.4f} ({time.perf_counter() - t0:.0f}s)")
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del feats, targets
+    if "params" in state:
+        net.set_params(state["params"])
+        net.set_norm(state["mean"], state["scale"])
+
+    def train_chunk(lo, hi, epochs):
+        # 1. training data: converged Ritz blocks of configurations lo .. hi - 1
+        t0 = time.perf_counter()
+        feats, targets, gen_passes = [], [], []
+        for j in range(lo, hi):
+            op = lib.Operator(ctx, workloads.config("c4", j))
+            X = random_block(op, j)
+            th, r, st = solve(op, X, j)
+            feats.append(featurize(op))
+            targets.append(X[:, :N].float().contiguous())
+            gen_passes.append(st["passes"])
+            del X
+            op.close()
+            if (j - lo) % 10 == 9:
+                log(f"# c4 data: {j + 1 - lo}/{hi - lo} solved, mean passes {np.mean(gen_passes):.1f}, "
+                    f"{time.perf_counter() - t0:.0f}s")
+        t_gen = time.perf_counter() - t0
+        # 2. standardisation from a host subsample of the first chunk's features
+        if "mean" not in state:
+            sample = np.concatenate([F[::64].cpu().numpy().astype(np.float64) for F in feats])
+            state["mean"], state["scale"] = sample.mean(axis=0), sample.std(axis=0) + 1e-6
+            net.set_norm(state["mean"], state["scale"])
+        # 3. training (Adam, one configuration per step)
+        t0 = time.perf_counter()
+        rng = np.random.default_rng(7 + lo)
+        curve = []
+        for ep in range(epochs):
+            losses = [net.train_step(feats[q], targets[q], lr=1e-3) for q in rng.permutation(hi - lo)]
+            curve.append(float(np.mean(losses)))
+            if ep % 5 == 4 or ep == epochs - 1:
+                log(f"# c4 training epoch {ep + 1}: mean loss {curve[-1]:.4f} ({time.perf_counter() - t0:.0f}s)")
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        return t_gen, t_train, curve, gen_passes
+
+    def save_state():
+        if args.c4_state:
+            os.makedirs(os.path.dirname(os.path.abspath(args.c4_state)), exist_ok=True)
+            np.savez(args.c4_state, **state)
+
+    if args.c4_phase == "train":
+        lo, hi = (int(x) for x in args.c4_range.split(":"))
+        t_gen, t_train, curve, gen_passes = train_chunk(lo, hi, args.c4_epochs)
+        state["params"] = net.params()
+        state["chunks"] = np.append(state.get("chunks", np.zeros((0, 2), dtype=np.int64)).reshape(-1, 2),
+                                    [[lo, hi]], axis=0)
+        state["loss_curve"] = np.append(state.get("loss_curve", np.zeros(0)), curve)
+        state["gen_passes"] = np.append(state.get("gen_passes", np.zeros(0)), gen_passes)
+        state["gen_s"] = float(state.get("gen_s", 0.0)) + t_gen
+        state["train_s"] = float(state.get("train_s", 0.0)) + t_train
+        save_state()
+        print(json.dumps({"c4_train_chunk": [lo, hi], "epochs": args.c4_epochs, "data_generation_s": t_gen,
+                          "training_s": t_train, "loss_first_last": [curve[0], curve[-1]],
+                          "data_passes_mean": float(np.mean(gen_passes))}), flush=True)
+        return
+    if args.c4_phase == "all":
+        t_gen, t_train, curve, gen_passes = train_chunk(0, args.c4_train, args.c4_epochs)
+        state.update(params=net.params(), chunks=np.array([[0, args.c4_train]]), loss_curve=np.array(curve),
+                     gen_passes=np.array(gen_passes, dtype=float), gen_s=t_gen, train_s=t_train)
+        save_state()
+    if "params" not in state:
+        raise SystemExit("c4 eval: no trained network (run the train phase first, or --c4-phase all)")
+    chunks = np.asarray(state["chunks"]).reshape(-1, 2)
+    n_train = int(np.sum(chunks[:, 1] - chunks[:, 0]))
+    curve = np.asarray(state["loss_curve"])
+    n_test = args.c4_test
     # 4. held-out configurations: random start vs learned start
     rows, captures = [], []
     for i in range(n_test):
@@ -648,12 +720,14 @@ def run_c4(args):
                      "heldout_loss": loss})
         del X, Xl, F, Q
         op.close()
-        log(f"# c4 held-out {i + 1}/{n_test}: passes random {st_r['passes']} learned {st_l['passes']}"
-            f"{' (fallback)' if fallback else ''}")
+        if i % 10 == 9 or i == n_test - 1:
+            log(f"# c4 held-out {i + 1}/{n_test}: passes random {st_r['passes']} learned {st_l['passes']}"
+                f"{' (fallback)' if fallback else ''}")
     pr = np.array([r_["passes_random"] for r_ in rows], dtype=float)
     pl = np.array([r_["passes_learned"] for r_ in rows], dtype=float)
     tr = np.array([r_["ms_random"] for r_ in rows])
     tl = np.array([r_["ms_learned"] for r_ in rows])
+    epochs = int(curve.size // max(1, len(chunks)))
     out = {
         "metric": "filter passes saved by the learned warm start at max r <= 1e-6 (c4)",
         "value": float(np.mean(pr - pl)), "unit": "passes", "n_gpus": 1, "steps": n_test, "warmup": 0,
@@ -662,16 +736,18 @@ def run_c4(args):
         "config": {"workload": "c4: 16 Gaussian atoms with projectors in a 12^3-cell p=5 box (L=24, M=216000), "
                                f"N=128 + {nb} buffer, B=128, m=30, tol 1e-6; {n_train} training and {n_test} "
                                "held-out configurations (seeds 4000+j, held out from j=1800)",
-                   "n_train": n_train, "n_test": n_test, "epochs": epochs},
+                   "n_train": n_train, "n_test": n_test, "epochs_per_chunk": epochs,
+                   "training_chunks": chunks.tolist()},
         "passes_random_mean": float(pr.mean()), "passes_random_sd": float(pr.std()),
         "passes_learned_mean": float(pl.mean()), "passes_learned_sd": float(pl.std()),
         "passes_saved_sd": float(np.std(pr - pl)),
         "time_to_tol_ms_random_mean": float(tr.mean()), "time_to_tol_ms_learned_mean": float(tl.mean()),
         "fallbacks": int(sum(r_["fallback"] for r_ in rows)),
         "all_converged": bool(all(r_["converged"] for r_ in rows)),
-        "train_loss_first_last": [curve[0], curve[-1]],
+        "train_loss_first_last": [float(curve[0]), float(curve[-1])],
         "heldout_loss_mean": float(np.mean([r_["heldout_loss"] for r_ in rows])),
-        "data_generation_s": t_gen, "training_s": t_train, "data_passes_mean": float(np.mean(gen_passes)),
+        "data_generation_s": float(state["gen_s"]), "training_s": float(state["train_s"]),
+        "data_passes_mean": float(np.mean(state["gen_passes"])),
         "captured_fraction_by_state_quarter": [float(x) for x in
                                                np.mean(captures, axis=0)[:N].reshape(4, -1).mean(axis=1)],
         "captured_fraction_buffer_states": float(np.mean(np.mean(captures, axis=0)[N:])),
@@ -999,26 +1075,34 @@ def density_oracle_sample(s, X, w, E):
                       f"{X.shape[1]} columns ({dt:.1f} s)", "seconds": dt}
 
 
-def c2_oracle_sample(sys_, Xref, theta, ref_tol):
-    """The oracle's cell-wise H~ on 8 sampled reference Ritz vectors (full size),
-    timed; their residuals in the oracle's own operator come out with it."""
+def c2_oracle_sample(sys_, Xref, theta, ref_tol, nwanted=1024):
+    """The oracle's cell-wise H~ applied to every wanted reference Ritz vector
+    (full size, 64 columns at a time), timed: the residuals of all
+    reference pairs in the oracle's own, independently built operator
+    certify the FP64 reference that the mixed runs are measured against."""
     import numpy as np
 
     from oracle import fe
-    idx = np.linspace(0, 1023, 8).astype(int)
-    V = Xref[:, idx].cpu().numpy()
     cores = len(os.sched_getaffinity(0))
     op = fe.build_operator(sys_)
+    res = np.empty(nwanted)
     t0 = time.perf_counter()
-    HV = fe.apply_cellwise(op, V, chunk=256)
+    for c0 in range(0, nwanted, 64):
+        c1 = min(nwanted, c0 + 64)
+        V = Xref[:, c0:c1].cpu().numpy()
+        HV = fe.apply_cellwise(op, V, chunk=256)
+        res[c0:c1] = np.linalg.norm(HV - V * theta[c0:c1][None, :], axis=0)
+        log(f"# c2 oracle certification: {c1}/{nwanted} reference pairs, max residual so far "
+            f"{res[:c1].max():.2e} ({time.perf_counter() - t0:.0f}s)")
     dt = time.perf_counter() - t0
-    res = np.linalg.norm(HV - V * theta[idx][None, :], axis=0)
-    fl = 2.0 * op.cells.shape[1] ** 2 * op.E * V.shape[1]
+    fl = 2.0 * op.cells.shape[1] ** 2 * op.E * nwanted
+    q = np.quantile(res, [0.5, 0.9, 0.99, 1.0])
     return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle cell-wise H~X on 8 reference Ritz vectors of the full c2 operator "
-                      f"({dt:.1f} s); their residuals in the oracle's operator are reported beside it",
-            "oracle_resid_max": float(res.max()), "oracle_resid": [float(x) for x in res],
-            "sample_indices": [int(i) for i in idx]}
+            "sample": f"oracle cell-wise H~X on all {nwanted} wanted reference Ritz vectors of the full c2 "
+                      f"operator, 64 at a time ({dt:.0f} s); their residuals in the oracle's operator certify "
+                      "the FP64 reference",
+            "oracle_resid_max": float(res.max()), "oracle_resid_quantiles_50_90_99_100": [float(x) for x in q],
+            "pairs_above_1e-9": int(np.sum(res > 1e-9)), "reference_tol": ref_tol}
 
 
 if __name__ == "__main__":

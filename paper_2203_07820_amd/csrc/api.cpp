@@ -77,9 +77,8 @@ bool is_single(int prec) { return prec == CHFSI_F32 || prec == CHFSI_BF16 || pre
 // P = h * C^H Xk for the projectors of op (node-level lists, deterministic
 // two-phase sum) into hP (natoms*4 x ldhp, real view), using `part` as the
 // chunk partials (nchunks*4 x ldhp).
-int nl_project(chfsi_op* op, int prec, const void* Xk, int64_t ldx, int64_t ncols, void* part, void* hP,
-               int64_t ldhp) {
-  chfsi_ctx* ctx = op->ctx;
+NlLaunch make_nl(const chfsi_op* op, const void* Xk, int64_t ldx, int64_t ncols, void* part, void* hP,
+                 int64_t ldhp) {
   const HostTables& t = op->t;
   NlLaunch nl;
   nl.natoms = t.natoms;
@@ -98,6 +97,13 @@ int nl_project(chfsi_op* op, int prec, const void* Xk, int64_t ldx, int64_t ncol
   nl.partial = part;
   nl.hP = hP;
   nl.ldhp = ldhp;
+  return nl;
+}
+
+int nl_project(chfsi_op* op, int prec, const void* Xk, int64_t ldx, int64_t ncols, void* part, void* hP,
+               int64_t ldhp) {
+  chfsi_ctx* ctx = op->ctx;
+  const NlLaunch nl = make_nl(op, Xk, ldx, ncols, part, hP, ldhp);
   HIP_TRY(ctx, launch_nl_project(nl, prec, ctx->stream));
   return 0;
 }
@@ -792,7 +798,13 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   const size_t db = hx_desc_bytes(prec);
   const size_t tab_desc = static_cast<size_t>(rounds) * m * n * db;
   const size_t tab_off = static_cast<size_t>(rounds) * (n + 1) * sizeof(int64_t);
-  const size_t tab_bytes = align256(tab_desc) + tab_off;
+  // the projections of all problems with projectors in two launches per step:
+  // their descriptors per (round, step), chunk and row offsets per round
+  const size_t tab_nl = static_cast<size_t>(rounds) * m * n * sizeof(NlLaunch);
+  const size_t tab_nloff = static_cast<size_t>(rounds) * 2 * (n + 1) * sizeof(int64_t);
+  const size_t nl_at = align256(tab_desc) + align256(tab_off);
+  const size_t nloff_at = nl_at + align256(tab_nl);
+  const size_t tab_bytes = nloff_at + tab_nloff;
   void *wsb, *tab, *host;
   CHECK(ws_get(ctx, WS_BATCH, total, &wsb));
   CHECK(ws_get(ctx, WS_BTAB, tab_bytes, &tab));
@@ -804,8 +816,12 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   std::memset(host, 0, tab_bytes);
   char* hdesc = static_cast<char*>(host);
   int64_t* hoff = reinterpret_cast<int64_t*>(static_cast<char*>(host) + align256(tab_desc));
+  NlLaunch* hnl = reinterpret_cast<NlLaunch*>(static_cast<char*>(host) + nl_at);
+  int64_t* hnloff = reinterpret_cast<int64_t*>(static_cast<char*>(host) + nloff_at);
   std::vector<std::vector<int>> active(rounds);
   std::vector<std::vector<int64_t>> width(rounds);
+  std::vector<int> nl_count(rounds, 0), nl_tiles(rounds, 0), nl_rowblk(rounds, 0);
+  std::vector<int64_t> nl_chunks(rounds, 0), nl_rows(rounds, 0);
   for (int r = 0; r < rounds; ++r) {
     int64_t acc = 0;
     for (int q = 0; q < n; ++q) {
@@ -831,15 +847,38 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
                              op->t.has_proj ? base + offHP[q] : nullptr, ldhp[q]);
         pack_hx_desc(L, prec, hdesc + ((static_cast<size_t>(r) * m + (st - 1)) * n + k) * db);
       }
+      if (op->t.has_proj && op->nchunks > 0) {
+        const int j = nl_count[r]++;
+        hnloff[(static_cast<size_t>(r) * 2) * (n + 1) + j] = nl_chunks[r];
+        hnloff[(static_cast<size_t>(r) * 2 + 1) * (n + 1) + j] = nl_rows[r];
+        nl_chunks[r] += op->nchunks;
+        nl_rows[r] += 4 * static_cast<int64_t>(op->t.natoms);
+        nl_tiles[r] = std::max<int>(nl_tiles[r], static_cast<int>((nb + 63) / 64));   // logical columns
+        nl_rowblk[r] = std::max<int>(nl_rowblk[r], static_cast<int>((ldhp[q] + 255) / 256));
+        for (int st = 1; st <= m; ++st)
+          hnl[(static_cast<size_t>(r) * m + (st - 1)) * n + j] =
+              make_nl(op, R(q, (st - 1) % 4), nb, nb, base + offPart[q], base + offHP[q], ldhp[q]);
+      }
     }
     for (int k = na; k <= n; ++k) hoff[r * (n + 1) + k] = acc;
+    for (int j = nl_count[r]; j <= n; ++j) {
+      hnloff[(static_cast<size_t>(r) * 2) * (n + 1) + j] = nl_chunks[r];
+      hnloff[(static_cast<size_t>(r) * 2 + 1) * (n + 1) + j] = nl_rows[r];
+    }
   }
   HIP_TRY(ctx, hipMemcpyAsync(tab, host, tab_bytes, hipMemcpyHostToDevice, ctx->stream));
   const char* dtab = static_cast<const char*>(tab);
   const int64_t* doff = reinterpret_cast<const int64_t*>(dtab + align256(tab_desc));
   const chfsi_ctx::Tuning tu = force ? *force : tuning_for(ctx, p, prec, block);
 
-  auto enqueue = [&]() -> int {
+  // per-round algorithmic flops of the cell kernel (timed launches)
+  std::vector<double> round_flops(rounds, 0.0);
+  for (int r = 0; r < rounds; ++r)
+    for (size_t k = 0; k < active[r].size(); ++k)
+      round_flops[r] += cell_kernel_flops(items[active[r][k]].op, width[r][k]);
+  // timed: HIP events around every batched cell-kernel launch (not inside a
+  // captured graph), read by chfsi_kernel_time like the single-problem ones
+  auto enqueue = [&](bool timed) -> int {
     for (int r = 0; r < rounds; ++r) {
       const int na = static_cast<int>(active[r].size());
       for (int k = 0; k < na; ++k) {
@@ -851,12 +890,17 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
         for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R(q, i), M, nb * cf, nb * cf, sp, ctx->stream));
       }
       for (int st = 1; st <= m; ++st) {
-        for (int k = 0; k < na; ++k) {
-          const int q = active[r][k];
-          chfsi_op* op = items[q].op;
-          if (op->t.has_proj)
-            CHECK(nl_project(op, prec, R(q, (st - 1) % 4), width[r][k], width[r][k], base + offPart[q],
-                             base + offHP[q], ldhp[q]));
+        if (nl_count[r] > 0) {
+          NlBatch nb_;
+          nb_.descs = dtab + nl_at + (static_cast<size_t>(r) * m + (st - 1)) * n * sizeof(NlLaunch);
+          nb_.chunk_off = reinterpret_cast<const int64_t*>(dtab + nloff_at) + (static_cast<size_t>(r) * 2) * (n + 1);
+          nb_.row_off = reinterpret_cast<const int64_t*>(dtab + nloff_at) + (static_cast<size_t>(r) * 2 + 1) * (n + 1);
+          nb_.nprob = nl_count[r];
+          nb_.total_chunks = nl_chunks[r];
+          nb_.total_rows = nl_rows[r];
+          nb_.max_col_tiles = nl_tiles[r];
+          nb_.max_row_blocks = nl_rowblk[r];
+          HIP_TRY(ctx, launch_nl_project_batched(nb_, prec, ctx->stream));
         }
         HxBatch hb;
         hb.p = p;
@@ -870,7 +914,18 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
                                      : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nitems_r, 0x7fffffff)));
         hb.contiguous = tu.contiguous;
         hb.one_per_item = tu.grid_per_cu == 0 && nitems_r <= 0x7fffffff;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+          HIP_TRY(ctx, hipEventCreate(&e0));
+          HIP_TRY(ctx, hipEventCreate(&e1));
+          HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+        }
         HIP_TRY(ctx, launch_cell_hx_batched(hb, prec, ctx->stream));
+        if (timed) {
+          HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+          ctx->pending.emplace_back(e0, e1);
+          ctx->pending_flops.push_back(round_flops[r]);
+        }
       }
       for (int k = 0; k < na; ++k) {
         const int q = active[r][k];
@@ -882,7 +937,7 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
     }
     return 0;
   };
-  if (!use_graph) return enqueue();
+  if (!use_graph) return enqueue(ctx->timing);
   // the graph is keyed by everything its nodes point at
   std::ostringstream key;
   key << m << ":" << prec << ":" << block << ":" << wsb << ":" << tab << ":" << tu.grid_per_cu << ":" << tu.contiguous;
@@ -898,7 +953,7 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
     hipStream_t user = ctx->stream;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
     ctx->stream = ctx->cap_stream;
-    const int rc = enqueue();
+    const int rc = enqueue(false);
     ctx->stream = user;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);

@@ -125,6 +125,21 @@ struct NlLaunch {
 };
 hipError_t launch_nl_project(const NlLaunch& a, int prec, hipStream_t s);
 
+// The projection of nprob operators' blocks in two launches (batched filter):
+// descs = device array of nprob NlLaunch; chunk_off / row_off = device
+// arrays of nprob + 1 offsets of the problems' chunks and of their
+// (atom, component) rows; max_col_tiles = max ceil(ncols / 64) and
+// max_row_blocks = max ceil(ldhp / 256) over the problems.
+struct NlBatch {
+  const void* descs;
+  const int64_t* chunk_off;
+  const int64_t* row_off;
+  int nprob;
+  int64_t total_chunks, total_rows;
+  int max_col_tiles, max_row_blocks;
+};
+hipError_t launch_nl_project_batched(const NlBatch& b, int prec, hipStream_t s);
+
 // Size of the fixed device scratch of chfsi_apply_noalloc() (kernels_nl.hip),
 // and its device address on the current device (call with that device
 // current; each device has its own copy).

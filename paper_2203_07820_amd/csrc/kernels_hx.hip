@@ -30,6 +30,7 @@
 #include <cstring>
 #include <type_traits>
 
+#include "device_util.h"
 #include "internal.h"
 
 namespace chfsi {
@@ -700,19 +701,15 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
 }
 
 // The same work list with exactly one workgroup per item (grid = number of
-// items): no item loop, the problem found by a binary search over item_off,
+// items): no item loop, the problem found by one ballot over item_off (a
+// binary search chained five dependent loads at the start of every item),
 // which keeps the scalar registers of the loop free for the cell item.
 template <int P, typename T, bool CPLX, int WAVES, int OCC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
   const int it = xcd_remap(blockIdx.x, gridDim.x);
-  int lo = 0, hi = nprob - 1;  // last problem whose first item is <= it
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (item_off[mid] <= it) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = __builtin_amdgcn_readfirstlane(problem_of(item_off, nprob, it));
   const HxArgs<T> d = descs[lo];
   const int local = it - static_cast<int>(item_off[lo]);
   const int E = d.nc * d.nc * d.nc;

@@ -4,6 +4,7 @@
 // helpers of the filter (zero fill, precision conversion of a block).
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "internal.h"
 
 namespace chfsi {
@@ -21,15 +22,14 @@ constexpr int kNlChunk = 512;
 // node ids and projector values are wave-uniform (scalar loads), the 8 row
 // loads of X are issued before any is used, so their latencies overlap.
 template <typename T, bool CPLX>
-__global__ void __launch_bounds__(256)
-nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const int64_t* atom_ptr,
-                  const int32_t* atom_node, const double* atom_val, const T* X, int64_t ldx,
-                  int ncols, T* partial, int64_t ldhp) {
+__device__ __forceinline__ void nl_partial_item(const int chunk, const int ctile, const int32_t* chunk_atom,
+                                                const int64_t* chunk_begin, const int64_t* atom_ptr,
+                                                const int32_t* atom_node, const double* atom_val, const T* X,
+                                                int64_t ldx, int ncols, T* partial, int64_t ldhp) {
   __shared__ T red[4][CPLX ? 8 : 4][64];
-  const int chunk = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
-  const int col = blockIdx.y * 64 + lane;  // logical column
+  const int col = ctile * 64 + lane;  // logical column
   const int colc = col < ncols ? col : ncols - 1;
   const int at = chunk_atom[chunk];
   const int64_t e0 = chunk_begin[chunk];
@@ -94,13 +94,21 @@ nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const i
   }
 }
 
-template <typename T>
+template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256)
-nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* partial, T* hP,
-                 int64_t ldhp, int nreal) {
-  const int am = blockIdx.x;  // atom * 4 + component
-  const int at = am / 4, m = am % 4;
-  const int j = blockIdx.y * 256 + threadIdx.x;
+nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const int64_t* atom_ptr,
+                  const int32_t* atom_node, const double* atom_val, const T* X, int64_t ldx,
+                  int ncols, T* partial, int64_t ldhp) {
+  nl_partial_item<T, CPLX>(blockIdx.x, blockIdx.y, chunk_atom, chunk_begin, atom_ptr, atom_node, atom_val, X, ldx,
+                           ncols, partial, ldhp);
+}
+
+template <typename T>
+__device__ __forceinline__ void nl_reduce_item(const int am, const int jblk, const int32_t* atom_chunk_ptr,
+                                               const double* hcoef, const T* partial, T* hP, int64_t ldhp,
+                                               int nreal) {
+  const int at = am / 4, m = am % 4;   // am = atom * 4 + component
+  const int j = jblk * 256 + threadIdx.x;
   if (j >= ldhp) return;
   T s = T(0);
   if (j < nreal) {
@@ -109,6 +117,37 @@ nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* pa
     s *= static_cast<T>(hcoef[am]);
   }
   hP[static_cast<int64_t>(am) * ldhp + j] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* partial, T* hP,
+                 int64_t ldhp, int nreal) {
+  nl_reduce_item<T>(blockIdx.x, blockIdx.y, atom_chunk_ptr, hcoef, partial, hP, ldhp, nreal);
+}
+
+// The projection of many operators' blocks in two launches: work units are
+// the concatenated chunks (partial sums) and (atom, component) rows (the
+// reduction) of every problem; per-problem tables and pointers come from the
+// device descriptors d[q].
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256)
+nl_partial_batched_kernel(const NlLaunch* __restrict__ d, const int64_t* __restrict__ chunk_off, const int nprob) {
+  const int q = problem_of(chunk_off, nprob, blockIdx.x);
+  const NlLaunch& L = d[q];
+  if (static_cast<int>(blockIdx.y) * 64 >= L.ncols) return;
+  nl_partial_item<T, CPLX>(static_cast<int>(blockIdx.x - chunk_off[q]), blockIdx.y, L.chunk_atom, L.chunk_begin,
+                           L.atom_ptr, L.atom_node, L.atom_val, static_cast<const T*>(L.X), L.ldx, L.ncols,
+                           static_cast<T*>(L.partial), L.ldhp);
+}
+
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256)
+nl_reduce_batched_kernel(const NlLaunch* __restrict__ d, const int64_t* __restrict__ am_off, const int nprob) {
+  const int q = problem_of(am_off, nprob, blockIdx.x);
+  const NlLaunch& L = d[q];
+  nl_reduce_item<T>(static_cast<int>(blockIdx.x - am_off[q]), blockIdx.y, L.atom_chunk_ptr, L.hcoef,
+                    static_cast<const T*>(L.partial), static_cast<T*>(L.hP), L.ldhp, CPLX ? 2 * L.ncols : L.ncols);
 }
 
 template <typename T, bool CPLX>
@@ -167,6 +206,33 @@ hipError_t launch_nl_project(const NlLaunch& L, int prec, hipStream_t s) {
     case CHFSI_C64: return nl_launch<float, true>(L, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_nl_project_batched(const NlBatch& b, int prec, hipStream_t s) {
+  if (b.nprob <= 0 || b.total_chunks <= 0) return hipSuccess;
+  const dim3 gp(static_cast<unsigned>(b.total_chunks), static_cast<unsigned>(b.max_col_tiles));
+  const dim3 gr(static_cast<unsigned>(b.total_rows), static_cast<unsigned>(b.max_row_blocks));
+  const NlLaunch* d = static_cast<const NlLaunch*>(b.descs);
+  switch (prec) {
+    case CHFSI_F64:
+      hipLaunchKernelGGL((nl_partial_batched_kernel<double, false>), gp, dim3(256), 0, s, d, b.chunk_off, b.nprob);
+      hipLaunchKernelGGL((nl_reduce_batched_kernel<double, false>), gr, dim3(256), 0, s, d, b.row_off, b.nprob);
+      break;
+    case CHFSI_F32:
+      hipLaunchKernelGGL((nl_partial_batched_kernel<float, false>), gp, dim3(256), 0, s, d, b.chunk_off, b.nprob);
+      hipLaunchKernelGGL((nl_reduce_batched_kernel<float, false>), gr, dim3(256), 0, s, d, b.row_off, b.nprob);
+      break;
+    case CHFSI_C128:
+      hipLaunchKernelGGL((nl_partial_batched_kernel<double, true>), gp, dim3(256), 0, s, d, b.chunk_off, b.nprob);
+      hipLaunchKernelGGL((nl_reduce_batched_kernel<double, true>), gr, dim3(256), 0, s, d, b.row_off, b.nprob);
+      break;
+    case CHFSI_C64:
+      hipLaunchKernelGGL((nl_partial_batched_kernel<float, true>), gp, dim3(256), 0, s, d, b.chunk_off, b.nprob);
+      hipLaunchKernelGGL((nl_reduce_batched_kernel<float, true>), gr, dim3(256), 0, s, d, b.row_off, b.nprob);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s) {
