@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["op_build.cpp", "api.cpp", "mlp.cpp", "kernels_hx.hip", "kernels_nl.hip", "kernels_density.hip",
            "kernels_dense.hip", "kernels_mlp.hip", "kernels_dhm.hip",
-           "kernels_scf.hip"]
+           "kernels_scf.hip", "kernels_small.hip"]
 
 ARCH = "gfx950"
 COMMON = [

@@ -310,12 +310,22 @@ int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo
   void* dinfo;
   CHECK(ws_get(ctx, WS_INFO, 64, &dinfo));
   const rocblas_int n = static_cast<rocblas_int>(N);
-  if (cplx)
+  int info = 0;
+  // small blocks: factor and inverse in one workgroup (the factor itself is
+  // not kept, so a caller asking for L takes the library route)
+  const bool small = N <= kSmallMaxN && L_host == nullptr;
+  if (small) {
+    SmallBatch sb;
+    sb.mat0 = S;
+    sb.n0 = static_cast<int>(N);
+    sb.info = static_cast<int*>(dinfo);
+    HIP_TRY(ctx, launch_small_cholinv(sb, 1, cplx, ctx->stream));
+  } else if (cplx) {
     RB_TRY(ctx, rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, reinterpret_cast<rocblas_double_complex*>(S), n,
                                  static_cast<rocblas_int*>(dinfo)));
-  else
+  } else {
     RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, n, S, n, static_cast<rocblas_int*>(dinfo)));
-  int info = 0;
+  }
   CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
   if (info != 0)
     return fail(ctx, CHFSI_ECHOL, "overlap matrix is not positive definite (leading minor " + std::to_string(info) +
@@ -329,14 +339,16 @@ int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo
         for (int q = 0; q < cf; ++q)
           L_host[(i * N + j) * cf + q] = (i >= j) ? Lcm[(i + j * N) * cf + q] : 0.0;
   }
-  if (cplx)
-    RB_TRY(ctx, rocsolver_ztrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n,
-                                 reinterpret_cast<rocblas_double_complex*>(S), n, static_cast<rocblas_int*>(dinfo)));
-  else
-    RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n, S, n,
-                                 static_cast<rocblas_int*>(dinfo)));
-  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
-  if (info != 0) return fail(ctx, CHFSI_ECHOL, "Cholesky factor is singular");
+  if (!small) {
+    if (cplx)
+      RB_TRY(ctx, rocsolver_ztrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n,
+                                   reinterpret_cast<rocblas_double_complex*>(S), n, static_cast<rocblas_int*>(dinfo)));
+    else
+      RB_TRY(ctx, rocsolver_dtrtri(ctx->blas, rocblas_fill_lower, rocblas_diagonal_non_unit, n, S, n,
+                                   static_cast<rocblas_int*>(dinfo)));
+    CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+    if (info != 0) return fail(ctx, CHFSI_ECHOL, "Cholesky factor is singular");
+  }
   // Z = L^-H (upper triangular), as a real-view matrix
   const double* Z = nullptr;
   int64_t ldz = 0;
@@ -377,16 +389,28 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
   double* D = static_cast<double*>(eig);
   double* Ework = D + N;
   const rocblas_int n = static_cast<rocblas_int>(N);
-  if (cplx)
-    RB_TRY(ctx, rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n,
-                                 reinterpret_cast<rocblas_double_complex*>(Hh), n, D, Ework,
-                                 static_cast<rocblas_int*>(dinfo)));
-  else
-    RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n, Hh, n, D, Ework,
-                                 static_cast<rocblas_int*>(dinfo)));
+  // small blocks: Jacobi in one workgroup; its convergence flag is read with
+  // the results at the end instead of through a synchronisation here
+  const bool small = N <= kSmallMaxN;
   int info = 0;
-  CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
-  if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
+  if (small) {
+    SmallBatch sb;
+    sb.mat0 = Hh;
+    sb.n0 = static_cast<int>(N);
+    sb.ev0 = D;
+    sb.info = static_cast<int*>(dinfo);
+    HIP_TRY(ctx, launch_small_eigh(sb, 1, cplx, ctx->stream));
+  } else {
+    if (cplx)
+      RB_TRY(ctx, rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n,
+                                   reinterpret_cast<rocblas_double_complex*>(Hh), n, D, Ework,
+                                   static_cast<rocblas_int*>(dinfo)));
+    else
+      RB_TRY(ctx, rocsolver_dsyevd(ctx->blas, rocblas_evect_original, rocblas_fill_lower, n, Hh, n, D, Ework,
+                                   static_cast<rocblas_int*>(dinfo)));
+    CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
+    if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
+  }
   const double* Z = nullptr;
   int64_t ldz = 0;
   void* Zb;
@@ -414,7 +438,9 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
     std::vector<double> hp(static_cast<size_t>(nch) * N);
     HIP_TRY(ctx, hipMemcpyAsync(hp.data(), rp, hp.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (small) HIP_TRY(ctx, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
     for (int64_t j = 0; j < N; ++j) {
       double s = 0.0;
       for (int c = 0; c < nch; ++c) s += hp[static_cast<size_t>(c) * N + j];
@@ -422,7 +448,9 @@ int rayleigh_ritz(chfsi_op* op, const double* X, int64_t ldx, double* Psi, int64
     }
   } else {
     HIP_TRY(ctx, hipMemcpyAsync(theta, D, N * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (small) HIP_TRY(ctx, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (info != 0) return fail(ctx, CHFSI_EHIP, "projected eigensolve did not converge");
   }
   return 0;
 }

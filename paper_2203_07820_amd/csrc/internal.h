@@ -238,6 +238,28 @@ hipError_t launch_add_scaled_cols(const float* C, int64_t ldc, const double* d, 
 hipError_t launch_sym_from_lower(const double* G, int64_t ldg, double* S, int n, hipStream_t s);
 // complex Hermitian S (n x n column-major interleaved) from the real-view Gram
 hipError_t launch_gram_combine_complex(const double* G2, int64_t ldg2, double* S, int n, hipStream_t s);
+// ---- small dense kernels (kernels_small.hip), one workgroup per matrix ----
+// Every matrix is column-major n x n (n <= kSmallMaxN), complex interleaved.
+// Matrix q of a launch of `count` workgroups is mats[q] (n = dims[q],
+// eigenvalues to evals[q]) when the device arrays are given, else the single
+// matrix mat0 (n0, ev0).  info[q] (device) = 0 on success.
+// cholinv: lower triangle of S -> L^-1 with S = L L^H (info k + 1 at a
+// non-positive k-th pivot, S then unchanged).  eigh: lower triangle of H ->
+// eigenvectors (column j for the j-th), eigenvalues ascending (info 1: no
+// convergence).
+constexpr int kSmallMaxN = 64;
+struct SmallBatch {
+  double* const* mats = nullptr;
+  const int* dims = nullptr;
+  double* const* evals = nullptr;
+  double* mat0 = nullptr;
+  int n0 = 0;
+  double* ev0 = nullptr;
+  int* info = nullptr;
+};
+hipError_t launch_small_cholinv(const SmallBatch& b, int count, bool cplx, hipStream_t s);
+hipError_t launch_small_eigh(const SmallBatch& b, int count, bool cplx, hipStream_t s);
+
 // real 2n1 x 2n2 expansion of a complex matrix: mode 0 row-major Z, mode 1
 // column-major L^-1 -> Z = L^-H (upper), mode 2 column-major Q -> Z = Q
 hipError_t launch_expand_complex(const double* Z, int n1, int n2, int mode, double* Z2, hipStream_t s);

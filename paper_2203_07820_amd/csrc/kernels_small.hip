@@ -1,0 +1,295 @@
+// Dense kernels for small subspaces (N <= 64 columns) of the CholGS and
+// Rayleigh-Ritz steps (Section 4.4, Algorithm 2): the Cholesky factor of the
+// overlap S = L L^H with its inverse L^-1, and the Hermitian eigensolve of the
+// projected Hamiltonian.  Each matrix is handled by one workgroup with the
+// whole matrix in LDS, and a launch covers any number of matrices (one
+// workgroup each), so a batch of small problems needs one launch per step.
+// For small N the solver library's routines are bound by their own launches
+// and host synchronisations, not by arithmetic; these kernels report failure
+// through a device flag that the host reads with the pass's results.
+//
+// Layout: every matrix is column-major, n x n, element (i, j) at i + j n
+// (complex: interleaved re, im), as the library routines they stand in for.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace chfsi {
+namespace {
+
+constexpr int kSmallThreads = 256;
+
+struct cd {
+  double re, im;
+};
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cd cmulc(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }  // a conj(b)
+
+// Element access for real (CPLX = false: im ignored, kept 0) and complex data.
+template <bool CPLX> __device__ __forceinline__ cd ld_el(const double* m, int64_t e) {
+  if constexpr (CPLX) return {m[2 * e], m[2 * e + 1]};
+  else return {m[e], 0.0};
+}
+template <bool CPLX> __device__ __forceinline__ void st_el(double* m, int64_t e, cd v) {
+  if constexpr (CPLX) {
+    m[2 * e] = v.re;
+    m[2 * e + 1] = v.im;
+  } else {
+    m[e] = v.re;
+  }
+}
+
+// ---- Cholesky factor and its inverse ---------------------------------------
+// S (lower triangle read) -> lower triangle of S overwritten with L^-1, where
+// S = L L^H.  info = 0, or k + 1 if the k-th pivot is not positive to
+// working precision, i.e. not above 16 eps S_kk: column k is then a linear
+// combination of the earlier ones up to rounding (a block whose condition
+// number exceeds about 1/sqrt(16 eps), where Cholesky orthonormalisation
+// loses all orthogonality anyway); the factorisation stops there and S is
+// left as it was.
+// Right-looking factorisation in LDS (L row-major with a padded row), then
+// forward substitution with one column of L^-1 per thread (no barriers).
+template <bool CPLX>
+__global__ void __launch_bounds__(kSmallThreads)
+small_cholinv_kernel(const SmallBatch b) {
+  constexpr int CF = CPLX ? 2 : 1;
+  __shared__ double sm[kSmallMaxN * (kSmallMaxN + 1) * CF + 2 * kSmallMaxN];
+  double* S = b.mats ? b.mats[blockIdx.x] : b.mat0;
+  const int n = b.dims ? b.dims[blockIdx.x] : b.n0;
+  int* info = b.info;
+  const int ld = n + 1;
+  double* L = sm;                        // L[i][j] at (i ld + j) CF, j <= i
+  double* dg = sm + static_cast<int64_t>(n) * ld * CF;   // diagonal of L
+  double* s0 = dg + n;                                    // diagonal of S
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kSmallThreads) {
+    const int i = e % n, j = e / n;
+    if (i >= j) st_el<CPLX>(L, static_cast<int64_t>(i) * ld + j, ld_el<CPLX>(S, e));
+    if (i == j) s0[i] = S[e * CF];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double d = L[(static_cast<int64_t>(k) * ld + k) * CF];   // real part (Hermitian diagonal)
+    // uniform: every thread read the same d and s0[k]
+    if (!(d > 16.0 * __DBL_EPSILON__ * s0[k]) || !(d > 0.0) || !(d < INFINITY)) {
+      if (tid == 0) info[blockIdx.x] = k + 1;
+      return;
+    }
+    const double lkk = sqrt(d), inv = 1.0 / lkk;
+    if (tid == 0) dg[k] = lkk;
+    for (int i = k + 1 + tid; i < n; i += kSmallThreads) {
+      const int64_t e = static_cast<int64_t>(i) * ld + k;
+      cd v = ld_el<CPLX>(L, e);
+      st_el<CPLX>(L, e, {v.re * inv, v.im * inv});
+    }
+    __syncthreads();
+    // trailing update of the lower triangle: L[i][j] -= L[i][k] conj(L[j][k])
+    const int nt = n - 1 - k;
+    for (int e = tid; e < nt * nt; e += kSmallThreads) {
+      const int i = k + 1 + e / nt, j = k + 1 + e % nt;
+      if (j > i) continue;
+      const cd lik = ld_el<CPLX>(L, static_cast<int64_t>(i) * ld + k);
+      const cd ljk = ld_el<CPLX>(L, static_cast<int64_t>(j) * ld + k);
+      const int64_t o = static_cast<int64_t>(i) * ld + j;
+      const cd a = ld_el<CPLX>(L, o), pr = cmulc(lik, ljk);
+      st_el<CPLX>(L, o, {a.re - pr.re, a.im - pr.im});
+    }
+    __syncthreads();
+  }
+  // X = L^-1 (lower): column j by thread j, X[i][j] = (delta_ij - sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i],
+  // written straight into S's lower triangle (column j of X only depends on
+  // itself, and column j of S's lower triangle is no longer read)
+  for (int j = tid; j < n; j += kSmallThreads) {
+    for (int i = j; i < n; ++i) {
+      cd s = {i == j ? 1.0 : 0.0, 0.0};
+      for (int k = j; k < i; ++k) {
+        const cd p = cmul(ld_el<CPLX>(L, static_cast<int64_t>(i) * ld + k), ld_el<CPLX>(S, k + static_cast<int64_t>(j) * n));
+        s.re -= p.re;
+        s.im -= p.im;
+      }
+      const double r = 1.0 / dg[i];
+      st_el<CPLX>(S, i + static_cast<int64_t>(j) * n, {s.re * r, s.im * r});
+    }
+  }
+  if (tid == 0) info[blockIdx.x] = 0;
+}
+
+// ---- Hermitian eigensolve --------------------------------------------------
+// H (lower triangle read) -> H overwritten with the eigenvectors (column j for
+// the j-th eigenvalue), D = eigenvalues in ascending order; info = 0, or 1 if
+// the iteration did not converge.  Cyclic Jacobi with the round-robin order:
+// each of the m - 1 rounds of a sweep (m = n rounded up to even) rotates m / 2
+// disjoint index pairs at once.  For a pair (p, q) with a_pq = r w (r = |a_pq|,
+// |w| = 1), U = diag(1, conj(w)) R, R = [[c, s], [-s, c]] the real rotation
+// that diagonalises [[a_pp, r], [r, a_qq]]; the rows are updated by U^H, then
+// the columns of A and V by U.  A sweep starts only while the off-diagonal
+// mass exceeds 1e-30 of the total.
+template <bool CPLX>
+__global__ void __launch_bounds__(kSmallThreads)
+small_eigh_kernel(const SmallBatch b) {
+  constexpr int CF = CPLX ? 2 : 1;
+  constexpr int kMaxSweeps = 50;
+  __shared__ double sm[2 * kSmallMaxN * (kSmallMaxN + 1) * CF + 4 * (kSmallMaxN / 2)];
+  __shared__ int pq[kSmallMaxN];   // per pair: p (-1: no rotation), q
+  double* H = b.mats ? b.mats[blockIdx.x] : b.mat0;
+  const int n = b.dims ? b.dims[blockIdx.x] : b.n0;
+  double* D = b.evals ? b.evals[blockIdx.x] : b.ev0;
+  int* info = b.info;
+  const int ld = n + 1;
+  const int m = n + (n & 1);
+  const int np = m / 2;
+  double* A = sm;                                        // A[i][j] at (i ld + j) CF
+  double* V = sm + static_cast<int64_t>(n) * ld * CF;    // V[i][j] likewise
+  double* rot = V + static_cast<int64_t>(n) * ld * CF;   // per pair: c, s, w.re, w.im
+  __shared__ double red[2 * kSmallThreads];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += kSmallThreads) {
+    const int i = e % n, j = e / n;
+    const int64_t o = static_cast<int64_t>(i) * ld + j;
+    if (i >= j) {
+      cd v = ld_el<CPLX>(H, e);
+      if (i == j) v.im = 0.0;
+      st_el<CPLX>(A, o, v);
+      st_el<CPLX>(A, static_cast<int64_t>(j) * ld + i, {v.re, -v.im});
+    }
+    st_el<CPLX>(V, o, {i == j ? 1.0 : 0.0, 0.0});
+  }
+  __syncthreads();
+  bool converged = n <= 1;
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    // off-diagonal and total mass
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += kSmallThreads) {
+      const int i = e / n, j = e % n;
+      const cd v = ld_el<CPLX>(A, static_cast<int64_t>(i) * ld + j);
+      const double a2 = v.re * v.re + v.im * v.im;
+      tot += a2;
+      if (i != j) off += a2;
+    }
+    red[tid] = off;
+    red[kSmallThreads + tid] = tot;
+    __syncthreads();
+    for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[tid] += red[tid + w];
+        red[kSmallThreads + tid] += red[kSmallThreads + tid + w];
+      }
+      __syncthreads();
+    }
+    converged = red[0] <= 1e-30 * red[kSmallThreads];
+    __syncthreads();   // red is rewritten by the next sweep
+    if (converged) break;
+    for (int r = 0; r < m - 1; ++r) {
+      // 1. rotation of every pair of this round
+      if (tid < np) {
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = m - 1;
+        } else {
+          p = (r + tid) % (m - 1);
+          q = (r - tid + m - 1) % (m - 1);
+        }
+        double c = 1.0, s = 0.0, wr = 1.0, wi = 0.0;
+        bool act = p < n && q < n;
+        if (act) {
+          const cd apq = ld_el<CPLX>(A, static_cast<int64_t>(p) * ld + q);
+          double rr = CPLX ? sqrt(apq.re * apq.re + apq.im * apq.im) : apq.re;
+          if (fabs(rr) <= 1e-300) {
+            act = false;
+          } else {
+            if constexpr (CPLX) {
+              wr = apq.re / rr;
+              wi = apq.im / rr;
+            }
+            const double app = A[(static_cast<int64_t>(p) * ld + p) * CF];
+            const double aqq = A[(static_cast<int64_t>(q) * ld + q) * CF];
+            const double th = (aqq - app) / (2.0 * rr);
+            const double t = fabs(th) < 1e150 ? (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0))
+                                              : 0.5 / th;
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        rot[4 * tid] = c;
+        rot[4 * tid + 1] = s;
+        rot[4 * tid + 2] = wr;
+        rot[4 * tid + 3] = wi;
+        pq[2 * tid] = act ? p : -1;
+        pq[2 * tid + 1] = q;
+      }
+      __syncthreads();
+      // 2. rows p, q <- U^H: p' = c A_p - s w A_q, q' = s A_p + c w A_q
+      for (int e = tid; e < np * n; e += kSmallThreads) {
+        const int k = e / n, j = e % n;
+        const int p = pq[2 * k];
+        if (p < 0) continue;
+        const int q = pq[2 * k + 1];
+        const double c = rot[4 * k], s = rot[4 * k + 1];
+        const cd w = {rot[4 * k + 2], rot[4 * k + 3]};
+        const int64_t op = static_cast<int64_t>(p) * ld + j, oq = static_cast<int64_t>(q) * ld + j;
+        const cd ap = ld_el<CPLX>(A, op), aq = ld_el<CPLX>(A, oq);
+        const cd waq = CPLX ? cmul(w, aq) : aq;
+        st_el<CPLX>(A, op, {c * ap.re - s * waq.re, c * ap.im - s * waq.im});
+        st_el<CPLX>(A, oq, {s * ap.re + c * waq.re, s * ap.im + c * waq.im});
+      }
+      __syncthreads();
+      // 3. columns p, q of A and V <- U: p' = c A_p - s conj(w) A_q,
+      //    q' = s A_p + c conj(w) A_q; the pair's off-diagonal entries are
+      //    set to exactly zero
+      for (int e = tid; e < np * n; e += kSmallThreads) {
+        const int k = e / n, i = e % n;
+        const int p = pq[2 * k];
+        if (p < 0) continue;
+        const int q = pq[2 * k + 1];
+        const double c = rot[4 * k], s = rot[4 * k + 1];
+        const cd wc = {rot[4 * k + 2], -rot[4 * k + 3]};
+#pragma unroll
+        for (int which = 0; which < 2; ++which) {
+          double* Mx = which ? V : A;
+          const int64_t op = static_cast<int64_t>(i) * ld + p, oq = static_cast<int64_t>(i) * ld + q;
+          const cd ap = ld_el<CPLX>(Mx, op), aq = ld_el<CPLX>(Mx, oq);
+          const cd waq = CPLX ? cmul(wc, aq) : aq;
+          cd np_ = {c * ap.re - s * waq.re, c * ap.im - s * waq.im};
+          cd nq_ = {s * ap.re + c * waq.re, s * ap.im + c * waq.im};
+          if (!which && i == p) nq_ = {0.0, 0.0};
+          if (!which && i == q) np_ = {0.0, 0.0};
+          st_el<CPLX>(Mx, op, np_);
+          st_el<CPLX>(Mx, oq, nq_);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // eigenvalues in ascending order (ties by index), vectors to the same columns
+  for (int i = tid; i < n; i += kSmallThreads) {
+    const double di = A[(static_cast<int64_t>(i) * ld + i) * CF];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = A[(static_cast<int64_t>(j) * ld + j) * CF];
+      rank += (dj < di || (dj == di && j < i)) ? 1 : 0;
+    }
+    D[rank] = di;
+    for (int row = 0; row < n; ++row)
+      st_el<CPLX>(H, row + static_cast<int64_t>(rank) * n, ld_el<CPLX>(V, static_cast<int64_t>(row) * ld + i));
+  }
+  if (tid == 0) info[blockIdx.x] = converged ? 0 : 1;
+}
+
+}  // namespace
+
+hipError_t launch_small_cholinv(const SmallBatch& b, int count, bool cplx, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (cplx) hipLaunchKernelGGL(small_cholinv_kernel<true>, dim3(count), dim3(kSmallThreads), 0, s, b);
+  else hipLaunchKernelGGL(small_cholinv_kernel<false>, dim3(count), dim3(kSmallThreads), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_eigh(const SmallBatch& b, int count, bool cplx, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (cplx) hipLaunchKernelGGL(small_eigh_kernel<true>, dim3(count), dim3(kSmallThreads), 0, s, b);
+  else hipLaunchKernelGGL(small_eigh_kernel<false>, dim3(count), dim3(kSmallThreads), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace chfsi

@@ -115,7 +115,9 @@ def test_apply_with_leading_dimension(ctx, case):
     assert np.all(Yg[:, 20:] == 0)
 
 
-@pytest.mark.parametrize("case", [SMALL[1], SMALL[4], SMALL[5]])
+# every order: real FP32 takes four column tiles per wave for p <= 6 and two
+# at p = 7; complex FP32 two
+@pytest.mark.parametrize("case", SMALL)
 def test_apply_fp32_matches_oracle(ctx, case):
     s = _sys(*case)
     op = lib.Operator(ctx, s)
@@ -215,6 +217,58 @@ def test_orthonormalize_rank_deficient_fails(ctx):
         op.orthonormalize(Xd)
     assert ei.value.code == -4
     assert np.array_equal(host(Xd), X)
+
+
+# Blocks of at most 64 columns take the one-workgroup Cholesky-inverse and
+# Jacobi eigensolver kernels; 65 columns the library route beside them.
+@pytest.mark.parametrize("N", [1, 2, 17, 64, 65])
+@pytest.mark.parametrize("case", [SMALL[2], SMALL[5]])
+def test_small_block_orthonormalize_and_rayleigh_ritz(ctx, case, N):
+    s = _sys(*case)
+    op = lib.Operator(ctx, s)
+    X = workloads.start_block(op.M, N, seed=31 + N, complex_=op.is_complex)
+    Xo, _, _ = ochfsi.cholgs(X)
+    Xd = dev(X)
+    op.orthonormalize(Xd)             # no factor requested: the small kernel for N <= 64
+    assert relerr(host(Xd), Xo) < 1e-12
+    H = fe.assemble(fe.build_operator(s))
+    th_ref, Psi_ref, _, r_ref, _ = ochfsi.rayleigh_ritz(lambda v: H @ v, Xo)
+    th, r = op.rayleigh_ritz(Xd)
+    assert np.all(np.diff(th) >= 0)
+    assert np.max(np.abs(th - th_ref)) < 1e-11 * max(1.0, np.max(np.abs(th_ref)))
+    assert np.max(np.abs(r - r_ref)) < 1e-10
+    Psi = host(Xd)
+    # Ritz vectors orthonormal and spanning the oracle's Ritz vectors (per
+    # column up to a unit phase where the Ritz values are distinct)
+    assert np.max(np.abs(Psi.conj().T @ Psi - np.eye(N))) < 1e-12
+    ph = np.sum(Psi.conj() * Psi_ref, axis=0)
+    ph = ph / np.abs(ph)
+    assert relerr(Psi * ph[None, :], Psi_ref) < 1e-9
+
+
+def test_small_block_rayleigh_ritz_degenerate(ctx):
+    # free electrons (V = 0, k = 0): the 6-fold |n|^2 = 1 shell makes the
+    # projected matrix of a block that holds it exactly degenerate; compare
+    # eigenvalues and the projector onto each cluster, not the vectors
+    s = workloads.small_system(2, 4, 0, seed=41)
+    op = lib.Operator(ctx, s)
+    H = fe.assemble(fe.build_operator(s))
+    lam, Q = np.linalg.eigh(H.toarray())
+    N = 20
+    rng = np.random.default_rng(42)
+    X = Q[:, :N] @ np.linalg.qr(rng.standard_normal((N, N)))[0]   # the lowest 20 states, rotated
+    Xd = dev(X)
+    th, r = op.rayleigh_ritz(Xd)
+    assert np.max(np.abs(th - lam[:N])) < 1e-11 * max(1.0, np.max(np.abs(lam[:N])))
+    assert np.max(r) < 1e-10
+    Psi = host(Xd)
+    cuts = np.nonzero(np.diff(lam[:N + 1]) > 1e-8)[0] + 1
+    lo = 0
+    for hi in cuts:
+        P = Psi[:, lo:hi] @ Psi[:, lo:hi].T
+        Pr = Q[:, lo:hi] @ Q[:, lo:hi].T
+        assert np.max(np.abs(P - Pr)) < 1e-10
+        lo = hi
 
 
 @pytest.mark.parametrize("case", [SMALL[2], SMALL[5]])

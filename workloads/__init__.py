@@ -163,11 +163,22 @@ C3_SYSTEMS = [(8, 8, 64), (10, 12, 96), (11, 16, 128), (13, 24, 160),
               (15, 28, 224), (17, 36, 256), (18, 40, 320), (20, 48, 384)]
 
 
+# (ncell, natoms, nwanted) for a batch of small p = 5 boxes (h = 2 bohr), each
+# at the 4 Monkhorst-Pack k-points: problems far too small to fill the GPU
+# one at a time (M = 3,375 .. 27,000).
+SMALL_BATCH_SYSTEMS = [(3, 2, 16), (3, 3, 24), (4, 2, 16), (4, 3, 24), (4, 4, 32), (5, 3, 24),
+                       (5, 4, 32), (5, 5, 40), (6, 4, 32), (6, 5, 40), (6, 6, 48), (3, 2, 24),
+                       (4, 5, 40), (5, 6, 48), (6, 3, 24), (4, 2, 16)]
+
+
 def config(name: str, index: int = 0) -> System:
     """The seeded system of workload ``name`` (``index`` selects c3/c4 members)."""
     if name == "c3":
         nc, na, _ = C3_SYSTEMS[index]
         return make_system(2.0 * nc, nc, 5, na, seed=3000 + index, d_min=1.0, has_proj=True)
+    if name == "small_batch":
+        nc, na, _ = SMALL_BATCH_SYSTEMS[index]
+        return make_system(2.0 * nc, nc, 5, na, seed=6000 + index, d_min=1.0, has_proj=True)
     c = CONFIGS[name]
     seed = c.seed + index
     return make_system(c.L, c.ncell, c.p, c.natoms, seed=seed, d_min=c.d_min,
