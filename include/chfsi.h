@@ -469,17 +469,24 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
 
 /* ---- autotuner of the batched launch ----------------------------------------
  * Times the batched filter on a synthetic batch of four uneven boxes of order
- * p with `block` columns over grid shapes (one workgroup per item, reported as
- * grid_per_cu = 0, or a persistent grid of 1..4 workgroups per CU with
- * contiguous or strided item assignment), keeps the fastest for the key
- * (gfx950, p, prec, block) in the context and, when cache_json is not NULL,
- * merges it into that JSON file (read first, then rewritten).  Synchronous.
- * chfsi_load_tuning() reads such a file into the context; chfsi_get_tuning()
- * returns the shape the batched launch will use (tuned or default). */
+ * p with `block` columns over launch shapes: the work item of the cell kernel
+ * (a cell by 64 columns, on 4 waves, or on 2 waves where real FP32 gives each
+ * wave all 64 columns; or a cell by 32 columns on half the waves) times the
+ * grid (one workgroup per item, reported as grid_per_cu = 0, or a persistent
+ * grid of 1..4 workgroups per CU with contiguous or strided item assignment).
+ * It keeps the fastest for the key (gfx950, p, prec, block) in the context
+ * and, when cache_json is not NULL, merges it into that JSON file (read
+ * first, then rewritten).  Synchronous.  chfsi_load_tuning() reads such a
+ * file into the context (an entry without "col_tile" takes the default
+ * rule); chfsi_get_tuning() returns the shape the batched launch will use:
+ * grid_per_cu, contiguous, col_tile (64 or 32; 0 = the default rule, 32 when
+ * every block has at most 32 real columns, else 64) and the tuned time in ms
+ * (0 when untuned); every output pointer is nullable.  Untuned single-problem
+ * launches use the same default rule for their column tile. */
 int chfsi_autotune(chfsi_ctx* ctx, const char* cache_json, int32_t p, int32_t prec, int32_t block);
 int chfsi_load_tuning(chfsi_ctx* ctx, const char* cache_json);
 int chfsi_get_tuning(chfsi_ctx* ctx, int32_t p, int32_t prec, int32_t block, int32_t* grid_per_cu,
-                     int32_t* contiguous, double* ms);
+                     int32_t* contiguous, int32_t* col_tile, double* ms);
 
 /* ---- learned warm start -------------------------------------------------------
  * A small network maps per-node features to an initial block (an extension

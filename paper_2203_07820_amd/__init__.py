@@ -183,10 +183,10 @@ class Context:
         self.check(self.lib.chfsi_load_tuning(self.h, cache_json.encode()))
 
     def get_tuning(self, p: int, prec: int, block: int):
-        g, c, ms = C.c_int32(), C.c_int32(), C.c_double()
+        g, c, ct, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
         self.check(self.lib.chfsi_get_tuning(self.h, int(p), int(prec), int(block), C.byref(g), C.byref(c),
-                                             C.byref(ms)))
-        return {"grid_per_cu": g.value, "contiguous": c.value, "ms": ms.value}
+                                             C.byref(ct), C.byref(ms)))
+        return {"grid_per_cu": g.value, "contiguous": c.value, "col_tile": ct.value, "ms": ms.value}
 
     def close(self):
         if getattr(self, "h", None):

@@ -102,7 +102,7 @@ def load() -> C.CDLL:
                                           C.POINTER(i64), C.POINTER(pd), C.POINTER(pd), C.POINTER(Stats), i32]),
         "chfsi_autotune": (C.c_int, [vp, C.c_char_p, i32, i32, i32]),
         "chfsi_load_tuning": (C.c_int, [vp, C.c_char_p]),
-        "chfsi_get_tuning": (C.c_int, [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), pd]),
+        "chfsi_get_tuning": (C.c_int, [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), pd]),
         "chfsi_features": (C.c_int, [vp, vp]),
         "chfsi_mlp_create": (C.c_int, [vp, i32, i32, i32, u64, C.POINTER(vp)]),
         "chfsi_mlp_destroy": (C.c_int, [vp]),

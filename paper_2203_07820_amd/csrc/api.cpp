@@ -122,6 +122,9 @@ HxLaunch make_hx(const chfsi_op* op, int prec, const void* Xk, int64_t ldx, cons
   L.nc = t.ncell;
   L.ncols = static_cast<int>(ncols * cf);
   L.cplx = t.cplx;
+  // a block of at most 32 real columns takes the 32-column work item (half
+  // the padding of a 64-column one)
+  L.nt = (prec != CHFSI_BF16 && L.ncols <= 32) ? 32 : 64;
   L.A = single ? op->A32 : op->A64;
   L.astride = op->astride;
   L.Ai = single ? op->Ai32 : op->Ai64;
@@ -809,6 +812,12 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
     Bq[q] = (block <= 0 || block > items[q].ncols) ? items[q].ncols : block;
     rounds = std::max<int>(rounds, static_cast<int>((items[q].ncols + Bq[q] - 1) / Bq[q]));
   }
+  // launch shape: tuned (or forced), else one workgroup per item and the
+  // 32-column work item for blocks of at most 32 real columns
+  const chfsi_ctx::Tuning tu = force ? *force : tuning_for(ctx, p, prec, block);
+  int64_t widest = 0;
+  for (int q = 0; q < n; ++q) widest = std::max(widest, Bq[q]);
+  const int nt = (tu.col_tile == 32 || tu.col_tile == 64) ? tu.col_tile : (widest * cf <= 32 ? 32 : 64);
   // workspace: per item R0..R3, projector partials and coefficients
   std::vector<size_t> offR(n), offPart(n), offHP(n);
   std::vector<int64_t> ldhp(n);
@@ -864,7 +873,7 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
       const int q = active[r][k];
       const chfsi_op* op = items[q].op;
       hoff[r * (n + 1) + k] = acc;
-      acc += op->t.E * ((width[r][k] * cf + 63) / 64);
+      acc += op->t.E * ((width[r][k] * cf + nt - 1) / nt);
       double c;
       std::vector<double> al, be;
       cheb_coeffs(m, items[q].a, items[q].b, items[q].aL, &c, al, be);
@@ -897,7 +906,6 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   HIP_TRY(ctx, hipMemcpyAsync(tab, host, tab_bytes, hipMemcpyHostToDevice, ctx->stream));
   const char* dtab = static_cast<const char*>(tab);
   const int64_t* doff = reinterpret_cast<const int64_t*>(dtab + align256(tab_desc));
-  const chfsi_ctx::Tuning tu = force ? *force : tuning_for(ctx, p, prec, block);
 
   // per-round algorithmic flops of the cell kernel (timed launches)
   std::vector<double> round_flops(rounds, 0.0);
@@ -932,6 +940,7 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
         }
         HxBatch hb;
         hb.p = p;
+        hb.nt = nt;
         hb.descs = dtab + (static_cast<size_t>(r) * m + (st - 1)) * n * db;
         hb.item_off = doff + r * (n + 1);
         hb.nprob = na;
@@ -968,7 +977,8 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
   if (!use_graph) return enqueue(ctx->timing);
   // the graph is keyed by everything its nodes point at
   std::ostringstream key;
-  key << m << ":" << prec << ":" << block << ":" << wsb << ":" << tab << ":" << tu.grid_per_cu << ":" << tu.contiguous;
+  key << m << ":" << prec << ":" << block << ":" << wsb << ":" << tab << ":" << tu.grid_per_cu << ":" << tu.contiguous
+      << ":" << nt;
   // operators by id (never reused within the context), so that an operator
   // built at a destroyed one's address cannot match a stale graph
   for (const BItem& it : items) key << ":op" << it.op->id << "," << it.X << "," << it.ncols << "," << it.ld;
@@ -1010,10 +1020,13 @@ int load_tuning_file(chfsi_ctx* ctx, const std::string& path) {
     const size_t g = line.find("\"grid_per_cu\": ");
     const size_t c = line.find("\"contiguous\": ");
     const size_t ms = line.find("\"ms\": ");
+    const size_t ct = line.find("\"col_tile\": ");
     if (k1 == std::string::npos || g == std::string::npos || c == std::string::npos) continue;
     t.grid_per_cu = std::atoi(line.c_str() + g + 15);
     t.contiguous = std::atoi(line.c_str() + c + 14);
     if (ms != std::string::npos) t.ms = std::atof(line.c_str() + ms + 6);
+    if (ct != std::string::npos) t.col_tile = std::atoi(line.c_str() + ct + 12);   // absent: the default rule
+    if (t.col_tile != 0 && t.col_tile != 32 && t.col_tile != 64) continue;
     if (t.grid_per_cu >= 0 && t.grid_per_cu <= 16) ctx->tuning[line.substr(k0 + 8, k1 - k0 - 8)] = t;
   }
   return 0;
@@ -1026,7 +1039,8 @@ int save_tuning_file(chfsi_ctx* ctx, const std::string& path) {
   size_t i = 0;
   for (const auto& kv : ctx->tuning) {
     f << "{\"key\": \"" << kv.first << "\", \"grid_per_cu\": " << kv.second.grid_per_cu
-      << ", \"contiguous\": " << kv.second.contiguous << ", \"ms\": " << kv.second.ms << "}"
+      << ", \"contiguous\": " << kv.second.contiguous << ", \"col_tile\": " << kv.second.col_tile
+      << ", \"ms\": " << kv.second.ms << "}"
       << (++i < ctx->tuning.size() ? "," : "") << "\n";
   }
   f << "]\n";
@@ -2386,12 +2400,14 @@ int chfsi_autotune(chfsi_ctx* ctx, const char* cache_json, int32_t p, int32_t pr
   chfsi_ctx::Tuning best;
   best.ms = 1e300;
   const int m = 4;
+  for (int nt : {64, 32})
   for (int g = 0; g <= 4 && rc == 0; ++g)
     for (int cont = 1; cont >= 0 && rc == 0; --cont) {
       if (g == 0 && cont == 1) continue;  // one item per workgroup: assignment is moot
       chfsi_ctx::Tuning t;
       t.grid_per_cu = g;
       t.contiguous = cont;
+      t.col_tile = nt;
       rc = batched_filter(ctx, items, m, prec, block, false, &t);  // warm-up
       if (rc < 0) break;
       (void)hipEventRecord(e0, ctx->stream);
@@ -2417,11 +2433,12 @@ int chfsi_load_tuning(chfsi_ctx* ctx, const char* cache_json) {
 }
 
 int chfsi_get_tuning(chfsi_ctx* ctx, int32_t p, int32_t prec, int32_t block, int32_t* grid_per_cu,
-                     int32_t* contiguous, double* ms) {
+                     int32_t* contiguous, int32_t* col_tile, double* ms) {
   if (!ctx) return CHFSI_EINVAL;
   const chfsi_ctx::Tuning t = tuning_for(ctx, p, prec, block);
   if (grid_per_cu) *grid_per_cu = t.grid_per_cu;
   if (contiguous) *contiguous = t.contiguous;
+  if (col_tile) *col_tile = t.col_tile;
   if (ms) *ms = t.ms;
   return 0;
 }

@@ -47,7 +47,9 @@ struct chfsi_ctx {
   double t_ms = 0.0, t_flops = 0.0;
   int64_t t_launches = 0;
   // batched launches: tuned persistent-grid shapes per (arch, p, prec, block)
-  struct Tuning { int grid_per_cu = 2; int contiguous = 1; double ms = 0.0; };
+  // col_tile: columns per work item of the cell kernel (64 or 32; 0: 32 for
+  // blocks of at most 32 real columns, else 64)
+  struct Tuning { int grid_per_cu = 2; int contiguous = 1; int col_tile = 0; double ms = 0.0; };
   std::map<std::string, Tuning> tuning;
   int ncu = 0;
   void* pinned = nullptr;           // host staging of descriptor tables

@@ -25,4 +25,20 @@ __device__ __forceinline__ int problem_of(const int64_t* __restrict__ off, const
   return cnt - 1;
 }
 
+// A pointer read from device memory (a descriptor table) is a generic
+// pointer to the compiler, so its loads, stores and atomics become flat
+// instructions, which count in the LDS/scalar counter as well as the vector
+// memory one: every wait for an LDS read then also waits for the flat
+// operations in flight.  (Pointer kernel arguments are known to be global.)
+// Accesses through a gptr are global instructions; only for pointers into
+// global memory (or null, never dereferenced).
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+__device__ __forceinline__ void atomic_add(gptr<double> p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add(gptr<float> p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace chfsi

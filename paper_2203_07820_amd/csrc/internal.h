@@ -89,6 +89,7 @@ struct HxLaunch {
   const void* Abf = nullptr;       // bf16 cell matrix in 16x16x32 operand order
   int64_t astride = 0;             // per-cell real matrices: elements per cell (0: shared)
   int ncu = 0;                     // compute units (persistent launches)
+  int nt = 64;                     // columns per work item: 64, or 32 (not for BF16)
 };
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).
@@ -97,9 +98,10 @@ hipError_t launch_cell_hx(const HxLaunch& a, int prec, hipStream_t s);
 // Many problems of the same order and precision in one persistent launch.
 // descs: device array of nprob packed kernel argument blocks (pack_hx_desc);
 // item_off: device array of nprob + 1 item offsets (items of problem q are
-// its E_q x ceil(ncols_q / 64) (cell, column tile) pairs).
+// its E_q x ceil(ncols_q / nt) (cell, column tile) pairs).
 struct HxBatch {
   int p;
+  int nt = 64;     // columns per work item: 64 or 32
   const void* descs;
   const int64_t* item_off;
   int nprob;

@@ -67,8 +67,6 @@ __device__ __forceinline__ f4 mma_bf16(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD works on a contiguous range of cells (neighbouring cells share nodes,
@@ -150,7 +148,7 @@ __device__ __forceinline__ void row_tables(const HxArgs<T>& a, const int cell, c
       const bool inner = la > 0 && la < P && lb > 0 && lb < P && lc > 0 && lc < P;
       const bool owner = la < P && lb < P && lc < P;
       g = node | (owner ? (1 << 30) : 0) | (inner ? (1 << 29) : 0);
-      if (owner) w = a.alpha * (static_cast<T>(a.vdiag[node]) - a.c);
+      if (owner) w = a.alpha * (static_cast<T>(to_global(a.vdiag)[node]) - a.c);
     }
     tab.xoff[l] = off;
     tab.gid[l] = g;
@@ -173,10 +171,11 @@ __device__ __forceinline__ void cell_nonlocal(const HxArgs<T>& a, typename Mma<T
                                               const int lane) {
   constexpr int RT = MP / 16;
   if (a.pair_ptr != nullptr) {
-    const int p0 = a.pair_ptr[cell], p1 = a.pair_ptr[cell + 1];
+    const gptr<const int32_t> pp = to_global(a.pair_ptr);
+    const int p0 = pp[cell], p1 = pp[cell + 1];
     for (int pr = p0; pr < p1; ++pr) {
-      const int at = a.pair_atom[pr];
-      const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
+      const int at = to_global(a.pair_atom)[pr];
+      const gptr<const T> hrow = to_global(a.hP) + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
       T b[CPW], bs[CPW], cv[RPW], ci[CPLX ? RPW : 1];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
@@ -189,8 +188,8 @@ __device__ __forceinline__ void cell_nonlocal(const HxArgs<T>& a, typename Mma<T
       }
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
-        cv[r] = a.pair_re[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
-        if constexpr (CPLX) ci[r] = a.pair_im[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
+        cv[r] = to_global(a.pair_re)[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
+        if constexpr (CPLX) ci[r] = to_global(a.pair_im)[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
       }
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
@@ -212,12 +211,13 @@ template <int MP, typename T, int RPW, int CPW>
 __device__ __forceinline__ void nl_load(const HxArgs<T>& a, const int pr, const int col0, const int rt0,
                                         const int ct0, const int lane, NlOps<T, RPW, CPW>& o) {
   constexpr int RT = MP / 16;
-  const int at = a.pair_atom[pr];
-  const T* hrow = a.hP + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
+  const int at = to_global(a.pair_atom)[pr];
+  const gptr<const T> hrow = to_global(a.hP) + (static_cast<int64_t>(at) * 4 + lane / 16) * a.ldhp + col0;
 #pragma unroll
   for (int c = 0; c < CPW; ++c) o.b[c] = hrow[(ct0 + c) * 16 + lane % 16];
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) o.cv[r] = a.pair_re[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
+  for (int r = 0; r < RPW; ++r)
+    o.cv[r] = to_global(a.pair_re)[(static_cast<int64_t>(pr) * RT + rt0 + r) * 64 + lane];
 }
 template <int MP, typename T, int RPW, int CPW>
 __device__ __forceinline__ void cell_nonlocal_pf(const HxArgs<T>& a, typename Mma<T>::acc_t (&acc)[RPW][CPW],
@@ -254,10 +254,10 @@ __device__ __forceinline__ void cell_tail(const HxArgs<T>& a, typename Mma<T>::a
   // the stores and atomics of tile r, so that their latency overlaps; the
   // selects discard what non-owners read, and only stores and atomics are
   // masked.  alpha (V - c) of owned rows comes from the LDS table.
-  const T* __restrict__ Xk = a.Xk;
-  T* __restrict__ Xp = const_cast<T*>(a.Xp);
-  T* __restrict__ Tg = a.Tg;
-  const bool has_prev = Xp != nullptr;
+  const gptr<const T> __restrict__ Xk = to_global(a.Xk);
+  const gptr<T> __restrict__ Xp = to_global(const_cast<T*>(a.Xp));
+  const gptr<T> __restrict__ Tg = to_global(a.Tg);
+  const bool has_prev = a.Xp != nullptr;
   int colc[CPW];
   bool colok[CPW];
 #pragma unroll
@@ -330,11 +330,18 @@ __device__ __forceinline__ void cell_tail(const HxArgs<T>& a, typename Mma<T>::a
   }
 }
 
-// One work item: cell `cell`, columns [col0, col0 + 64).
+// One work item: cell `cell`, columns [col0, col0 + NT) (NT = 64 or 32).
 //
-// Work split inside a workgroup: WAVES/2 row groups x 2 column groups.  The
+// Work split inside a workgroup: WAVES/CG row groups x CG column groups.  The
 // number of 16-row tiles is even for every order p in [2, 7], so each wave
-// owns RT / (WAVES/2) row tiles and 2 of the 4 column tiles, with no guards.
+// owns RT / (WAVES/CG) row tiles and NT/16/CG column tiles, with no guards.
+// The 64-column tile takes CG = 2 by default; CG = 1 (each wave all 64
+// columns, so each A fragment serves four column tiles) where the
+// accumulators fit beside the pipeline (real FP32, p <= 6): the 32-cycle FP32
+// MFMA leaves half the time of the FP64 one to hide the same operand loads.
+// The 32-column tile (CG = 1, two column tiles per wave, half the waves per
+// workgroup) halves the padding of blocks of at most 32 columns and doubles
+// the number of work items.
 // B fragments are read straight from global memory into registers (no LDS
 // staging of X, no barriers in the loop): in a 4-wide k step, lanes
 // 16 q .. 16 q + 15 read 16 consecutive columns of cell row 4 kg + q, one
@@ -345,7 +352,7 @@ __device__ __forceinline__ void cell_tail(const HxArgs<T>& a, typename Mma<T>::a
 // steps ahead, so that the in-order vector-memory counter never makes an MFMA
 // wait on HBM.  Column lanes beyond ncols read a valid column and are never
 // stored; padding rows (l >= mcell) are zeroed.
-template <int P, typename T, bool CPLX, int WAVES, int ED>
+template <int P, typename T, bool CPLX, int WAVES, int ED, int CG = 2, int NT = kNT>
 __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, const int col0,
                                           RowTables<(((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16), T>& tab) {
   constexpr int Q = P + 1;
@@ -353,16 +360,16 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   constexpr int MP = (MC + 15) / 16 * 16;
   constexpr int RT = MP / 16;           // row tiles
   constexpr int KS = MP / 4;            // 4-wide k steps
-  constexpr int RG = WAVES / 2;         // row groups
+  constexpr int RG = WAVES / CG;        // row groups
   constexpr int RPW = RT / RG;          // row tiles per wave
-  constexpr int CPW = kNT / 32;         // column tiles per wave (2 column groups)
-  static_assert(RT % RG == 0 && KS % 2 == 0, "tiling");
+  constexpr int CPW = NT / 16 / CG;     // column tiles per wave
+  static_assert(RT % RG == 0 && KS % 2 == 0 && WAVES % CG == 0, "tiling");
   using acc_t = typename Mma<T>::acc_t;
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int lane = tid % 64;
-  const int rt0 = (wave / 2) * RPW, ct0 = (wave % 2) * CPW;
+  const int rt0 = (wave / CG) * RPW, ct0 = (wave % CG) * CPW;
 
   // row tables (the barrier in front protects the previous item's readers)
   __syncthreads();
@@ -378,12 +385,12 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
   // per-lane column pointers, clamped to a valid column; complex blocks keep
   // the lane's parity (re/im) so that the partner column cc ^ 1 stays valid
   // (their ncols, counted in reals, is even)
-  const T* xcol[CPW];
+  gptr<const T> xcol[CPW];
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     int cc = col0 + (ct0 + c) * 16 + lane % 16;
     if (cc >= a.ncols) cc = CPLX ? a.ncols - 2 + (lane & 1) : a.ncols - 1;
-    xcol[c] = a.Xk + cc;
+    xcol[c] = to_global(a.Xk) + cc;
   }
 
   // A fragments of this wave: tile (rt0 + r, k step kg) at element
@@ -469,24 +476,28 @@ __device__ __forceinline__ void cell_item(const HxArgs<T>& a, const int cell, co
     }
   }
 
-  cell_tail<MP, T, CPLX, RPW, CPW, ED>(a, acc, cell, col0, rt0, ct0, lane, tab);
+  // 4-byte values with four column tiles per wave: epilogue stages of half a
+  // row tile, so that the stages fit beside the accumulators
+  constexpr int SR = (sizeof(T) == 8 || CPW > 2) ? 2 : 4;
+  cell_tail<MP, T, CPLX, RPW, CPW, ED, SR>(a, acc, cell, col0, rt0, ct0, lane, tab);
 }
 
-template <int P> constexpr int waves_for() {
-  return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 > 24 ? 8 : 4;
+// Column groups per workgroup of the 64-column tile (see cell_item).
+template <int P, typename T, bool CPLX> constexpr int col_groups() {
+  return (!CPLX && sizeof(T) == 4 && P <= 6) ? 1 : 2;
 }
 template <int P> constexpr int rows_padded() { return ((P + 1) * (P + 1) * (P + 1) + 15) / 16 * 16; }
 // epilogue stages in flight + 1
 template <typename T> constexpr int epilogue_depth() { return sizeof(T) == 8 ? 3 : 2; }
 
 // Single problem: one workgroup per (cell, column tile), cells fastest.
-template <int P, typename T, bool CPLX, int WAVES, int OCC>
+template <int P, typename T, bool CPLX, int WAVES, int OCC, int CG, int NT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
   const int E = a.nc * a.nc * a.nc;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>()>(a, bid % E, (bid / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>(), CG, NT>(a, bid % E, (bid / E) * NT, tab);
 }
 
 // bf16 cell products with FP32 iterates (the BF16 filter precision).  The
@@ -641,8 +652,8 @@ cell_hx_bf16_kernel(const HxArgs<float> a) {
   // 4. nonlocal term, then the epilogue: X_k from the LDS copy (memory for
   //    p = 7), X_{k-1} from the registers loaded above
   cell_nonlocal_pf<MP, float, RPW, CPW>(a, acc, p0, p1, col0, rt0, 0, lane, nl0);
-  float* __restrict__ Xp = const_cast<float*>(a.Xp);
-  float* __restrict__ Tg = a.Tg;
+  const gptr<float> __restrict__ Xp = to_global(const_cast<float*>(a.Xp));
+  const gptr<float> __restrict__ Tg = to_global(a.Tg);
 #pragma unroll
   for (int r = 0; r < RPW; ++r)
 #pragma unroll
@@ -678,7 +689,7 @@ cell_hx_bf16_kernel(const HxArgs<float> a) {
 // neighbouring cells of one problem.  Per-problem arguments, including the
 // recurrence scalars, are read from the device table `descs`, so a captured
 // graph stays valid when the host rewrites the table between replays.
-template <int P, typename T, bool CPLX, int WAVES, int OCC>
+template <int P, typename T, bool CPLX, int WAVES, int OCC, int CG, int NT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob,
                        const int contiguous) {
@@ -696,7 +707,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
     const HxArgs<T> d = descs[q];
     const int64_t local = it - item_off[q];
     const int E = d.nc * d.nc * d.nc;
-    cell_item<P, T, CPLX, WAVES, 2>(d, static_cast<int>(local % E), static_cast<int>(local / E) * kNT, tab);
+    cell_item<P, T, CPLX, WAVES, 2, CG, NT>(d, static_cast<int>(local % E), static_cast<int>(local / E) * NT, tab);
   }
 }
 
@@ -704,7 +715,7 @@ cell_hx_batched_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __res
 // items): no item loop, the problem found by one ballot over item_off (a
 // binary search chained five dependent loads at the start of every item),
 // which keeps the scalar registers of the loop free for the cell item.
-template <int P, typename T, bool CPLX, int WAVES, int OCC>
+template <int P, typename T, bool CPLX, int WAVES, int OCC, int CG, int NT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __restrict__ item_off, const int nprob) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
@@ -713,16 +724,23 @@ cell_hx_batched1_kernel(const HxArgs<T>* __restrict__ descs, const int64_t* __re
   const HxArgs<T> d = descs[lo];
   const int local = it - static_cast<int>(item_off[lo]);
   const int E = d.nc * d.nc * d.nc;
-  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>()>(d, local % E, (local / E) * kNT, tab);
+  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>(), CG, NT>(d, local % E, (local / E) * NT, tab);
 }
 
-// Waves per SIMD: two for real and complex FP64 and complex FP32 (one
-// workgroup's epilogue overlaps the other's MFMAs), three for real FP32
-// (140 VGPRs at p = 6); complex FP64 at p = 6 (11 row tiles per wave, A and
-// B fragments doubled) needs the 512 registers of one wave per SIMD.
-template <int P, typename T, bool CPLX> constexpr int occupancy() {
-  return (CPLX && sizeof(T) == 8) ? (P == 6 ? 1 : 2) : ((!CPLX && sizeof(T) == 4) ? 3 : 2);
-}
+// Launch shape of a column tile of NT columns: column groups, waves per
+// workgroup and waves per SIMD.  Waves per SIMD: two for real and complex
+// FP64, complex FP32 and real FP32 with four column tiles per wave (one
+// workgroup's epilogue overlaps the other's MFMAs), three for real FP32 with
+// two column tiles per wave; complex FP64 at p = 6 (11 row tiles per wave, A
+// and B fragments doubled) needs the 512 registers of one wave per SIMD.
+template <int P, typename T, bool CPLX, int NT> struct Shape {
+  static constexpr int CG = NT == 32 ? 1 : col_groups<P, T, CPLX>();
+  static constexpr int RG = ((P + 1) * (P + 1) * (P + 1) + 15) / 16 > 24 ? 4 : 2;
+  static constexpr int WAVES = RG * CG;
+  static constexpr int CPW = NT / 16 / CG;
+  static constexpr int OCC = (CPLX && sizeof(T) == 8) ? (P == 6 ? 1 : 2)
+                                                      : ((!CPLX && sizeof(T) == 4 && CPW == 2) ? 3 : 2);
+};
 
 template <typename T>
 HxArgs<T> pack_args(const HxLaunch& L) {
@@ -757,7 +775,8 @@ template <int P, typename T, bool CPLX, bool BF>
 hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   const HxArgs<T> a = pack_args<T>(L);
   const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
-  const int64_t nct = (L.ncols + kNT - 1) / kNT;
+  const int nt = (BF || L.nt != 32) ? kNT : 32;   // the bf16 kernel has 64-column tiles only
+  const int64_t nct = (L.ncols + nt - 1) / nt;
   const int64_t nblk = E * nct;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
@@ -765,11 +784,14 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
     static_assert(std::is_same<T, float>::value && !CPLX, "bf16 products: real FP32 iterates");
     hipLaunchKernelGGL((cell_hx_bf16_kernel<P>), dim3(static_cast<unsigned>(nblk)), dim3(64 * bf16_waves<P>()), 0,
                        s, a);
+  } else if (nt == 32) {
+    using S = Shape<P, T, CPLX, 32>;
+    hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, S::WAVES, S::OCC, S::CG, 32>), dim3(static_cast<unsigned>(nblk)),
+                       dim3(64 * S::WAVES), 0, s, a);
   } else {
-    constexpr int WAVES = waves_for<P>();
-    constexpr int OCC = occupancy<P, T, CPLX>();
-    hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, WAVES, OCC>), dim3(static_cast<unsigned>(nblk)),
-                       dim3(64 * WAVES), 0, s, a);
+    using S = Shape<P, T, CPLX, kNT>;
+    hipLaunchKernelGGL((cell_hx_kernel<P, T, CPLX, S::WAVES, S::OCC, S::CG, kNT>),
+                       dim3(static_cast<unsigned>(nblk)), dim3(64 * S::WAVES), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -789,18 +811,25 @@ hipError_t launch_t(const HxLaunch& L, hipStream_t s) {
 
 }  // namespace
 
+template <int P, typename T, bool CPLX, int NT>
+hipError_t launch_batched_shape(const HxBatch& b, hipStream_t s) {
+  using S = Shape<P, T, CPLX, NT>;
+  if (b.one_per_item)
+    hipLaunchKernelGGL((cell_hx_batched1_kernel<P, T, CPLX, S::WAVES, S::OCC, S::CG, NT>), dim3(b.grid),
+                       dim3(64 * S::WAVES), 0, s, static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob);
+  else
+    hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, S::WAVES, S::OCC, S::CG, NT>), dim3(b.grid),
+                       dim3(64 * S::WAVES), 0, s, static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob,
+                       b.contiguous);
+  return hipGetLastError();
+}
+
 template <int P, typename T, bool CPLX>
 hipError_t launch_batched_p(const HxBatch& b, hipStream_t s) {
-  constexpr int WAVES = waves_for<P>();
-  constexpr int OCC = occupancy<P, T, CPLX>();
   if (b.grid <= 0 || b.nprob <= 0) return hipErrorInvalidValue;
-  if (b.one_per_item)
-    hipLaunchKernelGGL((cell_hx_batched1_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
-                       static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob);
-  else
-    hipLaunchKernelGGL((cell_hx_batched_kernel<P, T, CPLX, WAVES, OCC>), dim3(b.grid), dim3(64 * WAVES), 0, s,
-                       static_cast<const HxArgs<T>*>(b.descs), b.item_off, b.nprob, b.contiguous);
-  return hipGetLastError();
+  if (b.nt == 32) return launch_batched_shape<P, T, CPLX, 32>(b, s);
+  if (b.nt == kNT) return launch_batched_shape<P, T, CPLX, kNT>(b, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, bool CPLX>

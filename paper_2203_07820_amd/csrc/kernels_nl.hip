@@ -22,10 +22,11 @@ constexpr int kNlChunk = 512;
 // node ids and projector values are wave-uniform (scalar loads), the 8 row
 // loads of X are issued before any is used, so their latencies overlap.
 template <typename T, bool CPLX>
-__device__ __forceinline__ void nl_partial_item(const int chunk, const int ctile, const int32_t* chunk_atom,
-                                                const int64_t* chunk_begin, const int64_t* atom_ptr,
-                                                const int32_t* atom_node, const double* atom_val, const T* X,
-                                                int64_t ldx, int ncols, T* partial, int64_t ldhp) {
+__device__ __forceinline__ void nl_partial_item(const int chunk, const int ctile, gptr<const int32_t> chunk_atom,
+                                                gptr<const int64_t> chunk_begin, gptr<const int64_t> atom_ptr,
+                                                gptr<const int32_t> atom_node, gptr<const double> atom_val,
+                                                gptr<const T> X, int64_t ldx, int ncols, gptr<T> partial,
+                                                int64_t ldhp) {
   __shared__ T red[4][CPLX ? 8 : 4][64];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int lane = threadIdx.x % 64;
@@ -41,7 +42,7 @@ __device__ __forceinline__ void nl_partial_item(const int chunk, const int ctile
 #pragma unroll
   for (int m = 0; m < NV; ++m) acc[m] = T(0);
   auto add = [&](int64_t e, T xr, T xi) {
-    const double* v = atom_val + e * NV;
+    const gptr<const double> v = atom_val + e * NV;
     if constexpr (CPLX) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -99,14 +100,15 @@ __global__ void __launch_bounds__(256)
 nl_partial_kernel(const int32_t* chunk_atom, const int64_t* chunk_begin, const int64_t* atom_ptr,
                   const int32_t* atom_node, const double* atom_val, const T* X, int64_t ldx,
                   int ncols, T* partial, int64_t ldhp) {
-  nl_partial_item<T, CPLX>(blockIdx.x, blockIdx.y, chunk_atom, chunk_begin, atom_ptr, atom_node, atom_val, X, ldx,
-                           ncols, partial, ldhp);
+  nl_partial_item<T, CPLX>(blockIdx.x, blockIdx.y, to_global(chunk_atom), to_global(chunk_begin),
+                           to_global(atom_ptr), to_global(atom_node), to_global(atom_val), to_global(X), ldx, ncols,
+                           to_global(partial), ldhp);
 }
 
 template <typename T>
-__device__ __forceinline__ void nl_reduce_item(const int am, const int jblk, const int32_t* atom_chunk_ptr,
-                                               const double* hcoef, const T* partial, T* hP, int64_t ldhp,
-                                               int nreal) {
+__device__ __forceinline__ void nl_reduce_item(const int am, const int jblk, gptr<const int32_t> atom_chunk_ptr,
+                                               gptr<const double> hcoef, gptr<const T> partial, gptr<T> hP,
+                                               int64_t ldhp, int nreal) {
   const int at = am / 4, m = am % 4;   // am = atom * 4 + component
   const int j = jblk * 256 + threadIdx.x;
   if (j >= ldhp) return;
@@ -123,7 +125,8 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 nl_reduce_kernel(const int32_t* atom_chunk_ptr, const double* hcoef, const T* partial, T* hP,
                  int64_t ldhp, int nreal) {
-  nl_reduce_item<T>(blockIdx.x, blockIdx.y, atom_chunk_ptr, hcoef, partial, hP, ldhp, nreal);
+  nl_reduce_item<T>(blockIdx.x, blockIdx.y, to_global(atom_chunk_ptr), to_global(hcoef), to_global(partial),
+                    to_global(hP), ldhp, nreal);
 }
 
 // The projection of many operators' blocks in two launches: work units are
@@ -136,9 +139,10 @@ nl_partial_batched_kernel(const NlLaunch* __restrict__ d, const int64_t* __restr
   const int q = problem_of(chunk_off, nprob, blockIdx.x);
   const NlLaunch& L = d[q];
   if (static_cast<int>(blockIdx.y) * 64 >= L.ncols) return;
-  nl_partial_item<T, CPLX>(static_cast<int>(blockIdx.x - chunk_off[q]), blockIdx.y, L.chunk_atom, L.chunk_begin,
-                           L.atom_ptr, L.atom_node, L.atom_val, static_cast<const T*>(L.X), L.ldx, L.ncols,
-                           static_cast<T*>(L.partial), L.ldhp);
+  nl_partial_item<T, CPLX>(static_cast<int>(blockIdx.x - chunk_off[q]), blockIdx.y, to_global(L.chunk_atom),
+                           to_global(L.chunk_begin), to_global(L.atom_ptr), to_global(L.atom_node),
+                           to_global(L.atom_val), to_global(static_cast<const T*>(L.X)), L.ldx, L.ncols,
+                           to_global(static_cast<T*>(L.partial)), L.ldhp);
 }
 
 template <typename T, bool CPLX>
@@ -146,8 +150,9 @@ __global__ void __launch_bounds__(256)
 nl_reduce_batched_kernel(const NlLaunch* __restrict__ d, const int64_t* __restrict__ am_off, const int nprob) {
   const int q = problem_of(am_off, nprob, blockIdx.x);
   const NlLaunch& L = d[q];
-  nl_reduce_item<T>(static_cast<int>(blockIdx.x - am_off[q]), blockIdx.y, L.atom_chunk_ptr, L.hcoef,
-                    static_cast<const T*>(L.partial), static_cast<T*>(L.hP), L.ldhp, CPLX ? 2 * L.ncols : L.ncols);
+  nl_reduce_item<T>(static_cast<int>(blockIdx.x - am_off[q]), blockIdx.y, to_global(L.atom_chunk_ptr),
+                    to_global(L.hcoef), to_global(static_cast<const T*>(L.partial)),
+                    to_global(static_cast<T*>(L.hP)), L.ldhp, CPLX ? 2 * L.ncols : L.ncols);
 }
 
 template <typename T, bool CPLX>

@@ -12,6 +12,7 @@
 // (complex: interleaved re, im), as the library routines they stand in for.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "internal.h"
 
 namespace chfsi {
@@ -25,12 +26,13 @@ struct cd {
 __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ __forceinline__ cd cmulc(cd a, cd b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }  // a conj(b)
 
-// Element access for real (CPLX = false: im ignored, kept 0) and complex data.
-template <bool CPLX> __device__ __forceinline__ cd ld_el(const double* m, int64_t e) {
+// Element access for real (CPLX = false: im ignored, kept 0) and complex data,
+// in LDS or (through a gptr) in global memory.
+template <bool CPLX, typename Ptr> __device__ __forceinline__ cd ld_el(Ptr m, int64_t e) {
   if constexpr (CPLX) return {m[2 * e], m[2 * e + 1]};
   else return {m[e], 0.0};
 }
-template <bool CPLX> __device__ __forceinline__ void st_el(double* m, int64_t e, cd v) {
+template <bool CPLX, typename Ptr> __device__ __forceinline__ void st_el(Ptr m, int64_t e, cd v) {
   if constexpr (CPLX) {
     m[2 * e] = v.re;
     m[2 * e + 1] = v.im;
@@ -54,9 +56,9 @@ __global__ void __launch_bounds__(kSmallThreads)
 small_cholinv_kernel(const SmallBatch b) {
   constexpr int CF = CPLX ? 2 : 1;
   __shared__ double sm[kSmallMaxN * (kSmallMaxN + 1) * CF + 2 * kSmallMaxN];
-  double* S = b.mats ? b.mats[blockIdx.x] : b.mat0;
+  const gptr<double> S = to_global(b.mats ? b.mats[blockIdx.x] : b.mat0);
   const int n = b.dims ? b.dims[blockIdx.x] : b.n0;
-  int* info = b.info;
+  const gptr<int> info = to_global(b.info);
   const int ld = n + 1;
   double* L = sm;                        // L[i][j] at (i ld + j) CF, j <= i
   double* dg = sm + static_cast<int64_t>(n) * ld * CF;   // diagonal of L
@@ -121,8 +123,10 @@ small_cholinv_kernel(const SmallBatch b) {
 // each of the m - 1 rounds of a sweep (m = n rounded up to even) rotates m / 2
 // disjoint index pairs at once.  For a pair (p, q) with a_pq = r w (r = |a_pq|,
 // |w| = 1), U = diag(1, conj(w)) R, R = [[c, s], [-s, c]] the real rotation
-// that diagonalises [[a_pp, r], [r, a_qq]]; the rows are updated by U^H, then
-// the columns of A and V by U.  A sweep starts only while the off-diagonal
+// that diagonalises [[a_pp, r], [r, a_qq]]; A <- U^H A U is applied by 2 x 2
+// blocks (all rotations of a round act on disjoint index pairs, so each block
+// sees exactly its row pair's and column pair's rotations), V <- V U beside
+// it: two barriers per round.  A sweep starts only while the off-diagonal
 // mass exceeds 1e-30 of the total.
 template <bool CPLX>
 __global__ void __launch_bounds__(kSmallThreads)
@@ -130,11 +134,12 @@ small_eigh_kernel(const SmallBatch b) {
   constexpr int CF = CPLX ? 2 : 1;
   constexpr int kMaxSweeps = 50;
   __shared__ double sm[2 * kSmallMaxN * (kSmallMaxN + 1) * CF + 4 * (kSmallMaxN / 2)];
-  __shared__ int pq[kSmallMaxN];   // per pair: p (-1: no rotation), q
-  double* H = b.mats ? b.mats[blockIdx.x] : b.mat0;
+  __shared__ int pq[kSmallMaxN];          // per pair: p, q (an index >= n: the dummy of odd n)
+  __shared__ int actf[kSmallMaxN / 2];    // per pair: 1 if rotated this round
+  const gptr<double> H = to_global(b.mats ? b.mats[blockIdx.x] : b.mat0);
   const int n = b.dims ? b.dims[blockIdx.x] : b.n0;
-  double* D = b.evals ? b.evals[blockIdx.x] : b.ev0;
-  int* info = b.info;
+  const gptr<double> D = to_global(b.evals ? b.evals[blockIdx.x] : b.ev0);
+  const gptr<int> info = to_global(b.info);
   const int ld = n + 1;
   const int m = n + (n & 1);
   const int np = m / 2;
@@ -215,48 +220,66 @@ small_eigh_kernel(const SmallBatch b) {
         rot[4 * tid + 1] = s;
         rot[4 * tid + 2] = wr;
         rot[4 * tid + 3] = wi;
-        pq[2 * tid] = act ? p : -1;
+        pq[2 * tid] = p;
         pq[2 * tid + 1] = q;
+        actf[tid] = act ? 1 : 0;
       }
       __syncthreads();
-      // 2. rows p, q <- U^H: p' = c A_p - s w A_q, q' = s A_p + c w A_q
-      for (int e = tid; e < np * n; e += kSmallThreads) {
-        const int k = e / n, j = e % n;
-        const int p = pq[2 * k];
-        if (p < 0) continue;
-        const int q = pq[2 * k + 1];
-        const double c = rot[4 * k], s = rot[4 * k + 1];
-        const cd w = {rot[4 * k + 2], rot[4 * k + 3]};
-        const int64_t op = static_cast<int64_t>(p) * ld + j, oq = static_cast<int64_t>(q) * ld + j;
-        const cd ap = ld_el<CPLX>(A, op), aq = ld_el<CPLX>(A, oq);
-        const cd waq = CPLX ? cmul(w, aq) : aq;
-        st_el<CPLX>(A, op, {c * ap.re - s * waq.re, c * ap.im - s * waq.im});
-        st_el<CPLX>(A, oq, {s * ap.re + c * waq.re, s * ap.im + c * waq.im});
-      }
-      __syncthreads();
-      // 3. columns p, q of A and V <- U: p' = c A_p - s conj(w) A_q,
-      //    q' = s A_p + c conj(w) A_q; the pair's off-diagonal entries are
-      //    set to exactly zero
-      for (int e = tid; e < np * n; e += kSmallThreads) {
-        const int k = e / n, i = e % n;
-        const int p = pq[2 * k];
-        if (p < 0) continue;
-        const int q = pq[2 * k + 1];
-        const double c = rot[4 * k], s = rot[4 * k + 1];
-        const cd wc = {rot[4 * k + 2], -rot[4 * k + 3]};
-#pragma unroll
-        for (int which = 0; which < 2; ++which) {
-          double* Mx = which ? V : A;
-          const int64_t op = static_cast<int64_t>(i) * ld + p, oq = static_cast<int64_t>(i) * ld + q;
-          const cd ap = ld_el<CPLX>(Mx, op), aq = ld_el<CPLX>(Mx, oq);
-          const cd waq = CPLX ? cmul(wc, aq) : aq;
-          cd np_ = {c * ap.re - s * waq.re, c * ap.im - s * waq.im};
-          cd nq_ = {s * ap.re + c * waq.re, s * ap.im + c * waq.im};
-          if (!which && i == p) nq_ = {0.0, 0.0};
-          if (!which && i == q) np_ = {0.0, 0.0};
-          st_el<CPLX>(Mx, op, np_);
-          st_el<CPLX>(Mx, oq, nq_);
+      // 2. A <- U^H A U by 2 x 2 blocks (rows of pair k, columns of pair l):
+      //    rows p' = c A_p - s w A_q, q' = s A_p + c w A_q, then columns
+      //    p' = c A_p - s conj(w) A_q, q' = s A_p + c conj(w) A_q; disjoint
+      //    blocks, so one phase; a rotated pair's own off-diagonal entries
+      //    are set to exactly zero.  V <- V U in the same phase.
+      for (int b = tid; b < np * np; b += kSmallThreads) {
+        const int k = b / np, l = b % np;
+        if (!actf[k] && !actf[l]) continue;
+        const int i0 = pq[2 * k], i1 = pq[2 * k + 1], j0 = pq[2 * l], j1 = pq[2 * l + 1];
+        const bool r0 = i0 < n, r1 = i1 < n, c0 = j0 < n, c1 = j1 < n;
+        const int64_t o00 = static_cast<int64_t>(i0) * ld + j0, o01 = static_cast<int64_t>(i0) * ld + j1;
+        const int64_t o10 = static_cast<int64_t>(i1) * ld + j0, o11 = static_cast<int64_t>(i1) * ld + j1;
+        const cd zero = {0.0, 0.0};
+        cd b00 = (r0 && c0) ? ld_el<CPLX>(A, o00) : zero, b01 = (r0 && c1) ? ld_el<CPLX>(A, o01) : zero;
+        cd b10 = (r1 && c0) ? ld_el<CPLX>(A, o10) : zero, b11 = (r1 && c1) ? ld_el<CPLX>(A, o11) : zero;
+        if (actf[k]) {
+          const double c = rot[4 * k], s = rot[4 * k + 1];
+          const cd w = {rot[4 * k + 2], rot[4 * k + 3]};
+          const cd w10 = CPLX ? cmul(w, b10) : b10, w11 = CPLX ? cmul(w, b11) : b11;
+          const cd n00 = {c * b00.re - s * w10.re, c * b00.im - s * w10.im};
+          const cd n01 = {c * b01.re - s * w11.re, c * b01.im - s * w11.im};
+          const cd n10 = {s * b00.re + c * w10.re, s * b00.im + c * w10.im};
+          const cd n11 = {s * b01.re + c * w11.re, s * b01.im + c * w11.im};
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
         }
+        if (actf[l]) {
+          const double c = rot[4 * l], s = rot[4 * l + 1];
+          const cd wc = {rot[4 * l + 2], -rot[4 * l + 3]};
+          const cd w01 = CPLX ? cmul(wc, b01) : b01, w11 = CPLX ? cmul(wc, b11) : b11;
+          const cd n00 = {c * b00.re - s * w01.re, c * b00.im - s * w01.im};
+          const cd n10 = {c * b10.re - s * w11.re, c * b10.im - s * w11.im};
+          const cd n01 = {s * b00.re + c * w01.re, s * b00.im + c * w01.im};
+          const cd n11 = {s * b10.re + c * w11.re, s * b10.im + c * w11.im};
+          b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+        }
+        if (k == l) {   // the rotated pair: its off-diagonal entries vanish
+          b01 = zero;
+          b10 = zero;
+        }
+        if (r0 && c0) st_el<CPLX>(A, o00, b00);
+        if (r0 && c1) st_el<CPLX>(A, o01, b01);
+        if (r1 && c0) st_el<CPLX>(A, o10, b10);
+        if (r1 && c1) st_el<CPLX>(A, o11, b11);
+      }
+      for (int e = tid; e < n * np; e += kSmallThreads) {
+        const int i = e / np, l = e % np;
+        if (!actf[l]) continue;
+        const int j0 = pq[2 * l], j1 = pq[2 * l + 1];   // both < n for a rotated pair
+        const double c = rot[4 * l], s = rot[4 * l + 1];
+        const cd wc = {rot[4 * l + 2], -rot[4 * l + 3]};
+        const int64_t o0 = static_cast<int64_t>(i) * ld + j0, o1 = static_cast<int64_t>(i) * ld + j1;
+        const cd v0 = ld_el<CPLX>(V, o0), v1 = ld_el<CPLX>(V, o1);
+        const cd wv1 = CPLX ? cmul(wc, v1) : v1;
+        st_el<CPLX>(V, o0, {c * v0.re - s * wv1.re, c * v0.im - s * wv1.im});
+        st_el<CPLX>(V, o1, {s * v0.re + c * wv1.re, s * v0.im + c * wv1.im});
       }
       __syncthreads();
     }

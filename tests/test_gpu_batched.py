@@ -96,6 +96,43 @@ def test_batched_filter_matches_individual_and_oracle(ctx, use_graph, prec):
             assert relerr(host(Xd2[q]), host(Xd3[q])) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("col_tile", [64, 32])
+def test_batched_real_filter_forced_col_tile(tmp_path, prec, col_tile):
+    # real operators with the work item forced to 64 or 32 columns through the
+    # tuning cache: blocks of 9 .. 37 columns (one ragged item of 64, or one or
+    # two of 32), F64 and F32 (F32 with 64 columns takes the four-tile waves)
+    systems = _batch((0.0, 0.0, 0.0))
+    P = lib.F64 if prec == "f64" else lib.F32
+    block = 40
+    path = tmp_path / "tune.json"
+    path.write_text('[\n{"key": "gfx950:p3:prec%d:B%d", "grid_per_cu": 0, "contiguous": 0, "col_tile": %d, '
+                    '"ms": 1.0}\n]\n' % (P, block, col_tile))
+    c = lib.Context(0)
+    c.load_tuning(str(path))
+    assert c.get_tuning(3, P, block)["col_tile"] == col_tile
+    ops = [lib.Operator(c, s) for s in systems]
+    ncols = [20, 37, 9, 33]
+    Xs, refs, params = [], [], []
+    for q, (s, op) in enumerate(zip(systems, ops)):
+        H = fe.assemble(fe.build_operator(s))
+        lam = np.linalg.eigvalsh(H.toarray())
+        a, b, aL = lam[ncols[q]], lam[-1] * 1.05, lam[0]
+        X = workloads.start_block(op.M, ncols[q], seed=70 + q)
+        refs.append(ochfsi.cheb_filter(lambda v: H @ v, X, 8, a, b, aL))
+        Xs.append(X)   # FP64 block; the F32 filter converts it and back
+        params.append((a, b, aL))
+    Xd = [dev(X) for X in Xs]
+    c.filter_batched(ops, Xd, 8, [p[0] for p in params], [p[1] for p in params], [p[2] for p in params], P,
+                     block=block, use_graph=False)
+    tol = 1e-11 if prec == "f64" else 1e-4
+    for q in range(len(ops)):
+        assert relerr(host(Xd[q]), refs[q]) < tol, q
+    for op in ops:
+        op.close()
+    c.close()
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_solve_batched_equals_individual_solves(ctx, use_graph):
     systems = _batch()
@@ -136,13 +173,14 @@ def test_autotune_writes_cache_and_is_used(ctx, tmp_path):
     path = str(tmp_path / "tune.json")
     t = ctx.autotune(3, lib.C128, 16, cache_json=path)
     assert 0 <= t["grid_per_cu"] <= 4 and t["contiguous"] in (0, 1) and t["ms"] > 0
+    assert t["col_tile"] in (32, 64)
     data = json.loads(open(path).read())
     assert any(e["key"] == "gfx950:p3:prec3:B16" for e in data)
     c2 = lib.Context(0)
     assert c2.get_tuning(3, lib.C128, 16)["ms"] == 0.0
     c2.load_tuning(path)
     t2 = c2.get_tuning(3, lib.C128, 16)
-    assert (t2["grid_per_cu"], t2["contiguous"]) == (t["grid_per_cu"], t["contiguous"])
+    assert (t2["grid_per_cu"], t2["contiguous"], t2["col_tile"]) == (t["grid_per_cu"], t["contiguous"], t["col_tile"])
     assert abs(t2["ms"] - t["ms"]) <= 1e-4 * t["ms"]
     c2.close()
 
@@ -182,22 +220,26 @@ def c3_like_refs():
 
 # every launch shape of the batched cell kernel: one workgroup per item
 # (grid_per_cu = 0), and persistent grids of 1, 2 and 4 workgroups per CU
-# with contiguous or strided item assignment
+# with contiguous or strided item assignment, each with the 64- and the
+# 32-column work item (block 16 complex = 32 real columns: one 64-column item
+# half padding, or one 32-column item; block 40 = 80 real columns: two items
+# of 64 or three of 32, the last ragged)
 TUNINGS = [(0, 1), (1, 1), (1, 0), (2, 1), (2, 0), (4, 1), (4, 0)]
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("col_tile,block", [(64, 16), (32, 16), (64, 40), (32, 40)])
 @pytest.mark.parametrize("tuning", TUNINGS)
-def test_batched_p5_kpoints_every_launch_shape(c3_like_refs, tmp_path, tuning, prec):
+def test_batched_p5_kpoints_every_launch_shape(c3_like_refs, tmp_path, tuning, col_tile, block, prec):
     systems, refs, params, X0 = c3_like_refs
     P = lib.C128 if prec == "c128" else lib.C64
-    block = 16
     path = tmp_path / "tune.json"
-    path.write_text('[\n{"key": "gfx950:p5:prec%d:B%d", "grid_per_cu": %d, "contiguous": %d, "ms": 1.0}\n]\n'
-                    % (P, block, tuning[0], tuning[1]))
+    path.write_text('[\n{"key": "gfx950:p5:prec%d:B%d", "grid_per_cu": %d, "contiguous": %d, "col_tile": %d, '
+                    '"ms": 1.0}\n]\n' % (P, block, tuning[0], tuning[1], col_tile))
     c = lib.Context(0)
     c.load_tuning(str(path))
-    assert c.get_tuning(5, P, block)["grid_per_cu"] == tuning[0]
+    got_t = c.get_tuning(5, P, block)
+    assert (got_t["grid_per_cu"], got_t["col_tile"]) == (tuning[0], col_tile)
     ops = [lib.Operator(c, s) for s in systems]
     Xd = [dev(X) for X in X0]
     c.filter_batched(ops, Xd, 8, [p[0] for p in params], [p[1] for p in params], [p[2] for p in params], P,
