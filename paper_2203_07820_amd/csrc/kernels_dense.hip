@@ -52,6 +52,7 @@ template <> struct Mfma<float> {
 // zeroed at use), the four 16-column groups in the instruction offset.
 // Loads run two k steps ahead of the MFMAs; no LDS, no barriers.
 constexpr int kGT = 128;  // Gram tile
+constexpr int kGramStages = 3;   // register stages of the Gram pipeline (loads GS - 1 steps ahead)
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, bytes, 0x00020000);
@@ -72,7 +73,7 @@ __device__ __forceinline__ T bload_group(__amdgpu_buffer_rsrc_t r, int voff) {
   else return bload32<G * 64>(r, voff);
 }
 
-template <typename T>
+template <typename T, int GS>
 __global__ void __attribute__((amdgpu_flat_work_group_size(256, 256), amdgpu_waves_per_eu(2, 2)))
 gram_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64_t ldy,
             int64_t M, int n, int64_t rows_per_chunk, int npad, double* __restrict__ part, int64_t offx,
@@ -142,15 +143,15 @@ gram_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64
   // stages would make the compiler wait for the loads in flight into the
   // source.  Loads past the last step read the chunk's last row (the row
   // index is clamped) and the steps past KS contribute zero.
-  T xq[3][4], yq[3][4];
+  T xq[GS][4], yq[GS][4];
   if (KS > 0) {
-    load(xq[0], yq[0], 0);
-    load(xq[1], yq[1], 1);
-  }
-  for (int s = 0; s < KS; s += 3) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      load(xq[(j + 2) % 3], yq[(j + 2) % 3], s + j + 2);
+    for (int j = 0; j < GS - 1; ++j) load(xq[j], yq[j], j);
+  }
+  for (int s = 0; s < KS; s += GS) {
+#pragma unroll
+    for (int j = 0; j < GS; ++j) {
+      load(xq[(j + GS - 1) % GS], yq[(j + GS - 1) % GS], s + j + GS - 1);
       compute(xq[j], yq[j], s + j);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -490,7 +491,7 @@ hipError_t gram_t(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t M, i
   int64_t rpc = (M + nch - 1) / nch;
   rpc = (rpc + 15) / 16 * 16;
   nch = static_cast<int>((M + rpc - 1) / rpc);   // rounding rpc up can leave trailing chunks empty
-  hipLaunchKernelGGL(gram_kernel<T>, dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial,
+  hipLaunchKernelGGL((gram_kernel<T, kGramStages>), dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial,
                      offx, offy);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
                      partial, nch, n, npad, G, ldg);
