@@ -347,12 +347,13 @@ def run_c2(args):
         g.manual_seed(sys_.seed + 1_000_000)
         return torch.randn(op.M, N + nb, dtype=torch.float64, device="cuda", generator=g)
 
-    def run(name, prec0, switch, limit, stop, split=False):
-        """split: each pass is the filter followed by the paper's
-        spectrum-splitting Rayleigh-Ritz in mixed precision (Algorithm 2;
-        X then holds the orthonormal basis Psi_o, the Ritz values come from
-        the generalised eigenproblem, no residuals); one full FP64
-        Rayleigh-Ritz at the end, timed, gives the Ritz vectors."""
+    def run(name, prec0, switch, limit, stop, split=None):
+        """split ("f64" or "mixed"): each pass is the filter followed by the
+        paper's spectrum-splitting Rayleigh-Ritz (Algorithm 2) in FP64 or in
+        its mixed precision (X then holds the orthonormal basis Psi_o, the
+        Ritz values come from the generalised eigenproblem, no residuals);
+        one full FP64 Rayleigh-Ritz at the end, timed, gives the Ritz
+        vectors."""
         X = start()
         Pfr = torch.empty(op.M, nfr, dtype=torch.float64, device="cuda") if split else None
         torch.cuda.synchronize()
@@ -366,7 +367,7 @@ def run_c2(args):
         for k in range(1, limit + 1):
             if split:
                 op.filter(X, m, th[-1], b, th[0], prec=prec, block=B)
-                th = op.rayleigh_ritz_split(X, nfr, Pfr, mixed=True)
+                th = op.rayleigh_ritz_split(X, nfr, Pfr, mixed=(split == "mixed"))
                 r = np.full(N + nb, np.nan)
             else:
                 th, r = op.one_pass(X, N, m, B, th[-1], b, th[0], n_buf=nb, filter_prec=prec)
@@ -436,9 +437,10 @@ def run_c2(args):
     hists = {"f64": ref}
     stop_target = lambda th, r: dE(th) <= target  # noqa: E731
     wanted = set(args.c2_runs.split(",")) if args.c2_runs else set()
-    plan = (("f32", lib.F32, False, cap, stop_target, False), ("mixed", lib.BF16, True, cap, stop_target, False),
-            ("f32_split_rr", lib.F32, False, cap, stop_target, True),
-            ("bf16", lib.BF16, False, 8, lambda th, r: False, False))
+    plan = (("f32", lib.F32, False, cap, stop_target, None), ("mixed", lib.BF16, True, cap, stop_target, None),
+            ("f32_split_rr", lib.F32, False, cap, stop_target, "f64"),
+            ("f32_split_rr_mixed", lib.F32, False, cap, stop_target, "mixed"),
+            ("bf16", lib.BF16, False, 8, lambda th, r: False, None))
     for name, prec0, switch, limit, stop, split in plan:
         if name not in wanted:
             continue

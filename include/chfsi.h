@@ -456,7 +456,11 @@ int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* 
  * chfsi_solve() for n independent problems (systems and/or k-points) that
  * advance pass by pass together: the filters of all unconverged problems run
  * through chfsi_filter_batched() (with use_graph: one graph replay per pass),
- * then each problem's CholGS and Rayleigh-Ritz run in turn.  params, X, ld,
+ * then the CholGS and Rayleigh-Ritz steps: when every block has at most 64
+ * columns, those of all active problems together (each N x N Cholesky,
+ * inverse and eigensolve of all problems in one launch, two host
+ * synchronisations per pass; stats t_rr then holds an even share of that
+ * step), otherwise each problem's in turn.  params, X, ld,
  * theta, resid, stats are arrays of n entries (resid, stats and their entries
  * nullable); m, block and filter_prec must be equal across params and
  * prec_switch must be 0.  History arrays are filled per problem, with times

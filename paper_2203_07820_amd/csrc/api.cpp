@@ -275,15 +275,16 @@ int do_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int m, double a,
 
 // ---- dense helpers ----------------------------------------------------------
 
-// S (N x N, column-major; complex interleaved) = X^H Y over real views.
+// S (N x N, column-major; complex interleaved) = X^H Y over real views, into
+// *S_out, or into the context's workspace when *S_out is null on entry.
 int gram(chfsi_op* op, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t N, double** S_out) {
   chfsi_ctx* ctx = op->ctx;
   const int cf = op->t.cplx ? 2 : 1;
   const int n = static_cast<int>(N * cf);
-  void *part, *G, *S;
+  void *part, *G, *S = *S_out;
   CHECK(ws_get(ctx, WS_GPART, gram_partial_bytes(op->t.M, n, std::max(ldx, ldy) * cf), &part));
   CHECK(ws_get(ctx, WS_G, static_cast<size_t>(n) * n * 8, &G));
-  CHECK(ws_get(ctx, WS_S, static_cast<size_t>(N) * N * 8 * cf, &S));
+  if (!S) CHECK(ws_get(ctx, WS_S, static_cast<size_t>(N) * N * 8 * cf, &S));
   HIP_TRY(ctx, launch_gram(X, ldx * cf, Y, ldy * cf, op->t.M, n, static_cast<double*>(part),
                            static_cast<double*>(G), n, ctx->stream));
   if (op->t.cplx)
@@ -2220,6 +2221,197 @@ int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* 
   return batched_filter(ctx, items, m, prec, block, use_graph != 0);
 }
 
+}  // extern "C"
+
+namespace {
+
+// CholGS and Rayleigh-Ritz of several problems whose blocks have at most
+// kSmallMaxN columns, with the N x N steps of all problems in one launch each
+// (small_cholinv_kernel, small_eigh_kernel: one workgroup per problem) and
+// two host synchronisations in all (the Cholesky flags, then the Ritz values,
+// residual partials and eigensolve flags).  The O(M N) and O(M N^2) steps
+// (Gram products, rotations, H~ X_o, residuals) are launched problem by
+// problem on the context's stream.  Problem q = idx[k]: X[q] (ld[q]) holds
+// the block on entry and the Ritz vectors on exit; th[q], r[q] (N[q]) the
+// Ritz values and residual norms.  Same results as cholgs() + rayleigh_ritz()
+// per problem.
+int subspace_small_batched(chfsi_ctx* ctx, const std::vector<int>& idx, chfsi_op* const* ops, void* const* Xv,
+                           const int64_t* ld, const std::vector<int64_t>& N, std::vector<std::vector<double>>& th,
+                           std::vector<std::vector<double>>& r) {
+  const int na = static_cast<int>(idx.size());
+  if (na == 0) return 0;
+  // per-problem device storage: X_o, W = H~ X_o, H Psi (M x N each), S, H^,
+  // Z (N x N, real view of Z for complex: 2N x 2N), eigenvalues, residual
+  // partials; then the pointer / dimension tables and the flags
+  std::vector<size_t> oX2(na), oW(na), oHP(na), oS(na), oH(na), oZ(na), oD(na), oR(na);
+  size_t tot = 0;
+  auto take = [&](size_t bytes) { const size_t at = tot; tot += align256(bytes); return at; };
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    const chfsi_op* op = ops[q];
+    const size_t cf = op->t.cplx ? 2 : 1;
+    const size_t mn = static_cast<size_t>(op->t.M) * N[q] * cf * 8;
+    const size_t nn = static_cast<size_t>(N[q]) * N[q] * cf * 8;
+    oX2[k] = take(mn);
+    oW[k] = take(mn);
+    oHP[k] = take(mn);
+    oS[k] = take(nn);
+    oH[k] = take(nn);
+    oZ[k] = take(nn * cf);
+    oD[k] = take(static_cast<size_t>(N[q]) * 8);
+    oR[k] = take(resid_partial_count(op->t.M, static_cast<int>(N[q])) * 8);
+  }
+  const size_t oTab = take(static_cast<size_t>(na) * (3 * sizeof(double*) + sizeof(int)));
+  const size_t oInfo = take(static_cast<size_t>(na) * 2 * sizeof(int));
+  void* wsv;
+  CHECK(ws_get(ctx, WS_SUBB, tot, &wsv));
+  char* base = static_cast<char*>(wsv);
+  auto at = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
+  int* dinfo = reinterpret_cast<int*>(base + oInfo);   // [0, na): Cholesky, [na, 2 na): eigensolve
+  // device tables: S pointers, H^ pointers, eigenvalue pointers, dimensions
+  std::vector<char> htab(static_cast<size_t>(na) * (3 * sizeof(double*) + sizeof(int)));
+  double** hS = reinterpret_cast<double**>(htab.data());
+  double** hH = hS + na;
+  double** hD = hH + na;
+  int* hdim = reinterpret_cast<int*>(hD + na);
+  int nmax = 0;
+  for (int k = 0; k < na; ++k) {
+    hS[k] = at(oS[k]);
+    hH[k] = at(oH[k]);
+    hD[k] = at(oD[k]);
+    hdim[k] = static_cast<int>(N[idx[k]]);
+    nmax = std::max(nmax, hdim[k]);
+  }
+  if (nmax > kSmallMaxN) return fail(ctx, CHFSI_EINVAL, "batched small subspace step: block too wide");
+  // the table travels through the pinned staging buffer (stream-ordered after
+  // any earlier use of it, which the host has synchronised before rewriting)
+  void* pin;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  CHECK(pinned_get(ctx, htab.size(), &pin));
+  std::memcpy(pin, htab.data(), htab.size());
+  char* dtab = base + oTab;
+  HIP_TRY(ctx, hipMemcpyAsync(dtab, pin, htab.size(), hipMemcpyHostToDevice, ctx->stream));
+  SmallBatch sb;
+  sb.dims = reinterpret_cast<const int*>(dtab + static_cast<size_t>(na) * 3 * sizeof(double*));
+  // 1. S_q = X_q^H X_q; all Cholesky factors and inverses in one launch
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    double* S = at(oS[k]);
+    CHECK(gram(ops[q], static_cast<const double*>(Xv[q]), ld[q], static_cast<const double*>(Xv[q]), ld[q], N[q],
+               &S));
+  }
+  sb.mats = reinterpret_cast<double* const*>(dtab);
+  sb.info = dinfo;
+  const bool cplx = ops[idx[0]]->t.cplx;
+  HIP_TRY(ctx, launch_small_cholinv(sb, na, cplx, ctx->stream));
+  std::vector<int> hinfo(2 * static_cast<size_t>(na));
+  HIP_TRY(ctx, hipMemcpyAsync(hinfo.data(), dinfo, na * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < na; ++k)
+    if (hinfo[k] != 0)
+      return fail(ctx, CHFSI_ECHOL, "overlap matrix of problem " + std::to_string(idx[k]) +
+                                        " is not positive definite (leading minor " + std::to_string(hinfo[k]) + ")");
+  // 2. X_o = X L^-H, W = H~ X_o, H^ = X_o^H W
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    chfsi_op* op = ops[q];
+    const int cf = op->t.cplx ? 2 : 1;
+    const int64_t Nq = N[q];
+    const int n1 = static_cast<int>(Nq);
+    double* S = at(oS[k]);
+    const double* Z = S;
+    int64_t ldz = Nq;
+    if (op->t.cplx) {
+      HIP_TRY(ctx, launch_expand_complex(S, n1, n1, 1, at(oZ[k]), ctx->stream));
+      Z = at(oZ[k]);
+      ldz = 2 * Nq;
+    } else {
+      HIP_TRY(ctx, launch_zero_strict_lower(S, n1, Nq, ctx->stream));
+    }
+    double* X2 = at(oX2[k]);
+    HIP_TRY(ctx, launch_rotate(static_cast<const double*>(Xv[q]), ld[q] * cf, Z, ldz, X2, Nq * cf, op->t.M,
+                               static_cast<int>(Nq * cf), static_cast<int>(Nq * cf), true, ctx->stream));
+    const int prec = op->t.cplx ? CHFSI_C128 : CHFSI_F64;
+    double* W = at(oW[k]);
+    HIP_TRY(ctx, launch_fill(W, op->t.M, Nq * cf, Nq * cf, prec, ctx->stream));
+    CHECK(hx_step(op, prec, X2, Nq, nullptr, 0, W, Nq, Nq, 1.0, 0.0, 0.0, false));
+    double* Hh = at(oH[k]);
+    CHECK(gram(op, X2, Nq, W, Nq, Nq, &Hh));
+  }
+  // 3. all eigensolves in one launch
+  sb.mats = reinterpret_cast<double* const*>(dtab + static_cast<size_t>(na) * sizeof(double*));
+  sb.evals = reinterpret_cast<double* const*>(dtab + static_cast<size_t>(na) * 2 * sizeof(double*));
+  sb.info = dinfo + na;
+  HIP_TRY(ctx, launch_small_eigh(sb, na, cplx, ctx->stream));
+  // 4. Psi = X_o Q, H Psi = W Q, residual partials; results to the host
+  std::vector<int> nch(na);
+  size_t hbytes = 0;
+  std::vector<size_t> hoR(na), hoD(na);
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    hoR[k] = hbytes;
+    hbytes += resid_partial_count(ops[q]->t.M, static_cast<int>(N[q])) * 8;
+    hoD[k] = hbytes;
+    hbytes += static_cast<size_t>(N[q]) * 8;
+  }
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    chfsi_op* op = ops[q];
+    const int cf = op->t.cplx ? 2 : 1;
+    const int64_t Nq = N[q];
+    const int n1 = static_cast<int>(Nq);
+    double* Hh = at(oH[k]);
+    double* Zb = at(oZ[k]);
+    int64_t ldz;
+    if (op->t.cplx) {
+      HIP_TRY(ctx, launch_expand_complex(Hh, n1, n1, 2, Zb, ctx->stream));
+      ldz = 2 * Nq;
+    } else {
+      HIP_TRY(ctx, launch_transpose(Hh, Zb, n1, ctx->stream));
+      ldz = Nq;
+    }
+    double* X2 = at(oX2[k]);
+    double* W = at(oW[k]);
+    double* HP = at(oHP[k]);
+    HIP_TRY(ctx, launch_rotate(X2, Nq * cf, Zb, ldz, static_cast<double*>(Xv[q]), ld[q] * cf, op->t.M,
+                               static_cast<int>(Nq * cf), static_cast<int>(Nq * cf), false, ctx->stream));
+    HIP_TRY(ctx, launch_rotate(W, Nq * cf, Zb, ldz, HP, Nq * cf, op->t.M, static_cast<int>(Nq * cf),
+                               static_cast<int>(Nq * cf), false, ctx->stream));
+    HIP_TRY(ctx, launch_resid(HP, Nq, static_cast<double*>(Xv[q]), ld[q], at(oD[k]), op->t.M, n1, op->t.cplx,
+                              at(oR[k]), &nch[k], ctx->stream));
+  }
+  void* hres;
+  CHECK(pinned_get(ctx, hbytes, &hres));   // the table copy above has completed (synchronised in step 1)
+  char* hb = static_cast<char*>(hres);
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    HIP_TRY(ctx, hipMemcpyAsync(hb + hoR[k], at(oR[k]), static_cast<size_t>(nch[k]) * N[q] * 8,
+                                hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(hb + hoD[k], at(oD[k]), static_cast<size_t>(N[q]) * 8, hipMemcpyDeviceToHost,
+                                ctx->stream));
+  }
+  HIP_TRY(ctx, hipMemcpyAsync(hinfo.data() + na, dinfo + na, na * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < na; ++k) {
+    const int q = idx[k];
+    if (hinfo[na + k] != 0)
+      return fail(ctx, CHFSI_EHIP, "projected eigensolve of problem " + std::to_string(q) + " did not converge");
+    const double* rp = reinterpret_cast<const double*>(hb + hoR[k]);
+    const double* D = reinterpret_cast<const double*>(hb + hoD[k]);
+    for (int64_t j = 0; j < N[q]; ++j) {
+      double sum = 0.0;
+      for (int c = 0; c < nch[k]; ++c) sum += rp[static_cast<size_t>(c) * N[q] + j];
+      r[q][j] = std::sqrt(sum);
+      th[q][j] = D[j];
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const chfsi_params* params,
                         void* const* Xv, const int64_t* ld, double* const* theta, double* const* resid,
                         chfsi_stats* stats, int32_t use_graph) {
@@ -2262,6 +2454,11 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
     for (int i = 0; i < params[q].nwanted; ++i) mr = std::max(mr, r[q][i]);
     return mr;
   };
+  // every block of at most kSmallMaxN columns: the CholGS and Rayleigh-Ritz
+  // steps of all problems together (one launch per N x N step)
+  bool all_small = true;
+  for (int q = 0; q < n; ++q) all_small = all_small && N[q] <= kSmallMaxN;
+  std::vector<int> all(n);
   for (int q = 0; q < n; ++q) {
     chfsi_op* op = ops[q];
     const chfsi_params& pr = params[q];
@@ -2271,11 +2468,13 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
       CHECK(do_bounds(op, pr.lanczos_steps > 0 ? pr.lanczos_steps : 20, nullptr, pr.lanczos_v0, pr.seed, &b, &lmin));
     }
     bq[q] = b;
+    th[q].assign(N[q], 0.0);
+    r[q].assign(N[q], 0.0);
+    all[q] = q;
+    if (all_small) continue;
     const int cf = op->t.cplx ? 2 : 1;
     void* X2v;
     CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(op->t.M) * N[q] * 8 * cf, &X2v));
-    th[q].assign(N[q], 0.0);
-    r[q].assign(N[q], 0.0);
     CHECK(cholgs(op, static_cast<double*>(Xv[q]), ld[q], static_cast<double*>(X2v), N[q], N[q], nullptr));
     CHECK(rayleigh_ritz(op, static_cast<double*>(X2v), N[q], static_cast<double*>(Xv[q]), ld[q], N[q],
                         th[q].data(), r[q].data()));
@@ -2284,6 +2483,13 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
       HIP_TRY(ctx, hipEventSynchronize(e1));
       record_hist(pr, 0, event_ms(es, e1), maxr_of(q), -1, th[q].data(), N[q]);
     }
+  }
+  if (all_small) {
+    CHECK(subspace_small_batched(ctx, all, ops, Xv, ld, N, th, r));
+    HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    HIP_TRY(ctx, hipEventSynchronize(e1));
+    for (int q = 0; q < n; ++q)
+      if (params[q].hist_len > 0) record_hist(params[q], 0, event_ms(es, e1), maxr_of(q), -1, th[q].data(), N[q]);
   }
   auto converged = [&](int q) {
     const chfsi_params& pr = params[q];
@@ -2311,6 +2517,23 @@ int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const c
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     HIP_TRY(ctx, hipEventSynchronize(e1));
     const double tf = event_ms(e0, e1);
+    if (all_small) {
+      // the subspace step of all active problems together; its time is
+      // shared evenly among them in the statistics
+      HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+      CHECK(subspace_small_batched(ctx, idx, ops, Xv, ld, N, th, r));
+      HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+      HIP_TRY(ctx, hipEventSynchronize(e1));
+      const double ts = event_ms(e0, e1) / static_cast<double>(idx.size());
+      for (int q : idx) {
+        trr[q] += ts;
+        tfilt[q] += tf;
+        ++passes[q];
+        CHECK(check_ritz(ctx, th[q].data(), r[q].data(), N[q], bq[q]));
+        record_hist(params[q], passes[q], event_ms(es, e1), maxr_of(q), prec, th[q].data(), N[q]);
+      }
+      continue;
+    }
     for (int q : idx) {
       chfsi_op* op = ops[q];
       const int cf = op->t.cplx ? 2 : 1;

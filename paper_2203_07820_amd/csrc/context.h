@@ -26,6 +26,7 @@ enum Slot {
   WS_SCF,                          // SCF vectors (potentials, densities, CG, mixing history)
   WS_CG,                           // CG scalars and the residual history of one check interval
   WS_PFR,                          // SCF: the highest Ritz vectors of the split Rayleigh-Ritz
+  WS_SUBB,                         // batched small subspace step: per-problem blocks and matrices
   WS_COUNT
 };
 

@@ -155,6 +155,31 @@ def test_solve_batched_equals_individual_solves(ctx, use_graph):
         assert np.max(np.abs(th[q][:nw[q]] - ref.theta)) < 1e-8
 
 
+@pytest.mark.parametrize("widest", [20, 70])
+def test_solve_batched_real_equals_individual_solves(ctx, widest):
+    # real operators; blocks of at most 64 columns take the subspace step of
+    # all problems together (one Cholesky and one eigensolve launch), a
+    # block of 70 columns makes every problem take its own
+    systems = _batch((0.0, 0.0, 0.0))[:3]
+    ops = [lib.Operator(ctx, s) for s in systems]
+    nw = [12, widest - 4, 10]
+    X0 = [workloads.start_block(op.M, nw[q] + 4, seed=170 + q) for q, op in enumerate(ops)]
+    v0 = [workloads.lanczos_start(op.M, seed=180 + q) for q, op in enumerate(ops)]
+    Xb = [dev(X) for X in X0]
+    th, rs, st = ctx.solve_batched(ops, Xb, nw, m=10, block=16, filter_prec=lib.F64, n_buf=4, fixed_passes=3,
+                                   lanczos_v0=v0, use_graph=False)
+    for q, op in enumerate(ops):
+        Xi = dev(X0[q])
+        thi, ri, sti = op.solve(Xi, nw[q], m=10, block=16, n_buf=4, fixed_passes=3, lanczos_v0=v0[q])
+        assert st[q]["passes"] == 3
+        assert np.max(np.abs(th[q] - thi)) < 1e-10
+        assert np.max(np.abs(rs[q] - ri)) < 1e-9
+        # the lowest Ritz vectors up to sign (well separated Ritz values)
+        Pb, Pi = host(Xb[q])[:, :6], host(Xi)[:, :6]
+        sg = np.sign(np.sum(Pb * Pi, axis=0))
+        assert relerr(Pb * sg[None, :], Pi) < 1e-8
+
+
 def test_solve_batched_tolerance_retires_problems(ctx):
     systems = _batch()[:3]
     ops = [lib.Operator(ctx, s) for s in systems]
