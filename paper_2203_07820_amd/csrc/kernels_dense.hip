@@ -138,11 +138,12 @@ gram_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Y, int64
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mma(xv[a], yv[b], acc[a][b]);
   };
-  // Three register stages with fixed roles (the loop is unrolled by 3): the
-  // rows of step s + 2 are in flight while step s multiplies.  A copy between
-  // stages would make the compiler wait for the loads in flight into the
-  // source.  Loads past the last step read the chunk's last row (the row
-  // index is clamped) and the steps past KS contribute zero.
+  // GS register stages with fixed roles (the loop is unrolled by GS; three
+  // by default: four or five measured no faster): the rows of step
+  // s + GS - 1 are in flight while step s multiplies.  A copy between stages
+  // would make the compiler wait for the loads in flight into the source.
+  // Loads past the last step read the chunk's last row (the row index is
+  // clamped) and the steps past KS contribute zero.
   T xq[GS][4], yq[GS][4];
   if (KS > 0) {
 #pragma unroll
@@ -491,8 +492,8 @@ hipError_t gram_t(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t M, i
   int64_t rpc = (M + nch - 1) / nch;
   rpc = (rpc + 15) / 16 * 16;
   nch = static_cast<int>((M + rpc - 1) / rpc);   // rounding rpc up can leave trailing chunks empty
-  hipLaunchKernelGGL((gram_kernel<T, kGramStages>), dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc, npad, partial,
-                     offx, offy);
+  hipLaunchKernelGGL((gram_kernel<T, kGramStages>), dim3(ntiles, nch), dim3(256), 0, s, X, ldx, Y, ldy, M, n, rpc,
+                     npad, partial, offx, offy);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(static_cast<int64_t>(n) * n)), dim3(256), 0, s,
                      partial, nch, n, npad, G, ldg);
   return hipGetLastError();
