@@ -452,11 +452,21 @@ def run_c2(args):
     tmix = results.get("mixed", {}).get("time_to_target_s")
     t32 = results.get("f32", {}).get("time_to_target_s")
     tsp = results.get("f32_split_rr", {}).get("time_to_target_s")
+    # the headline is the fastest reduced-precision route that reaches the
+    # target (every route's figures stay in "runs")
+    routes = {n: r["time_to_target_s"] for n, r in results.items()
+              if n not in ("f64", "bf16") and r.get("time_to_target_s") is not None}
+    best = min(routes, key=routes.get) if routes else None
+    dtypes = {"f32": "f32 filter, f64 subspace", "mixed": "bf16/f32 filter, f64 subspace",
+              "f32_split_rr": "f32 filter, f64 spectrum-split Rayleigh-Ritz",
+              "f32_split_rr_mixed": "f32 filter, mixed spectrum-split Rayleigh-Ritz"}
     out = {
         "metric": "time to Delta E <= 1e-6 Ha, mixed precision vs FP64 (c2)",
-        "value": tmix, "unit": "s", "n_gpus": 1, "steps": results.get("mixed", {}).get("passes"), "warmup": 0,
-        "ms_per_step": 1e3 * results.get("mixed", results["f64"])["sec_per_pass"], "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f32 filter, f64 subspace", "data": "synthetic",
+        "value": routes.get(best), "unit": "s", "n_gpus": 1,
+        "steps": results.get(best, {}).get("passes"), "warmup": 0,
+        "ms_per_step": 1e3 * results.get(best, results["f64"])["sec_per_pass"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtypes.get(best, "f64"), "data": "synthetic",
+        "route": best,
         "config": {"workload": "c2: c1 operator (24^3 cells p=6, M=2985984, 64 atoms with projectors), N=1024 "
                                "+ 128 buffer columns, B=128, m=30, start N(0,1) seeded",
                    "N": N, "n_buf": nb, "block": B, "degree": m, "b_upper": b,
@@ -464,7 +474,8 @@ def run_c2(args):
                    "reference_max_resid": r_ref, "gap_prefixes": {f"{g:g}": k for g, k in prefixes.items()}},
         "speedup_vs_f64": {"f32": (t64 / t32) if (t64 and t32) else None,
                            "mixed": (t64 / tmix) if (t64 and tmix) else None,
-                           "f32_split_rr": (t64 / tsp) if (t64 and tsp) else None},
+                           "f32_split_rr": (t64 / tsp) if (t64 and tsp) else None,
+                           "best": (t64 / routes[best]) if (t64 and best) else None},
         "runs": results,
     }
     if not args.no_cpu_baseline:
