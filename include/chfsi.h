@@ -537,6 +537,28 @@ int chfsi_mlp_train_step(chfsi_mlp* net, const float* F, int64_t rows, const flo
 int chfsi_initial_block(chfsi_op* op, chfsi_mlp* net, uint64_t seed, void* X, int64_t ncols, int64_t ld,
                         int32_t* used_fallback);
 
+/* ---- deterministic assembly ----------------------------------------------
+ * Section 4.3 assembles the cell products Y^c into the global vector (the
+ * scatter of Eq. celldgemm); the default path adds them with hardware
+ * atomics, so the order in which the up to 8 cells sharing a node add into
+ * it depends on workgroup timing and the result can differ from run to run
+ * in the last bits.  chfsi_set_deterministic(ctx, 1) runs every H~.X of the
+ * context (chfsi_apply, chfsi_apply_noalloc, the filter, the solvers, and the
+ * batched filter and solve, which then run problem by problem) colour class
+ * by colour class: along each axis the cells take colours 0, 1, 0, 1, ...
+ * (and 2 for the last cell of an odd side), a class is a triple of axis
+ * colours, no two cells of one class share a node, and the classes run in a
+ * fixed order, one launch each (8 launches per H~.X for an even number of
+ * cells per side, 27 for an odd one).  Results are then bitwise reproducible
+ * for the same inputs, launch shapes and device.  Enabling builds the colour
+ * classes of every live operator (one int32 per cell on the device); an
+ * operator built later gets them at construction.  Operators with a single
+ * cell per side (a cell sharing nodes with its own periodic images) cannot
+ * be coloured: their H~.X calls return CHFSI_EINVAL while the mode is on.
+ * Returns CHFSI_EINVAL for a null ctx, CHFSI_ENOMEM / CHFSI_EHIP if the
+ * classes cannot be uploaded (the mode then stays as it was). */
+int chfsi_set_deterministic(chfsi_ctx* ctx, int32_t enable);
+
 /* ---- kernel timing ---------------------------------------------------------
  * When enabled, the library brackets every launch of the cell H~.X kernel
  * with HIP events on the context stream.  chfsi_kernel_time() waits for the

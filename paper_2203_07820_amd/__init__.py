@@ -112,6 +112,10 @@ class Context:
     def set_timing(self, enable: bool):
         self.check(self.lib.chfsi_set_timing(self.h, 1 if enable else 0))
 
+    def set_deterministic(self, enable: bool):
+        """H~.X assembled colour class by colour class (bitwise reproducible)."""
+        self.check(self.lib.chfsi_set_deterministic(self.h, 1 if enable else 0))
+
     def kernel_time(self, reset: bool = True):
         """(total ms, launches, algorithmic flops) of the timed cell-kernel launches."""
         ms, n, fl = C.c_double(), C.c_int64(), C.c_double()

@@ -17,7 +17,7 @@ EXPORTS = [
     "chfsi_ctx_create", "chfsi_ctx_destroy", "chfsi_last_error", "chfsi_sync", "chfsi_version", "chfsi_abi_sizes",
     "chfsi_op_build", "chfsi_op_destroy", "chfsi_op_info", "chfsi_op_tables",
     "chfsi_apply", "chfsi_apply_noalloc", "chfsi_bounds", "chfsi_filter", "chfsi_orthonormalize",
-    "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_kernel_time",
+    "chfsi_rayleigh_ritz", "chfsi_solve", "chfsi_pass", "chfsi_set_timing", "chfsi_set_deterministic", "chfsi_kernel_time",
     "chfsi_filter_batched", "chfsi_solve_batched", "chfsi_autotune", "chfsi_load_tuning", "chfsi_get_tuning",
     "chfsi_features", "chfsi_mlp_create", "chfsi_mlp_destroy", "chfsi_mlp_info", "chfsi_mlp_params",
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
@@ -95,6 +95,7 @@ def load() -> C.CDLL:
         "chfsi_solve": (C.c_int, [vp, C.POINTER(Params), vp, i64, pd, pd, C.POINTER(Stats)]),
         "chfsi_pass": (C.c_int, [vp, C.POINTER(Params), vp, i64, dbl, dbl, dbl, pd, pd]),
         "chfsi_set_timing": (C.c_int, [vp, i32]),
+        "chfsi_set_deterministic": (C.c_int, [vp, i32]),
         "chfsi_kernel_time": (C.c_int, [vp, pd, C.POINTER(i64), pd, i32]),
         "chfsi_filter_batched": (C.c_int, [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), C.POINTER(i64),
                                            i32, pd, pd, pd, i32, i32, i32]),

@@ -54,6 +54,74 @@ int upload_f32(chfsi_op* op, const std::vector<double>& v, void** out) {
   return 0;
 }
 
+// Colour classes of the cells for deterministic assembly.  Along each axis
+// the cells of the periodic mesh form a cycle; they take colours 0, 1, 0,
+// 1, ... and, when the number of cells per side is odd, the last cell colour
+// 2, so that neighbouring cells never share a colour.  A class is a triple
+// of axis colours (8 classes for an even side, 27 for an odd one); two
+// cells of one class are not neighbours along any axis and so share no
+// node, which the construction checks by marking the nodes of each class.
+int build_colours(chfsi_op* op) {
+  if (op->colour_cells) return 0;
+  const HostTables& t = op->t;
+  const int nc = t.ncell, p = t.p, n = nc * p;
+  if (nc < 2)
+    return fail(op->ctx, CHFSI_EINVAL,
+                "deterministic assembly needs at least 2 cells per side (a single cell shares nodes with its "
+                "own periodic images)");
+  const int K = (nc % 2) ? 3 : 2;
+  auto colour = [&](int i) { return (nc % 2 && i == nc - 1) ? 2 : i % 2; };
+  std::vector<std::vector<int32_t>> cls(K * K * K);
+  for (int cz = 0; cz < nc; ++cz)
+    for (int cy = 0; cy < nc; ++cy)
+      for (int cx = 0; cx < nc; ++cx)
+        cls[colour(cx) + K * (colour(cy) + K * colour(cz))].push_back(cx + nc * (cy + nc * cz));
+  std::vector<int32_t> mark(static_cast<size_t>(n) * n * n, -1);
+  std::vector<int32_t> flat;
+  std::vector<int> off{0};
+  for (int k = 0; k < K * K * K; ++k) {
+    if (cls[k].empty()) continue;
+    for (const int32_t cell : cls[k]) {
+      const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
+      for (int lc = 0; lc <= p; ++lc)
+        for (int lb = 0; lb <= p; ++lb)
+          for (int la = 0; la <= p; ++la) {
+            const int gx = (cx * p + la) % n, gy = (cy * p + lb) % n, gz = (cz * p + lc) % n;
+            int32_t& m = mark[gx + static_cast<size_t>(n) * (gy + static_cast<size_t>(n) * gz)];
+            if (m == k) return fail(op->ctx, CHFSI_EINVAL, "internal error: a colour class shares a node");
+            m = k;
+          }
+    }
+    flat.insert(flat.end(), cls[k].begin(), cls[k].end());
+    off.push_back(static_cast<int>(flat.size()));
+  }
+  int32_t* d = nullptr;
+  CHECK(upload(op, flat, &d));
+  op->colour_cells = d;
+  op->colour_off = off;
+  return 0;
+}
+
+// One H~.X launch over all cells, or, with deterministic assembly, one per
+// colour class in a fixed order: inside a class every node receives at most
+// one contribution, so each node's sum is formed in the class order
+// whatever the order in which the workgroups run.
+int launch_hx_cells(chfsi_op* op, const HxLaunch& L, int prec) {
+  chfsi_ctx* ctx = op->ctx;
+  if (!ctx->deterministic) {
+    HIP_TRY(ctx, launch_cell_hx(L, prec, ctx->stream));
+    return 0;
+  }
+  if (!op->colour_cells) return fail(ctx, CHFSI_EINVAL, "colour classes of the operator are not built");
+  for (size_t k = 0; k + 1 < op->colour_off.size(); ++k) {
+    HxLaunch Lk = L;
+    Lk.cells = op->colour_cells + op->colour_off[k];
+    Lk.ncell = op->colour_off[k + 1] - op->colour_off[k];
+    HIP_TRY(ctx, launch_cell_hx(Lk, prec, ctx->stream));
+  }
+  return 0;
+}
+
 bool prec_valid_for(const chfsi_op* op, int prec) {
   if (op->t.cplx) return prec == CHFSI_C128 || prec == CHFSI_C64;
   // per-cell matrices exist in FP64 and FP32 only
@@ -189,13 +257,14 @@ int hx_step(chfsi_op* op, int prec, const void* Xk, int64_t ldx, const void* Xp,
   }
   HxLaunch L = make_hx(op, prec, Xk, ldx, Xp, ldp, T, ldt, ncols, alpha, c, beta, zero_prev, hP, ldhp);
   const int kp = prec;
+  if (ctx->deterministic) CHECK(build_colours(op));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
   }
-  HIP_TRY(ctx, launch_cell_hx(L, kp, ctx->stream));
+  CHECK(launch_hx_cells(op, L, kp));
   if (ctx->timing) {
     HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     ctx->pending.emplace_back(e0, e1);
@@ -801,6 +870,12 @@ int batched_filter(chfsi_ctx* ctx, const std::vector<BItem>& items, int m, int p
     if (!prec_valid_for(it.op, prec)) return fail(ctx, CHFSI_EINVAL, "precision does not match the operators");
     if (prec == CHFSI_BF16) return fail(ctx, CHFSI_EINVAL, "batched filter supports F64, F32, C128, C64");
     if (!(it.aL < it.a && it.a < it.b)) return fail(ctx, CHFSI_EINVAL, "need aL < a < b for every item");
+  }
+  // deterministic assembly: each problem's filter on its own, colour class
+  // by colour class (no batched launch, no graph)
+  if (ctx->deterministic && !force) {
+    for (const BItem& it : items) CHECK(do_filter(it.op, it.X, it.ncols, it.ld, m, it.a, it.b, it.aL, prec, block));
+    return 0;
   }
   const int cf = cplx ? 2 : 1;
   const int sp = storage_of(prec);
@@ -1418,6 +1493,15 @@ int chfsi_op_build(chfsi_ctx* ctx, const chfsi_system* sys, chfsi_op** out) {
   std::vector<int32_t>().swap(t.atom_node);
   std::vector<double>().swap(t.pair_re);
   std::vector<double>().swap(t.pair_im);
+  // deterministic assembly already on: the colour classes now, so that no
+  // later call has to allocate them (operators with one cell per side have
+  // none and are refused at their first H~.X)
+  if (ctx->deterministic && t.ncell >= 2) {
+    if ((rc = build_colours(op.get())) < 0) {
+      cleanup();
+      return rc;
+    }
+  }
   op->id = ctx->next_op_id++;
   ctx->live_ops.insert(op.get());
   *out = op.release();
@@ -1650,8 +1734,7 @@ int chfsi_apply_noalloc(chfsi_op* op, const void* X, void* Y, int64_t ncols, int
     CHECK(nl_project(op, prec, X, ld, ncols, base, hP, ldhp));
   }
   const HxLaunch L = make_hx(op, prec, X, ld, nullptr, ld, Y, ld, ncols, 1.0, 0.0, 0.0, false, hP, ldhp);
-  HIP_TRY(ctx, launch_cell_hx(L, prec, ctx->stream));
-  return 0;
+  return launch_hx_cells(op, L, prec);
 }
 
 int chfsi_bounds(chfsi_op* op, int32_t steps, const void* v0, uint64_t seed, double* b_upper, double* lmin_est) {
@@ -2073,6 +2156,20 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
 int chfsi_set_timing(chfsi_ctx* ctx, int32_t enable) {
   if (!ctx) return CHFSI_EINVAL;
   ctx->timing = enable != 0;
+  return 0;
+}
+
+int chfsi_set_deterministic(chfsi_ctx* ctx, int32_t enable) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (enable) {
+    // colour classes of the live operators now (one cell per side: none; such
+    // an operator is refused at its first H~.X while the mode is on)
+    for (const void* o : ctx->live_ops) {
+      chfsi_op* op = static_cast<chfsi_op*>(const_cast<void*>(o));
+      if (op->t.ncell >= 2) CHECK(build_colours(op));
+    }
+  }
+  ctx->deterministic = enable != 0;
   return 0;
 }
 

@@ -43,6 +43,9 @@ struct chfsi_ctx {
   size_t ws_size[WS_COUNT] = {};
   // opt-in timing of the cell kernel: event pairs not yet read, totals
   bool timing = false;
+  // deterministic assembly (chfsi_set_deterministic): every H~.X launch runs
+  // colour class by colour class
+  bool deterministic = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<double> pending_flops;
   double t_ms = 0.0, t_flops = 0.0;
@@ -97,6 +100,11 @@ struct chfsi_op {
   void* pair_re32 = nullptr; void* pair_im32 = nullptr;
   double* d_x1d = nullptr;      // node coordinates along one axis (features)
   double* d_atoms = nullptr;    // atom table (features)
+  // colour classes of the cells for deterministic assembly: the cells of
+  // class k are colour_cells[colour_off[k] .. colour_off[k + 1]) (device);
+  // built when deterministic assembly is first switched on for the operator
+  int32_t* colour_cells = nullptr;
+  std::vector<int> colour_off;
   std::vector<void*> allocs;
 };
 

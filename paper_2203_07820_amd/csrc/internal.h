@@ -90,6 +90,10 @@ struct HxLaunch {
   int64_t astride = 0;             // per-cell real matrices: elements per cell (0: shared)
   int ncu = 0;                     // compute units (persistent launches)
   int nt = 64;                     // columns per work item: 64, or 32 (not for BF16)
+  // deterministic assembly: launch over one colour class of cells only
+  // (device array of ncell cell ids, no two sharing a node); null: all cells
+  const int32_t* cells = nullptr;
+  int ncell = 0;
 };
 
 // prec: CHFSI_F64 / F32 / BF16 (real), C128 / C64 (complex, data real view).

@@ -97,7 +97,22 @@ struct HxArgs {
   const T* hP;
   int64_t ldhp;
   int64_t astride;  // elements between the real cell matrices of consecutive cells (0: one shared)
+  // deterministic assembly: this launch covers only the cells cells[0..ncell)
+  // (one colour class, no two of which share a node); null: every cell
+  const int32_t* cells;
+  int ncell;
 };
+
+// Work item bid of a single-problem launch: its cell and first column.  With
+// a colour class, work item bid takes the class's cell bid % ncell.
+template <int NT, typename T>
+__device__ __forceinline__ void item_of(const HxArgs<T>& a, const int bid, int& cell, int& col0) {
+  const int E = a.nc * a.nc * a.nc;
+  const int ne = a.cells ? a.ncell : E;
+  const int i = bid % ne;
+  cell = a.cells ? to_global(a.cells)[i] : i;
+  col0 = (bid / ne) * NT;
+}
 
 // Buffer resource over `bytes` bytes at p (raw buffer, 32-bit words).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -495,9 +510,9 @@ template <int P, typename T, bool CPLX, int WAVES, int OCC, int CG, int NT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64 * WAVES, 64 * WAVES), amdgpu_waves_per_eu(OCC, OCC)))
 cell_hx_kernel(const HxArgs<T> a) {
   __shared__ RowTables<rows_padded<P>(), T> tab;
-  const int E = a.nc * a.nc * a.nc;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>(), CG, NT>(a, bid % E, (bid / E) * NT, tab);
+  int cell, col0;
+  item_of<NT>(a, xcd_remap(blockIdx.x, gridDim.x), cell, col0);
+  cell_item<P, T, CPLX, WAVES, epilogue_depth<T>(), CG, NT>(a, cell, col0, tab);
 }
 
 // bf16 cell products with FP32 iterates (the BF16 filter precision).  The
@@ -552,9 +567,8 @@ cell_hx_bf16_kernel(const HxArgs<float> a) {
   __shared__ __attribute__((aligned(16))) __bf16 bt[kNT * CS];
   __shared__ float xs[XS_LDS ? MP * XS : 1];
 
-  const int E = a.nc * a.nc * a.nc;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int cell = bid % E, col0 = (bid / E) * kNT;
+  int cell, col0;
+  item_of<kNT>(a, xcd_remap(blockIdx.x, gridDim.x), cell, col0);
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   const int lane = tid % 64;
@@ -768,6 +782,8 @@ HxArgs<T> pack_args(const HxLaunch& L) {
   a.hP = static_cast<const T*>(L.hP);
   a.ldhp = L.ldhp;
   a.astride = L.astride;
+  a.cells = L.cells;
+  a.ncell = L.ncell;
   return a;
 }
 
@@ -777,7 +793,7 @@ hipError_t launch_p(const HxLaunch& L, hipStream_t s) {
   const int64_t E = static_cast<int64_t>(L.nc) * L.nc * L.nc;
   const int nt = (BF || L.nt != 32) ? kNT : 32;   // the bf16 kernel has 64-column tiles only
   const int64_t nct = (L.ncols + nt - 1) / nt;
-  const int64_t nblk = E * nct;
+  const int64_t nblk = (L.cells ? L.ncell : E) * nct;
   if (nblk <= 0) return hipSuccess;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
   if constexpr (BF) {
