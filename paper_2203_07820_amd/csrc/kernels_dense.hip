@@ -216,13 +216,15 @@ __global__ void gram_combine_complex_kernel(const double* __restrict__ G, int64_
 }
 
 // ---- rotation C = X Z --------------------------------------------------------
-// Workgroup tile 64 rows x 128 columns, 4 waves of 32 x 64 (2 x 4 MFMA tiles).
-// X rows are staged through LDS (the A operand needs 16 rows per fragment),
-// Z through LDS as well; both double buffered, with the next 16-deep k chunk
-// loaded into registers from global memory while the current one multiplies,
-// so there is one barrier per chunk and the global latency overlaps the
-// MFMAs.  upper: Z is upper triangular, k stops at the tile's last column.
-constexpr int kRM = 64;   // rows per workgroup
+// Workgroup tile 128 x 128, 4 waves of 64 x 64 (4 x 4 MFMA tiles: each A and
+// B fragment read from LDS serves four MFMAs).  X rows are staged through
+// LDS (the A operand needs 16 rows per fragment), Z through LDS as well; both
+// double buffered, with the next 16-deep k chunk loaded into registers from
+// global memory while the current one multiplies, so there is one barrier
+// per chunk (64 MFMAs per wave) and the global latency overlaps the MFMAs.
+// The two stages take 70 KB of LDS at FP64: two workgroups per CU.
+// upper: Z is upper triangular, k stops at the tile's last column.
+constexpr int kRM = 128;  // rows per workgroup
 constexpr int kRN = 128;  // columns per workgroup
 constexpr int kRK = 16;   // k per stage
 constexpr int kZP = kRN + 8;  // padded LDS row of the Z stage
@@ -236,24 +238,24 @@ rotate_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int
   const int64_t r0 = blockIdx.x * static_cast<int64_t>(kRM);
   const int c0 = blockIdx.y * kRN;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int wr = (wave / 2) * 32, wc = (wave % 2) * 64;
+  const int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
   using Acc = typename Mfma<T>::Acc;
-  Acc acc[2][4];
+  Acc acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   int kend = K;
   if (upper && c0 + kRN < kend) kend = c0 + kRN;
-  // loaders: X 64 rows x 16 k (4 per thread, 16 threads per row), Z 16 k x
+  // loaders: X 128 rows x 16 k (8 per thread, 16 threads per row), Z 16 k x
   // 128 columns (8 per thread, one row per 128 threads); addresses clamped,
   // out-of-range values zeroed when stored to LDS
   const int xk = tid % kRK, xr = tid / kRK;
   const int zc = tid % kRN, zr = tid / kRN;
-  T gx[4], gz[8];
+  T gx[8], gz[8];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       int64_t row = r0 + xr + 16 * i;
       row = row < M ? row : M - 1;
       int k = k0 + xk;
@@ -271,7 +273,7 @@ rotate_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int
   };
   auto sstore = [&](int buf, int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const bool ok = r0 + xr + 16 * i < M && k0 + xk < K;
       xs[buf][xr + 16 * i][xk] = ok ? gx[i] : T(0);
     }
@@ -293,13 +295,13 @@ rotate_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int
 #pragma unroll
     for (int ks = 0; ks < kRK / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
-      T av[2], bv[4];
+      T av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = xs[buf][wr + a * 16 + lane % 16][kr];
+      for (int a = 0; a < 4; ++a) av[a] = xs[buf][wr + a * 16 + lane % 16][kr];
 #pragma unroll
       for (int b = 0; b < 4; ++b) bv[b] = zs[buf][kr][wc + b * 16 + lane % 16];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::mma(av[a], bv[b], acc[a][b]);
     }
@@ -308,7 +310,7 @@ rotate_kernel(const T* __restrict__ X, int64_t ldx, const T* __restrict__ Z, int
     buf ^= 1;
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
