@@ -315,8 +315,12 @@ int chfsi_rayleigh_ritz_split(chfsi_op* op, void* X, int64_t ncols, int64_t ld, 
  * CholGS + RR on X giving a = theta_{N+n_buf}, aL = theta_1; then passes of
  * (filter every block, CholGS, RR, update a and aL).  theta and resid (host,
  * N + n_buf each, resid nullable) receive the final Ritz values and residual
- * norms; stats (nullable) the timings.  Returns CHFSI_NOTCONV if a tolerance
- * was requested and not met.  Synchronous. */
+ * norms; stats (nullable) the timings and stats->b_upper the bound used.
+ * Returns CHFSI_NOTCONV if a tolerance was requested and not met.
+ * Checkpoint and resume: the state between passes is X and b (a and aL are
+ * recomputed from the Ritz values by the initial Rayleigh-Ritz), so a solve
+ * restarted from the X it returned, with params->b_upper = stats->b_upper,
+ * continues the same iteration up to rounding.  Synchronous. */
 int chfsi_solve(chfsi_op* op, const chfsi_params* params, void* X, int64_t ld, double* theta,
                 double* resid, chfsi_stats* stats);
 
