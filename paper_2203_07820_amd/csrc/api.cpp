@@ -112,7 +112,10 @@ int launch_hx_cells(chfsi_op* op, const HxLaunch& L, int prec) {
     HIP_TRY(ctx, launch_cell_hx(L, prec, ctx->stream));
     return 0;
   }
-  if (!op->colour_cells) return fail(ctx, CHFSI_EINVAL, "colour classes of the operator are not built");
+  if (!op->colour_cells) {
+    if (op->t.ncell < 2) CHECK(build_colours(op));   // fails with the reason
+    return fail(ctx, CHFSI_EINVAL, "colour classes of the operator are not built");
+  }
   for (size_t k = 0; k + 1 < op->colour_off.size(); ++k) {
     HxLaunch Lk = L;
     Lk.cells = op->colour_cells + op->colour_off[k];
