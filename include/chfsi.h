@@ -559,9 +559,11 @@ int chfsi_initial_block(chfsi_op* op, chfsi_mlp* net, uint64_t seed, void* X, in
  * operator built later gets them at construction.  Operators with a single
  * cell per side (a cell sharing nodes with its own periodic images) cannot
  * be coloured: their H~.X calls return CHFSI_EINVAL while the mode is on.
- * Not covered: the Hartree solve of chfsi_hartree and chfsi_scf, whose
- * stiffness assembly and CG dot products also add by atomics, so an SCF run
- * is reproducible only to rounding.  Returns CHFSI_EINVAL for a null ctx,
+ * The mode also covers the Hartree solve of chfsi_hartree and chfsi_scf:
+ * its stiffness assembly runs by colour class as well, and the dot products
+ * of its CG are summed from per-block partials in a fixed order instead of
+ * by atomic adds (three more small launches per CG iteration), so a whole
+ * SCF run is bitwise reproducible.  Returns CHFSI_EINVAL for a null ctx,
  * CHFSI_ENOMEM / CHFSI_EHIP if the classes cannot be uploaded (the mode then
  * stays as it was). */
 int chfsi_set_deterministic(chfsi_ctx* ctx, int32_t enable);

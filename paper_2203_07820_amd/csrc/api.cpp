@@ -1204,7 +1204,15 @@ int apply_stiffness(chfsi_op* op, const double* u, double* qv) {
   chfsi_ctx* ctx = op->ctx;
   const HostTables& t = op->t;
   HIP_TRY(ctx, launch_fill(qv, t.M, 1, 1, CHFSI_F64, ctx->stream));
-  HIP_TRY(ctx, launch_stiffness(u, op->dscale, qv, t.p, t.ncell, t.K1d.data(), t.M1d.data(), ctx->stream));
+  if (!ctx->deterministic) {
+    HIP_TRY(ctx, launch_stiffness(u, op->dscale, qv, t.p, t.ncell, t.K1d.data(), t.M1d.data(), ctx->stream));
+    return 0;
+  }
+  // deterministic assembly: colour class by colour class, as for H~X
+  CHECK(build_colours(op));
+  for (size_t k = 0; k + 1 < op->colour_off.size(); ++k)
+    HIP_TRY(ctx, launch_stiffness(u, op->dscale, qv, t.p, t.ncell, t.K1d.data(), t.M1d.data(), ctx->stream,
+                                  op->colour_cells + op->colour_off[k], op->colour_off[k + 1] - op->colour_off[k]));
   return 0;
 }
 
@@ -1259,10 +1267,13 @@ int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int m
   // the host reads the residual history once per kCheck iterations, so a
   // solve runs up to kCheck - 1 iterations past the stopping point
   constexpr int kCheck = 8;
+  // scalars, residual history, and (deterministic mode) the dot products'
+  // block partials, 5 x 256 values
   void* scv;
-  CHECK(ws_get(ctx, WS_CG, (8 + kCheck) * 8, &scv));
+  CHECK(ws_get(ctx, WS_CG, (8 + kCheck + 5 * 256) * 8, &scv));
   double* sc = static_cast<double*>(scv);
   double* hist = sc + 8;
+  double* part = ctx->deterministic ? sc + 8 + kCheck : nullptr;
   const double sc0[8] = {rz, 0.0, 0.0, 0.0, 0.0, zz, 0.0, 0.0};
   HIP_TRY(ctx, hipMemcpyAsync(sc, sc0, sizeof(sc0), hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -1273,7 +1284,7 @@ int hartree_solve(chfsi_op* op, const double* rho, double* vh, double tol, int m
     const int k = std::min(kCheck, maxit - it);
     for (int j = 0; j < k; ++j) {
       CHECK(apply_stiffness(op, pv, qv));
-      HIP_TRY(ctx, launch_cg_iteration(u, r, z, pv, qv, kd, sqm, sc, hist, j, M, st));
+      HIP_TRY(ctx, launch_cg_iteration(u, r, z, pv, qv, kd, sqm, sc, hist, j, M, st, part));
     }
     HIP_TRY(ctx, hipMemcpyAsync(hh, hist, k * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));

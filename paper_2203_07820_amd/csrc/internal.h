@@ -186,12 +186,17 @@ hipError_t launch_veff(const double* vext, const double* vh, const double* rho, 
 // One preconditioned CG iteration after q = A p: with the device scalars
 // sc (6 values: r.z, p.q, r.r, z.n, new r.z, n.n) it updates u, r, z (Jacobi,
 // then projected off the null vector nv) and p, and stores r.r in hist[it].
+// part (nullable, 5 x 256 values): the dot products' block partials are
+// stored there and summed in a fixed order instead of added atomically
 hipError_t launch_cg_iteration(double* u, double* r, double* z, double* p, const double* q, const double* kd,
-                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s);
+                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s,
+                               double* part = nullptr);
 // q += D K D u on the structured mesh by sum factorisation (K1, M1: the 1D
 // stiffness and consistent mass, host, (p+1)^2 values each)
+// (cells: the ncell cells of one colour class, no two sharing a node; null:
+// every cell)
 hipError_t launch_stiffness(const double* u, const double* dscale, double* q, int p, int nc, const double* K1,
-                            const double* M1, hipStream_t s);
+                            const double* M1, hipStream_t s, const int32_t* cells = nullptr, int ncell = 0);
 
 // Elementwise helpers on row-major blocks (real view).
 hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int prec, hipStream_t s);

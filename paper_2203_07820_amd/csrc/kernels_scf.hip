@@ -44,6 +44,7 @@ struct StiffArgs {
   const double* u;       // M values
   const double* dscale;  // M^-1/2 per node
   double* q;             // M values, accumulated
+  const int32_t* cells;  // deterministic assembly: the cells of one colour class (null: all)
   int nc, n;             // cells and nodes per side
   double K1[64];         // 1D stiffness, row-major (p+1) x (p+1)
   double M1[64];         // 1D consistent mass
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(64) stiffness_kernel(StiffArgs a) {
   __shared__ double x[MC], ux[MC], vx[MC], s1[MC], s2[MC];
   __shared__ int32_t node[MC];
   const int t = threadIdx.x;
-  const int64_t e = blockIdx.x;
+  const int64_t e = a.cells ? a.cells[blockIdx.x] : blockIdx.x;
   const int cx = static_cast<int>(e % a.nc), cy = static_cast<int>((e / a.nc) % a.nc),
             cz = static_cast<int>(e / (static_cast<int64_t>(a.nc) * a.nc));
   for (int l = t; l < MC; l += 64) {
@@ -115,11 +116,12 @@ __global__ void __launch_bounds__(64) stiffness_kernel(StiffArgs a) {
 }  // namespace
 
 hipError_t launch_stiffness(const double* u, const double* dscale, double* q, int p, int nc, const double* K1,
-                            const double* M1, hipStream_t s) {
+                            const double* M1, hipStream_t s, const int32_t* cells, int ncell) {
   StiffArgs a{};
   a.u = u;
   a.dscale = dscale;
   a.q = q;
+  a.cells = cells;
   a.nc = nc;
   a.n = nc * p;
   const int Q = p + 1;
@@ -127,7 +129,8 @@ hipError_t launch_stiffness(const double* u, const double* dscale, double* q, in
     a.K1[i] = K1[i];
     a.M1[i] = M1[i];
   }
-  const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(nc) * nc * nc)), block(64);
+  const dim3 grid(static_cast<unsigned>(cells ? ncell : static_cast<int64_t>(nc) * nc * nc)), block(64);
+  if (grid.x == 0) return hipSuccess;
   switch (p) {
     case 2: hipLaunchKernelGGL(stiffness_kernel<2>, grid, block, 0, s, a); break;
     case 3: hipLaunchKernelGGL(stiffness_kernel<3>, grid, block, 0, s, a); break;
@@ -145,7 +148,9 @@ namespace {
 // ---- preconditioned CG with its scalars on the device ------------------------
 // sc[0] = r.z, sc[1] = p.q, sc[2] = r.r, sc[3] = z.n, sc[4] = r.z (new),
 // sc[5] = |n|^2 (n = M^1/2 1, the null vector); dot products accumulate by
-// one atomic add per block.
+// one atomic add per block, or, for deterministic results, each block
+// stores its partial sum of scalar k at part[k * kCgMaxBlocks + block] and
+// one block sums them in a fixed order (cg_sum_kernel).
 
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[4];
@@ -159,12 +164,31 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;   // valid in thread 0
 }
 
+constexpr int kCgMaxBlocks = 256;
+
+// block partial v of scalar k: added into sc[k], or stored for cg_sum_kernel
+__device__ __forceinline__ void put_partial(double* sc, double* part, int k, double v) {
+  if (threadIdx.x != 0) return;
+  if (part) part[k * kCgMaxBlocks + blockIdx.x] = v;
+  else atomicAdd(sc + k, v);
+}
+
+// sc[k] = sum of the nb partials of scalar k, for k in [k0, k0 + cnt), in
+// one fixed order (one block)
+__global__ void __launch_bounds__(256) cg_sum_kernel(const double* __restrict__ part, double* __restrict__ sc,
+                                                     int k0, int cnt, int nb) {
+  for (int k = k0; k < k0 + cnt; ++k) {
+    const double v = block_sum(threadIdx.x < nb ? part[k * kCgMaxBlocks + threadIdx.x] : 0.0);
+    if (threadIdx.x == 0) sc[k] = v;
+  }
+}
+
 __global__ void __launch_bounds__(256) cg_pq_kernel(const double* __restrict__ p, const double* __restrict__ q,
-                                                    double* __restrict__ sc, int64_t n) {
+                                                    double* __restrict__ sc, double* __restrict__ part, int64_t n) {
   double v = 0.0;
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) v += p[i] * q[i];
   v = block_sum(v);
-  if (threadIdx.x == 0) atomicAdd(sc + 1, v);
+  put_partial(sc, part, 1, v);
 }
 
 // u += a p, r -= a q, z = r / kd; sums r.r, z.n, r.n
@@ -172,7 +196,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(double* __restrict__ u, 
                                                         double* __restrict__ z, const double* __restrict__ p,
                                                         const double* __restrict__ q, const double* __restrict__ kd,
                                                         const double* __restrict__ nv, double* __restrict__ sc,
-                                                        int64_t n) {
+                                                        double* __restrict__ part, int64_t n) {
   const double pq = sc[1];
   const double al = pq > 0.0 ? sc[0] / pq : 0.0;
   double rr = 0.0, zn = 0.0;
@@ -186,15 +210,15 @@ __global__ void __launch_bounds__(256) cg_update_kernel(double* __restrict__ u, 
     zn += zi * nv[i];
   }
   rr = block_sum(rr);
-  if (threadIdx.x == 0) atomicAdd(sc + 2, rr);
+  put_partial(sc, part, 2, rr);
   zn = block_sum(zn);
-  if (threadIdx.x == 0) atomicAdd(sc + 3, zn);
+  put_partial(sc, part, 3, zn);
 }
 
 // z -= (z.n / n.n) n; sum r.z
 __global__ void __launch_bounds__(256) cg_project_kernel(const double* __restrict__ r, double* __restrict__ z,
                                                          const double* __restrict__ nv, double* __restrict__ sc,
-                                                         int64_t n) {
+                                                         double* __restrict__ part, int64_t n) {
   const double c = sc[3] / sc[5];
   double rz = 0.0;
   for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
@@ -203,7 +227,7 @@ __global__ void __launch_bounds__(256) cg_project_kernel(const double* __restric
     rz += r[i] * zi;
   }
   rz = block_sum(rz);
-  if (threadIdx.x == 0) atomicAdd(sc + 4, rz);
+  put_partial(sc, part, 4, rz);
 }
 
 // p = z + (rz_new / rz) p
@@ -230,17 +254,22 @@ __global__ void cg_scalars_kernel(double* __restrict__ sc, double* __restrict__ 
 // into the same few scalars, and those atomics serialise in L2
 unsigned cg_grid(int64_t n) {
   const int64_t b = (n + 255) / 256;
-  return static_cast<unsigned>(b < 256 ? b : 256);
+  return static_cast<unsigned>(b < kCgMaxBlocks ? b : kCgMaxBlocks);
 }
 
 }  // namespace
 
 hipError_t launch_cg_iteration(double* u, double* r, double* z, double* p, const double* q, const double* kd,
-                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s) {
+                               const double* nv, double* sc, double* hist, int it, int64_t n, hipStream_t s,
+                               double* part) {
   const dim3 g(cg_grid(n)), b(256);
-  hipLaunchKernelGGL(cg_pq_kernel, g, b, 0, s, p, q, sc, n);
-  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, s, u, r, z, p, q, kd, nv, sc, n);
-  hipLaunchKernelGGL(cg_project_kernel, g, b, 0, s, r, z, nv, sc, n);
+  const int nb = static_cast<int>(g.x);
+  hipLaunchKernelGGL(cg_pq_kernel, g, b, 0, s, p, q, sc, part, n);
+  if (part) hipLaunchKernelGGL(cg_sum_kernel, dim3(1), b, 0, s, part, sc, 1, 1, nb);
+  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, s, u, r, z, p, q, kd, nv, sc, part, n);
+  if (part) hipLaunchKernelGGL(cg_sum_kernel, dim3(1), b, 0, s, part, sc, 2, 2, nb);
+  hipLaunchKernelGGL(cg_project_kernel, g, b, 0, s, r, z, nv, sc, part, n);
+  if (part) hipLaunchKernelGGL(cg_sum_kernel, dim3(1), b, 0, s, part, sc, 4, 1, nb);
   hipLaunchKernelGGL(cg_direction_kernel, g, b, 0, s, z, p, sc, n);
   hipLaunchKernelGGL(cg_scalars_kernel, dim3(1), dim3(64), 0, s, sc, hist, it);
   return hipGetLastError();

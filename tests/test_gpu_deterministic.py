@@ -16,6 +16,9 @@ class by colour class, so that every node's sum is formed in a fixed order.
 * The batched filter in this mode runs problem by problem and equals the
   individual deterministic filters bitwise; one cell per side (a cell that
   shares nodes with its own periodic images) is refused.
+* The Hartree solve and the whole SCF loop give the same bits twice, and the
+  atomic path agrees to the CG tolerance (1e-9 on v_H) and to the SCF
+  tolerance (1e-6 on rho and mu).
 """
 import numpy as np
 import pytest
@@ -183,3 +186,44 @@ def test_one_cell_per_side_is_refused(ctx):
     ctx.set_deterministic(False)
     assert rc == EINVAL
     assert "2 cells per side" in ctx.lib.chfsi_last_error(ctx.h).decode()
+
+
+def test_deterministic_hartree_and_scf_are_bitwise_repeatable(ctx):
+    # the Hartree solve (stiffness by colour class, CG sums in a fixed order)
+    # and the whole SCF loop give the same bits twice; the atomic path agrees
+    # to the CG tolerance
+    s = workloads.small_system(2, 4, 2, seed=7, L=6.0)
+    op = lib.Operator(ctx, s)
+    M = op.M
+    m = fe.build_operator(s).Mdiag
+    rho0 = np.random.default_rng(4).uniform(0.01, 0.5, M)
+
+    def hartree():
+        vh = torch.zeros(M, dtype=torch.float64, device="cuda")
+        it, rr = op.hartree(torch.from_numpy(rho0).cuda(), vh, tol=1e-12, maxit=5000)
+        return it, vh.cpu().numpy()
+
+    def scf():
+        X = torch.from_numpy(workloads.start_block(M, 12, seed=8)).cuda()
+        rho = torch.from_numpy(np.full(M, 6.0 / np.sum(m))).cuda()
+        out = op.scf(X, rho, nwanted=8, n_buf=4, n_electrons=6.0, kT=0.01, m=20, tol=1e-9, maxit=120)
+        return out, rho.cpu().numpy()
+
+    it_a, vh_a = hartree()
+    out_a, rho_a = scf()
+    ctx.set_deterministic(True)
+    it1, vh1 = hartree()
+    it2, vh2 = hartree()
+    out1, rho1 = scf()
+    out2, rho2 = scf()
+    ctx.set_deterministic(False)
+    assert it1 == it2 and np.array_equal(_bits(vh1), _bits(vh2))
+    assert np.max(np.abs(vh1 - vh_a)) <= 1e-9 * np.max(np.abs(vh_a))
+    assert out1["converged"] and out2["converged"] and out_a["converged"]
+    assert out1["iters"] == out2["iters"]
+    assert np.array_equal(_bits(rho1), _bits(rho2))
+    assert np.array_equal(_bits(out1["theta"]), _bits(out2["theta"]))
+    assert np.array_equal(_bits(out1["residuals"]), _bits(out2["residuals"]))
+    assert out1["mu"] == out2["mu"]
+    assert np.max(np.abs(rho1 - rho_a)) <= 1e-6 * np.max(rho_a)
+    assert abs(out1["mu"] - out_a["mu"]) < 1e-6
