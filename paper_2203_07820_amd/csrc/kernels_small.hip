@@ -50,12 +50,16 @@ template <bool CPLX, typename Ptr> __device__ __forceinline__ void st_el(Ptr m, 
 // loses all orthogonality anyway); the factorisation stops there and S is
 // left as it was.
 // Right-looking factorisation in LDS (L row-major with a padded row), then
-// forward substitution with one column of L^-1 per thread (no barriers).
+// forward substitution with one column of L^-1 per thread (no barriers),
+// the column built in LDS: each entry depends on the column's earlier ones,
+// which read back from global memory would put an L2 round trip on every
+// step of the chain.
 template <bool CPLX>
 __global__ void __launch_bounds__(kSmallThreads)
 small_cholinv_kernel(const SmallBatch b) {
   constexpr int CF = CPLX ? 2 : 1;
   __shared__ double sm[kSmallMaxN * (kSmallMaxN + 1) * CF + 2 * kSmallMaxN];
+  __shared__ double xs[kSmallMaxN * kSmallMaxN * CF];   // L^-1, X[i][j] at (i kSmallMaxN + j) CF
   const gptr<double> S = to_global(b.mats ? b.mats[blockIdx.x] : b.mat0);
   const int n = b.dims ? b.dims[blockIdx.x] : b.n0;
   const gptr<int> info = to_global(b.info);
@@ -99,18 +103,21 @@ small_cholinv_kernel(const SmallBatch b) {
     __syncthreads();
   }
   // X = L^-1 (lower): column j by thread j, X[i][j] = (delta_ij - sum_{k=j}^{i-1} L[i][k] X[k][j]) / L[i][i],
-  // written straight into S's lower triangle (column j of X only depends on
-  // itself, and column j of S's lower triangle is no longer read)
+  // kept in xs (column j of X only depends on itself) and stored into S's
+  // lower triangle, whose column j is no longer read
   for (int j = tid; j < n; j += kSmallThreads) {
     for (int i = j; i < n; ++i) {
       cd s = {i == j ? 1.0 : 0.0, 0.0};
       for (int k = j; k < i; ++k) {
-        const cd p = cmul(ld_el<CPLX>(L, static_cast<int64_t>(i) * ld + k), ld_el<CPLX>(S, k + static_cast<int64_t>(j) * n));
+        const cd p = cmul(ld_el<CPLX>(L, static_cast<int64_t>(i) * ld + k),
+                          ld_el<CPLX>(xs, static_cast<int64_t>(k) * kSmallMaxN + j));
         s.re -= p.re;
         s.im -= p.im;
       }
       const double r = 1.0 / dg[i];
-      st_el<CPLX>(S, i + static_cast<int64_t>(j) * n, {s.re * r, s.im * r});
+      const cd x = {s.re * r, s.im * r};
+      st_el<CPLX>(xs, static_cast<int64_t>(i) * kSmallMaxN + j, x);
+      st_el<CPLX>(S, i + static_cast<int64_t>(j) * n, x);
     }
   }
   if (tid == 0) info[blockIdx.x] = 0;
