@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="c1: assemble H~X colour class by colour class (chfsi_set_deterministic)")
     ap.add_argument("--workload", default="c1",
                     choices=["c0", "c1", "c2", "c3", "c4", "kernels", "density", "rrgep", "scf", "small_batch"],
                     help="c1: FP64 pass at production size (the headline line); c2: mixed precision "
@@ -160,6 +162,8 @@ def run_c1(args):
     N, B, m = 256, 128, 30
     torch.cuda.set_device(0)
     ctx = lib.Context(0)
+    if args.deterministic:
+        ctx.set_deterministic(True)
     t0 = time.perf_counter()
     op = lib.Operator(ctx, sys_)
     t_build = time.perf_counter() - t0
@@ -208,14 +212,15 @@ def run_c1(args):
         "config": {"workload": "c1: FP64 Gamma-point ChFSI pass, 24^3 cells p=6 (M=2985984), 64 Gaussian "
                                "atoms with s/p projectors, N=256, B=128, m=30",
                    "M": op.M, "E": op.E, "mcell": op.mcell, "npairs": op.npairs, "N": N, "block": B,
-                   "degree": m},
+                   "degree": m, "assembly": "colour classes" if args.deterministic else "atomic"},
         "pass_time_s": pass_s,
         "hx_kernel_tflops": achieved,
         "hx_kernel_ms_avg": kms / launches if launches else None,
         "hx_kernel_launches": launches,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": profiled_traffic(), "traffic_unit": "HBM bytes per 128-column launch"},
+                     "traffic": None if args.deterministic else profiled_traffic(),
+                     "traffic_unit": "HBM bytes per 128-column launch"},
     }
     if not args.no_cpu_baseline:
         try:
