@@ -169,6 +169,8 @@ typedef struct {
   double max_resid;         /* max_{i<N} r_i after the last pass          */
   int32_t final_prec;       /* filter precision of the last pass          */
   int32_t prec_changes;     /* passes after which the precision was raised */
+  int32_t redrawn_columns;  /* start-block columns redrawn because the block
+                               was rank deficient (chfsi_solve; 0: none)   */
 } chfsi_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -317,6 +319,11 @@ int chfsi_rayleigh_ritz_split(chfsi_op* op, void* X, int64_t ncols, int64_t ld, 
  * N + n_buf each, resid nullable) receive the final Ritz values and residual
  * norms; stats (nullable) the timings and stats->b_upper the bound used.
  * Returns CHFSI_NOTCONV if a tolerance was requested and not met.
+ * A start block that is rank deficient to working precision (repeated or
+ * linearly dependent columns: its overlap matrix fails the Cholesky test)
+ * is repaired once: the columns from the first dependent one on are redrawn
+ * N(0, 1) from params->seed and stats->redrawn_columns says how many; a
+ * second failure returns CHFSI_ECHOL.
  * Checkpoint and resume: the state between passes is X and b (a and aL are
  * recomputed from the Ritz values by the initial Rayleigh-Ritz), so a solve
  * restarted from the X it returned, with params->b_upper = stats->b_upper,

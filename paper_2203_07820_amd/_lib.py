@@ -55,7 +55,7 @@ class Stats(C.Structure):
         ("t_rr", C.c_double), ("t_total", C.c_double), ("passes", C.c_int32),
         ("hx_columns", C.c_int64), ("hx_flops", C.c_double), ("b_upper", C.c_double),
         ("a_last", C.c_double), ("aL_last", C.c_double), ("max_resid", C.c_double),
-        ("final_prec", C.c_int32), ("prec_changes", C.c_int32),
+        ("final_prec", C.c_int32), ("prec_changes", C.c_int32), ("redrawn_columns", C.c_int32),
     ]
 
 

@@ -376,8 +376,11 @@ int read_info(chfsi_ctx* ctx, rocblas_int* dinfo, int* info) {
   return 0;
 }
 
-// CholGS: Xout = X L^-H with S = X^H X = L L^H.  Xout may not alias X.
-int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo, int64_t N, double* L_host) {
+// CholGS: Xout = X L^-H with S = X^H X = L L^H.  Xout may not alias X.  On
+// CHFSI_ECHOL, *bad_col (nullable) receives the first column that is a
+// combination of the earlier ones to working precision.
+int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo, int64_t N, double* L_host,
+           int64_t* bad_col = nullptr) {
   chfsi_ctx* ctx = op->ctx;
   const bool cplx = op->t.cplx;
   const int cf = cplx ? 2 : 1;
@@ -403,9 +406,11 @@ int cholgs(chfsi_op* op, const double* X, int64_t ldx, double* Xout, int64_t ldo
     RB_TRY(ctx, rocsolver_dpotrf(ctx->blas, rocblas_fill_lower, n, S, n, static_cast<rocblas_int*>(dinfo)));
   }
   CHECK(read_info(ctx, static_cast<rocblas_int*>(dinfo), &info));
-  if (info != 0)
+  if (info != 0) {
+    if (bad_col) *bad_col = info - 1;   // the leading minor of order info fails
     return fail(ctx, CHFSI_ECHOL, "overlap matrix is not positive definite (leading minor " + std::to_string(info) +
                                       ")");
+  }
   if (L_host) {
     std::vector<double> Lcm(static_cast<size_t>(N) * N * cf);
     HIP_TRY(ctx, hipMemcpyAsync(Lcm.data(), S, Lcm.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -2250,8 +2255,25 @@ int chfsi_solve(chfsi_op* op, const chfsi_params* prm, void* Xv, int64_t ld, dou
   CHECK(ws_get(ctx, WS_X2, static_cast<size_t>(t.M) * N * 8 * cf, &X2v));
   double* X2 = static_cast<double*>(X2v);
   std::vector<double> th(N), r(N);
-  // initial CholGS + RR: X -> X2 (orthonormal) -> X (Ritz vectors)
-  CHECK(cholgs(op, X, ld, X2, N, N, nullptr));
+  // initial CholGS + RR: X -> X2 (orthonormal) -> X (Ritz vectors).  A start
+  // block that is rank deficient to working precision (repeated or dependent
+  // columns) is repaired once: its columns from the first dependent one on
+  // are redrawn N(0, 1) from the seed, and the CholGS is repeated.
+  int64_t bad = -1;
+  const int rc0 = cholgs(op, X, ld, X2, N, N, nullptr, &bad);
+  if (rc0 == CHFSI_ECHOL && bad >= 0 && bad < N) {
+    const int64_t nr = (N - bad) * cf;
+    std::vector<double> h(static_cast<size_t>(t.M) * nr);
+    SplitMix g{prm->seed ^ 0x7265647261770000ULL};
+    for (auto& x : h) x = g.normal();
+    HIP_TRY(ctx, hipMemcpy2DAsync(X + bad * cf, ld * cf * 8, h.data(), nr * 8, nr * 8, t.M, hipMemcpyHostToDevice,
+                                  ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    st.redrawn_columns = static_cast<int32_t>(N - bad);
+    CHECK(cholgs(op, X, ld, X2, N, N, nullptr));
+  } else if (rc0 < 0) {
+    return rc0;
+  }
   CHECK(rayleigh_ritz(op, X2, N, X, ld, N, th.data(), r.data()));
   st.hx_columns += N;
   auto max_r = [&]() {

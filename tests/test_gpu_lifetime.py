@@ -9,6 +9,9 @@
 * An upper bound b below lambda_max makes the filter amplify the top of the
   spectrum (Section 3.1): a Ritz value then exceeds b, which no valid bound
   allows (Cauchy interlacing), and the solve stops with CHFSI_EDIVERGE.
+* A rank-deficient start block (a repeated column, or all zeros) is
+  repaired once by chfsi_solve: the columns from the first dependent one on
+  are redrawn, and the solve converges to the dense eigenvalues.
 """
 import ctypes as C
 import os
@@ -147,4 +150,33 @@ def test_bound_below_lambda_max_returns_ediverge():
     with pytest.raises(lib.ChfsiError) as ei:
         op.solve(X, N, m=10, block=N, fixed_passes=3, b_upper=0.5 * lam[-1])
     assert ei.value.code == EDIVERGE, str(ei.value)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["repeated", "zero"])
+def test_rank_deficient_start_block_is_redrawn_once(case):
+    # a repeated column (column 10 = column 3) fails the Cholesky test at the
+    # leading minor of order 11: columns 10.. are redrawn; an all-zero block
+    # fails at once and is redrawn whole.  Either way the solve then reaches
+    # the dense eigenvalues.  chfsi_orthonormalize itself still refuses such
+    # a block (CHFSI_ECHOL, tested with the CholGS parity).
+    ctx = lib.Context(0)
+    s = workloads.small_system(2, 4, 2, seed=12, has_proj=True)
+    op = lib.Operator(ctx, s)
+    lam = np.linalg.eigvalsh(fe.assemble(fe.build_operator(s)).toarray())
+    N, nbuf = 16, 6
+    X0 = workloads.start_block(op.M, N + nbuf, seed=13)
+    if case == "repeated":
+        X0[:, 10] = X0[:, 3]
+    else:
+        X0[:] = 0.0
+    X = torch.from_numpy(X0).cuda()
+    th, r, st = op.solve(X, N, m=16, block=N + nbuf, n_buf=nbuf, tol=1e-9, max_passes=80, seed=5)
+    assert st["redrawn_columns"] == (N + nbuf - 10 if case == "repeated" else N + nbuf)
+    assert st["converged"]
+    assert np.max(np.abs(th[:N] - lam[:N])) < 1e-8
+    # a healthy block is left alone
+    X = torch.from_numpy(workloads.start_block(op.M, N + nbuf, seed=13)).cuda()
+    _, _, st2 = op.solve(X, N, m=16, block=N + nbuf, n_buf=nbuf, fixed_passes=2)
+    assert st2["redrawn_columns"] == 0
     ctx.close()
