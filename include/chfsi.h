@@ -477,7 +477,8 @@ int chfsi_filter_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, void* 
  * prec_switch must be 0.  History arrays are filled per problem, with times
  * measured from the start of the call.  A problem stops when its own
  * criterion is met; the others continue.  Returns CHFSI_NOTCONV if any
- * tolerance was not met.  Synchronous. */
+ * tolerance was not met; a rank-deficient start block is not redrawn here
+ * (CHFSI_ECHOL).  Synchronous. */
 int chfsi_solve_batched(chfsi_ctx* ctx, int32_t n, chfsi_op* const* ops, const chfsi_params* params,
                         void* const* X, const int64_t* ld, double* const* theta, double* const* resid,
                         chfsi_stats* stats, int32_t use_graph);
