@@ -180,14 +180,24 @@ __global__ void fill_kernel(T* dst, int64_t rows, int64_t cols, int64_t ld) {
   }
 }
 
+// dst[r][c] = src[r][c] for a rows x cols block.  Blocks of at most 256
+// columns: each workgroup step covers 256 / cols whole rows (thread = row in
+// the step, column), so no thread divides a 64-bit index; wider blocks: one
+// row per step, columns strided by 256.
 template <typename TD, typename TS>
-__global__ void convert_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds, int64_t rows,
-                               int64_t cols) {
-  const int64_t total = rows * cols;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t r = i / cols, c = i % cols;
-    dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
+__global__ void __launch_bounds__(256) convert_kernel(TD* dst, int64_t ldd, const TS* src, int64_t lds,
+                                                      int64_t rows, int ncol) {
+  if (ncol <= 256) {
+    const int rpb = 256 / ncol;
+    const int tr = threadIdx.x / ncol, c = threadIdx.x % ncol;
+    if (tr >= rpb) return;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * rpb;
+#pragma unroll 4
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * rpb + tr; r < rows; r += step)
+      dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
+  } else {
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
+      for (int c = threadIdx.x; c < ncol; c += 256) dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
   }
 }
 
@@ -253,20 +263,22 @@ hipError_t launch_fill(void* dst, int64_t rows, int64_t cols, int64_t ld, int pr
 hipError_t launch_convert(void* dst, int64_t ldd, int dprec, const void* src, int64_t lds, int sprec,
                           int64_t rows, int64_t cols, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (cols > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned g = grid_for(rows * cols);
   const bool dd = is_double(dprec), sd = is_double(sprec);
+  const int ncol = static_cast<int>(cols);
   if (dd && sd)
     hipLaunchKernelGGL((convert_kernel<double, double>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
-                       static_cast<const double*>(src), lds, rows, cols);
+                       static_cast<const double*>(src), lds, rows, ncol);
   else if (dd && !sd)
     hipLaunchKernelGGL((convert_kernel<double, float>), dim3(g), dim3(256), 0, s, static_cast<double*>(dst), ldd,
-                       static_cast<const float*>(src), lds, rows, cols);
+                       static_cast<const float*>(src), lds, rows, ncol);
   else if (!dd && sd)
     hipLaunchKernelGGL((convert_kernel<float, double>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
-                       static_cast<const double*>(src), lds, rows, cols);
+                       static_cast<const double*>(src), lds, rows, ncol);
   else
     hipLaunchKernelGGL((convert_kernel<float, float>), dim3(g), dim3(256), 0, s, static_cast<float*>(dst), ldd,
-                       static_cast<const float*>(src), lds, rows, cols);
+                       static_cast<const float*>(src), lds, rows, ncol);
   return hipGetLastError();
 }
 
