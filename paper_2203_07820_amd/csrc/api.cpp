@@ -298,10 +298,10 @@ void cheb_coeffs(int m, double a, double b, double aL, double* c, std::vector<do
 
 // Filter one block already converted into R0 (storage of prec, ld = ncols).
 // Returns the index of the buffer holding the result.
-// Filters the block held in R[0] (ncols columns, leading dimension ldr) with
-// the buffers R[1..3]; the result is in R[*out_idx].
-int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int64_t ldr, int m, double a, double b,
-                 double aL, int* out_idx) {
+// Filters the block held in R[0] (ncols columns, leading dimensions ldr[i])
+// with the buffers R[1..3]; the result is in R[*out_idx].
+int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, const int64_t ldr[4], int m, double a,
+                 double b, double aL, int* out_idx) {
   chfsi_ctx* ctx = op->ctx;
   const int cf = op->t.cplx ? 2 : 1;
   const int64_t M = op->t.M;
@@ -309,11 +309,11 @@ int filter_block(chfsi_op* op, int prec, void* const R[4], int64_t ncols, int64_
   std::vector<double> al, be;
   cheb_coeffs(m, a, b, aL, &c, al, be);
   const int sp = storage_of(prec);
-  for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R[i], M, ncols * cf, ldr * cf, sp, ctx->stream));
-  CHECK(hx_step(op, prec, R[0], ldr, nullptr, ldr, R[1], ldr, ncols, al[0], c, 0.0, false));
+  for (int i = 1; i < 4; ++i) HIP_TRY(ctx, launch_fill(R[i], M, ncols * cf, ldr[i] * cf, sp, ctx->stream));
+  CHECK(hx_step(op, prec, R[0], ldr[0], nullptr, ldr[0], R[1], ldr[1], ncols, al[0], c, 0.0, false));
   for (int i = 2; i <= m; ++i) {
-    CHECK(hx_step(op, prec, R[(i - 1) % 4], ldr, R[(i - 2) % 4], ldr, R[i % 4], ldr, ncols, al[i - 1], c,
-                  be[i - 1], true));
+    const int k = (i - 1) % 4, p = (i - 2) % 4, t = i % 4;
+    CHECK(hx_step(op, prec, R[k], ldr[k], R[p], ldr[p], R[t], ldr[t], ncols, al[i - 1], c, be[i - 1], true));
   }
   *out_idx = m % 4;
   return 0;
@@ -333,14 +333,27 @@ int do_filter(chfsi_op* op, void* X, int64_t ncols, int64_t ld, int m, double a,
   const int64_t ldmax = (block + 3) / 4 * 4;
   void* R[4];
   for (int i = 0; i < 4; ++i) CHECK(ws_get(ctx, WS_R0 + i, static_cast<size_t>(t.M) * ldmax * eb, &R[i]));
+  // in the block's own storage type the caller's block itself is the first
+  // buffer of the rotation (no copy in; the owners clear its rows at step 2
+  // for reuse as a target, and the result, unless it lands there, is copied
+  // back over it)
+  const bool in_place = sp == xprec;
   for (int64_t c0 = 0; c0 < ncols; c0 += block) {
     const int64_t nb = std::min<int64_t>(block, ncols - c0);
-    const int64_t ldr = (nb + 3) / 4 * 4;
+    const int64_t ldw = (nb + 3) / 4 * 4;
     double* Xb = static_cast<double*>(X) + c0 * cf;
-    HIP_TRY(ctx, launch_convert(R[0], ldr * cf, sp, Xb, ld * cf, xprec, t.M, nb * cf, ctx->stream));
+    void* Rb[4] = {R[0], R[1], R[2], R[3]};
+    int64_t ldr[4] = {ldw, ldw, ldw, ldw};
+    if (in_place) {
+      Rb[0] = Xb;
+      ldr[0] = ld;
+    } else {
+      HIP_TRY(ctx, launch_convert(R[0], ldw * cf, sp, Xb, ld * cf, xprec, t.M, nb * cf, ctx->stream));
+    }
     int idx = 0;
-    CHECK(filter_block(op, prec, R, nb, ldr, m, a, b, aL, &idx));
-    HIP_TRY(ctx, launch_convert(Xb, ld * cf, xprec, R[idx], ldr * cf, sp, t.M, nb * cf, ctx->stream));
+    CHECK(filter_block(op, prec, Rb, nb, ldr, m, a, b, aL, &idx));
+    if (!(in_place && idx == 0))
+      HIP_TRY(ctx, launch_convert(Xb, ld * cf, xprec, Rb[idx], ldr[idx] * cf, sp, t.M, nb * cf, ctx->stream));
   }
   return 0;
 }
