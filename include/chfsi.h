@@ -401,8 +401,9 @@ int chfsi_op_set_potential(chfsi_op* op, const double* V);
  * The CG scalars stay on the device and the residual is checked every 8
  * iterations, so the count is a multiple of 8 (or maxit) and the solve may
  * run up to 7 iterations past tol.  iters / relres (nullable) receive the
- * iteration count and the final relative residual.  Real operators with a
- * nodal potential only.  Returns CHFSI_NOTCONV if tol was not reached,
+ * iteration count and the final relative residual.  Operators with a nodal
+ * potential (real or Bloch: the problem depends on the mesh only).  Returns
+ * CHFSI_NOTCONV if tol was not reached,
  * CHFSI_EDIVERGE on a non-finite residual.  Synchronous. */
 int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32_t maxit, int32_t* iters,
                   double* relres);
@@ -420,7 +421,8 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
  * mixing of the density (weight beta, the last `depth` differences,
  * M-weighted inner products).  Stops when the M-weighted norm of
  * rho_out - rho_in falls below tol or after maxit steps.
- * X: device, M x ld FP64, nwanted + n_buf columns (start block in, Ritz
+ * X: device, M x ld FP64 (complex double for a Bloch operator: one k-point,
+ * its density |psi|^2 real), nwanted + n_buf columns (start block in, Ritz
  * vectors out); rho: device, M values (initial density in; the converged
  * output density, or the last mixed density if not converged, out); theta:
  * host, nwanted + n_buf Ritz values of the last step; mu_out, res_hist
@@ -435,8 +437,9 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
  * f_i = 0), nfr covering every state whose vacancy 1 - f_i exceeded 1e-14
  * at the previous step, plus two; 2 = the same with the mixed-precision
  * blocks of chfsi_rayleigh_ritz_split (the paper's form).  In modes 1 and 2
- * X holds the orthonormal basis (not Ritz vectors) on return.  Real
- * operators with a nodal potential; 0 < n_electrons < 2 nwanted.  On
+ * X holds the orthonormal basis (not Ritz vectors) on return.  Operators
+ * with a nodal potential (V_ext is the build-time potential without
+ * |k|^2 / 2); 0 < n_electrons < 2 nwanted.  On
  * return the operator holds the last step's effective potential (restore
  * the original with chfsi_op_set_potential if needed).  Returns
  * CHFSI_NOTCONV if tol was not met.  Synchronous. */

@@ -1178,8 +1178,11 @@ int scf_tables(chfsi_op* op) {
   double* sqm = vext + M;
   double* mm = sqm + M;
   double* kd = mm + M;
+  // the build-time potential without the |k|^2 / 2 of a Bloch operator
+  // (chfsi_op_set_potential adds it back)
+  const double k2 = 0.5 * (t.k[0] * t.k[0] + t.k[1] * t.k[1] + t.k[2] * t.k[2]);
   for (int64_t j = 0; j < M; ++j) {
-    vext[j] = t.vdiag[j];
+    vext[j] = t.vdiag[j] - k2;
     sqm[j] = 1.0 / t.dscale[j];
     mm[j] = sqm[j] * sqm[j];
   }
@@ -1951,8 +1954,7 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
   if (!op) return CHFSI_EINVAL;
   chfsi_ctx* ctx = op->ctx;
   if (!rho || !vH) return fail(ctx, CHFSI_EINVAL, "null density or output");
-  if (op->t.cplx || op->astride != 0)
-    return fail(ctx, CHFSI_EINVAL, "the Hartree solve uses a real operator with a nodal potential");
+  if (op->astride != 0) return fail(ctx, CHFSI_EINVAL, "the Hartree solve uses an operator with a nodal potential");
   if (!(tol > 0.0) || maxit < 1) return fail(ctx, CHFSI_EINVAL, "need tol > 0 and maxit >= 1");
   void* w;
   CHECK(ws_get(ctx, WS_SCF, static_cast<size_t>(op->t.M) * 6 * 8, &w));
@@ -1973,8 +1975,7 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   const HostTables& t = op->t;
   const int64_t N = static_cast<int64_t>(nwanted) + n_buf;
   CHECK(check_block(op, Xv, N, ld));
-  if (t.cplx || op->astride != 0)
-    return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on a real operator with a nodal potential");
+  if (op->astride != 0) return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on an operator with a nodal potential");
   if (!rho || !theta) return fail(ctx, CHFSI_EINVAL, "null density or theta");
   if (nwanted < 1 || n_buf < 0 || m < 1 || maxit < 1 || depth < 0 || depth > 16 || !(beta > 0.0) ||
       !(kT > 0.0) || !(tol > 0.0) || !(n_electrons > 0.0) || !(n_electrons < 2.0 * nwanted) || rr_mode < 0 ||
@@ -2014,7 +2015,10 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   prm.n_buf = n_buf;
   prm.m = m;
   prm.block = block > 0 ? block : static_cast<int32_t>(N);
-  prm.filter_prec = CHFSI_F64;
+  // one k-point: the real operator at Gamma, the complex Bloch operator H(k)
+  // elsewhere (its density is real: |psi|^2 of the complex states)
+  const int xprec = t.cplx ? CHFSI_C128 : CHFSI_F64;
+  prm.filter_prec = xprec;
   std::vector<double> th(N), f(nwanted), occ(nwanted), wfr;
   int hist = 0, it = 0;
   bool conv = false;
@@ -2028,7 +2032,7 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   double b0 = 0.0;                    // Lanczos bound of the first step's operator
   if (rr_mode > 0) {
     void* pv;
-    CHECK(ws_get(ctx, WS_PFR, static_cast<size_t>(M) * N * 8, &pv));
+    CHECK(ws_get(ctx, WS_PFR, static_cast<size_t>(M) * N * 8 * (t.cplx ? 2 : 1), &pv));
     Pfr = static_cast<double*>(pv);
   }
   for (it = 0; it < maxit; ++it) {
@@ -2074,7 +2078,7 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
       // Rayleigh-Ritz through the generalised problem with spectrum
       // splitting (Algorithm 2): X becomes the orthonormal basis Psi_o,
       // Pfr the nfr highest Ritz vectors
-      CHECK(do_filter(op, Xv, N, ld, m, a, b, aL, CHFSI_F64, prm.block));
+      CHECK(do_filter(op, Xv, N, ld, m, a, b, aL, xprec, prm.block));
       CHECK(rrgep_split(op, static_cast<double*>(Xv), ld, N, nfr, rr_mode == 2, th.data(), Pfr, nfr));
       CHECK(check_ritz(ctx, th.data(), nullptr, N, b));
     }

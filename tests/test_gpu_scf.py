@@ -8,6 +8,10 @@ change: FP64 products, 1e-12.  SCF: the fixed point does not depend on the
 eigensolver or the mixing path; both loops stop at an M-norm residual of
 1e-9, the GPU one with ChFSI subspaces converged alongside, so densities
 agree to 1e-6 of max rho, Ritz values and the Fermi level to 1e-6 Ha.
+One k-point on a Bloch operator (no oracle loop at k != 0: parity unpinned
+there): the Hartree solve equals Gamma's (it depends on the mesh only), and
+the loops at k and -k, whose Hamiltonians are complex conjugates, agree to
+the loop tolerance.
 """
 import numpy as np
 import pytest
@@ -119,3 +123,46 @@ def test_scf_rejects_bad_arguments(ctx):
     opq = lib.Operator(ctx, s, potential="quadrature")
     with pytest.raises(lib.ChfsiError):
         opq.set_potential(rho)
+
+
+def test_hartree_of_a_bloch_operator_equals_gamma(ctx):
+    # the Hartree problem depends on the mesh only: a k != 0 operator of the
+    # same system gives the Gamma operator's potential
+    s0 = workloads.small_system(2, 4, 2, seed=3, L=6.0)
+    sk = workloads.small_system(2, 4, 2, seed=3, L=6.0, k=(0.3, -0.1, 0.2))
+    op0, opk = lib.Operator(ctx, s0), lib.Operator(ctx, sk)
+    assert opk.is_complex and not op0.is_complex
+    rho = np.random.default_rng(4).uniform(0.01, 0.5, op0.M)
+    v0 = torch.empty(op0.M, dtype=torch.float64, device="cuda")
+    vk = torch.empty(op0.M, dtype=torch.float64, device="cuda")
+    op0.hartree(dev(rho), v0, tol=1e-12)
+    opk.hartree(dev(rho), vk, tol=1e-12)
+    assert np.max(np.abs(vk.cpu().numpy() - v0.cpu().numpy())) <= 1e-11 * np.max(np.abs(v0.cpu().numpy()))
+
+
+@pytest.mark.parametrize("rr_mode", [0, 2])
+def test_scf_at_k_and_minus_k_agree(ctx, rr_mode):
+    # one k-point SCF on the complex Bloch operator: H(-k) is the complex
+    # conjugate of H(k) (time reversal), so the loops at k and -k reach the
+    # same density, Ritz values and Fermi level; the density holds N_e
+    # electrons, and the upper Ritz values differ from the Gamma-point loop's
+    def run(k):
+        s = workloads.small_system(2, 4, 2, seed=7, L=6.0, k=k)
+        op = lib.Operator(ctx, s)
+        m = fe.build_operator(s).Mdiag
+        X = dev(workloads.start_block(op.M, 12, seed=8, complex_=op.is_complex))
+        rho = dev(np.full(op.M, 6.0 / np.sum(m)))
+        out = op.scf(X, rho, nwanted=8, n_buf=4, n_electrons=6.0, kT=0.01, m=20, beta=0.3, depth=4, tol=1e-9,
+                     maxit=120, rr_mode=rr_mode)
+        return out, rho.cpu().numpy(), m
+    k = (0.35, -0.2, 0.1)
+    a, ra, m = run(k)
+    b, rb, _ = run(tuple(-x for x in k))
+    g, rg, _ = run((0.0, 0.0, 0.0))
+    assert a["converged"] and b["converged"] and g["converged"]
+    assert abs(float(np.sum(m * ra)) - 6.0) < 1e-9
+    assert np.max(np.abs(ra - rb)) <= 1e-7 * np.max(ra)
+    assert np.max(np.abs(a["theta"][:8] - b["theta"][:8])) < 1e-7
+    assert abs(a["mu"] - b["mu"]) < 1e-7
+    # the Bloch phase acts: the upper (delocalised) states move with k
+    assert np.max(np.abs(a["theta"] - g["theta"])) > 1e-3
