@@ -447,6 +447,24 @@ int chfsi_scf(chfsi_op* op, void* X, int64_t ld, int32_t nwanted, int32_t n_buf,
               int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
               double* rho, double* theta, double* mu_out, double* res_hist, int32_t* iters);
 
+/* The same loop with k-point sampling: nk operators of one mesh (the same
+ * system at nk Bloch vectors, e.g. a Monkhorst-Pack set), each with its
+ * block X[k] (ld[k]; nwanted + n_buf columns, complex for k != 0) and
+ * weight weights[k] (non-negative, normalised to sum 1 here; NULL: equal).
+ * The density is sum_k w_k sum_i 2 f_ki |psi_ki|^2, the Fermi level is
+ * taken over all k-points' nwanted lowest Ritz values with their weights
+ * (n_electrons per cell: 0 < n_electrons < 2 nwanted), the Hartree
+ * potential, the mixing and the stopping rule are those of chfsi_scf, and
+ * the eigensolver step (passes, spectrum splitting with its own split per
+ * k-point) runs for each k-point in turn.  theta: nk host arrays of
+ * nwanted + n_buf values.  chfsi_scf is this call with nk = 1.
+ * Synchronous. */
+int chfsi_scf_kpoints(chfsi_ctx* ctx, int32_t nk, chfsi_op* const* ops, void* const* X, const int64_t* ld,
+                      const double* weights, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
+                      int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol,
+                      int32_t maxit, double* rho, double* const* theta, double* mu_out, double* res_hist,
+                      int32_t* iters);
+
 /* ---- batched filter (many operators, one persistent launch per step) -------
  * Applies the filter of chfsi_filter() to n independent blocks at once:
  * block q is X[q] (device, double / complex double, ncols[q] columns, ld[q])

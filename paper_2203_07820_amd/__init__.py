@@ -178,6 +178,32 @@ class Context:
                 stats[q]["history"] = _trim_history(hists[q], stats[q]["passes"])
         return th, rs, stats
 
+    def scf_kpoints(self, ops, Xs, rho, nwanted: int, n_buf: int, n_electrons: float, kT: float, weights=None,
+                    m: int = 20, block: int = 0, beta: float = 0.3, depth: int = 4, tol: float = 1e-8,
+                    maxit: int = 60, rr_mode: int = 2):
+        """chfsi_scf_kpoints: one SCF loop over the k-points `ops` (one mesh),
+        blocks `Xs` (device tensors), weights (None: equal)."""
+        n = len(ops)
+        VP = C.c_void_p * n
+        I64 = C.c_int64 * n
+        lds = []
+        for X in Xs:
+            ncols, ld = _ld_cols(X)
+            if ncols != nwanted + n_buf:
+                raise ValueError("each X must have nwanted + n_buf columns")
+            lds.append(ld)
+        ths = [np.zeros(nwanted + n_buf) for _ in range(n)]
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        hist = np.zeros(maxit)
+        mu, it = C.c_double(), C.c_int32()
+        rc = self.check(self.lib.chfsi_scf_kpoints(
+            self.h, n, VP(*[o.h for o in ops]), VP(*[_tptr(X) for X in Xs]), I64(*lds),
+            None if w is None else C.c_void_p(w.ctypes.data), int(nwanted), int(n_buf), int(m), int(block), int(rr_mode),
+            float(n_electrons), float(kT), float(beta), int(depth), float(tol), int(maxit), _tptr(rho),
+            VP(*[C.c_void_p(t.ctypes.data) for t in ths]), C.byref(mu), _dptr(hist), C.byref(it)), allow=(0, 1))
+        return {"theta": ths, "mu": mu.value, "iters": it.value, "residuals": hist[:it.value],
+                "converged": rc == 0}
+
     def autotune(self, p: int, prec: int, block: int, cache_json: Optional[str] = None):
         self.check(self.lib.chfsi_autotune(self.h, cache_json.encode() if cache_json else None, int(p), int(prec),
                                            int(block)))

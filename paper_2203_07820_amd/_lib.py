@@ -23,7 +23,7 @@ EXPORTS = [
     "chfsi_mlp_set_norm", "chfsi_mlp_forward", "chfsi_mlp_loss_grad", "chfsi_mlp_train_step",
     "chfsi_initial_block", "chfsi_next_prec", "chfsi_fermi_level", "chfsi_density",
     "chfsi_rayleigh_ritz_split", "chfsi_op_build_quadrature", "chfsi_op_set_potential", "chfsi_hartree",
-    "chfsi_scf",
+    "chfsi_scf", "chfsi_scf_kpoints",
 ]
 
 
@@ -122,6 +122,8 @@ def load() -> C.CDLL:
         "chfsi_hartree": (C.c_int, [vp, vp, vp, dbl, i32, C.POINTER(i32), pd]),
         "chfsi_scf": (C.c_int, [vp, vp, i64, i32, i32, i32, i32, i32, dbl, dbl, dbl, i32, dbl, i32, vp, pd, pd, pd,
                                 C.POINTER(i32)]),
+        "chfsi_scf_kpoints": (C.c_int, [vp, i32, vp, vp, vp, vp, i32, i32, i32, i32, i32, dbl, dbl, dbl, i32, dbl,
+                                        i32, vp, vp, pd, pd, C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1967,16 +1967,28 @@ int chfsi_hartree(chfsi_op* op, const double* rho, double* vH, double tol, int32
   return rr <= tol ? 0 : CHFSI_NOTCONV;
 }
 
-int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
-              int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
-              double* rho, double* theta, double* mu_out, double* res_hist, int32_t* iters) {
-  if (!op) return CHFSI_EINVAL;
-  chfsi_ctx* ctx = op->ctx;
+// The SCF loop over nk k-points of one mesh (nk = 1: chfsi_scf): operator,
+// block and normalised weight of each k-point; the density, the Hartree
+// potential and the mixing are shared, the eigensolver step runs per k-point
+// and the Fermi level is taken over all k-points' Ritz values with their
+// weights.
+static int scf_loop(chfsi_ctx* ctx, int nk, chfsi_op* const* ops, void* const* Xvs, const int64_t* lds,
+                    const double* wk, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block, int32_t rr_mode,
+                    double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
+                    double* rho, double* const* thetas, double* mu_out, double* res_hist, int32_t* iters) {
+  chfsi_op* op = ops[0];
   const HostTables& t = op->t;
   const int64_t N = static_cast<int64_t>(nwanted) + n_buf;
-  CHECK(check_block(op, Xv, N, ld));
-  if (op->astride != 0) return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on an operator with a nodal potential");
-  if (!rho || !theta) return fail(ctx, CHFSI_EINVAL, "null density or theta");
+  for (int k = 0; k < nk; ++k) {
+    const chfsi_op* o = ops[k];
+    if (!o || o->ctx != ctx) return fail(ctx, CHFSI_EINVAL, "null operator, or one of another context");
+    if (o->t.M != t.M || o->t.ncell != t.ncell || o->t.p != t.p || o->t.L != t.L)
+      return fail(ctx, CHFSI_EINVAL, "the k-points of an SCF loop must share the mesh");
+    if (o->astride != 0) return fail(ctx, CHFSI_EINVAL, "the SCF loop runs on operators with a nodal potential");
+    CHECK(check_block(ops[k], Xvs[k], N, lds[k]));
+    if (!thetas[k]) return fail(ctx, CHFSI_EINVAL, "null theta");
+  }
+  if (!rho) return fail(ctx, CHFSI_EINVAL, "null density");
   if (nwanted < 1 || n_buf < 0 || m < 1 || maxit < 1 || depth < 0 || depth > 16 || !(beta > 0.0) ||
       !(kT > 0.0) || !(tol > 0.0) || !(n_electrons > 0.0) || !(n_electrons < 2.0 * nwanted) || rr_mode < 0 ||
       rr_mode > 2)
@@ -2015,25 +2027,25 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   prm.n_buf = n_buf;
   prm.m = m;
   prm.block = block > 0 ? block : static_cast<int32_t>(N);
-  // one k-point: the real operator at Gamma, the complex Bloch operator H(k)
+  // per k-point: the real operator at Gamma, the complex Bloch operator H(k)
   // elsewhere (its density is real: |psi|^2 of the complex states)
-  const int xprec = t.cplx ? CHFSI_C128 : CHFSI_F64;
-  prm.filter_prec = xprec;
-  std::vector<double> th(N), f(nwanted), occ(nwanted), wfr;
+  std::vector<std::vector<double>> th(nk, std::vector<double>(N));
+  std::vector<double> f(nwanted), occ(static_cast<size_t>(nk) * nwanted), wfr, thall(occ.size()), wall(occ.size());
   int hist = 0, it = 0;
   bool conv = false;
   double mu = 0.0;
   // spectrum splitting (rr_mode 1: FP64, 2: mixed precision): the nfr
   // highest Ritz vectors of each step, the states below them being fully
   // occupied (chosen from the previous step's occupations)
-  int nfr = static_cast<int>(N);
-  double* Pfr = nullptr;
+  std::vector<int> nfr(nk, static_cast<int>(N));
+  std::vector<double*> Pfr(nk, nullptr);
   std::vector<double> vhost(M), v0;   // effective potentials (host): this step's, the first step's
-  double b0 = 0.0;                    // Lanczos bound of the first step's operator
+  std::vector<double> b0(nk, 0.0);    // Lanczos bounds of the first step's operators
   if (rr_mode > 0) {
     void* pv;
-    CHECK(ws_get(ctx, WS_PFR, static_cast<size_t>(M) * N * 8 * (t.cplx ? 2 : 1), &pv));
-    Pfr = static_cast<double*>(pv);
+    const size_t per = static_cast<size_t>(M) * N * 2;   // doubles per k-point (complex room)
+    CHECK(ws_get(ctx, WS_PFR, per * nk * 8, &pv));
+    for (int k = 0; k < nk; ++k) Pfr[k] = static_cast<double*>(pv) + per * k;
   }
   for (it = 0; it < maxit; ++it) {
     // potential of the input density
@@ -2042,69 +2054,85 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
     // from the previous step's potential after the first step
     CHECK(hartree_solve(op, rin, vh, 1e-10, 5000, cg, &cgit, &cgr, it > 0));
     HIP_TRY(ctx, launch_veff(vext, vh, rin, V, M, st));
-    CHECK(chfsi_op_set_potential(op, V));
+    for (int k = 0; k < nk; ++k) CHECK(chfsi_op_set_potential(ops[k], V));
     // upper bound of the spectrum: Lanczos on the first step's operator;
     // later the potential only moves the diagonal, so by Weyl's inequality
     // lambda_max(H + dV) <= lambda_max(H) + max_j dV_j bounds it without
     // another Lanczos run
     HIP_TRY(ctx, hipMemcpyAsync(vhost.data(), V, M * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
-    double b = 0.0;
+    double dmax = 0.0;
     if (it == 0) {
-      CHECK(do_bounds(op, 20, nullptr, nullptr, 12345, &b0, nullptr));
+      for (int k = 0; k < nk; ++k) CHECK(do_bounds(ops[k], 20, nullptr, nullptr, 12345, &b0[k], nullptr));
       v0 = vhost;
-      b = b0;
     } else {
-      double dmax = 0.0;
       for (int64_t j = 0; j < M; ++j) dmax = std::max(dmax, vhost[j] - v0[j]);
-      b = b0 + dmax;
     }
-    // eigensolver: the first step orthonormalises the start block and runs
-    // four passes, later steps one pass from the previous subspace
-    if (it == 0) {
-      CHECK(chfsi_orthonormalize(op, Xv, N, ld, nullptr));
-      CHECK(chfsi_rayleigh_ritz(op, Xv, N, ld, th.data(), nullptr));
+    for (int k = 0; k < nk; ++k) {
+      chfsi_op* opk = ops[k];
+      void* Xv = Xvs[k];
+      const int64_t ld = lds[k];
+      std::vector<double>& thk = th[k];
+      const int xprec = opk->t.cplx ? CHFSI_C128 : CHFSI_F64;
+      prm.filter_prec = xprec;
+      const double b = b0[k] + dmax;
+      // eigensolver: the first step orthonormalises the start block and runs
+      // four passes, later steps one pass from the previous subspace
+      if (it == 0) {
+        CHECK(chfsi_orthonormalize(opk, Xv, N, ld, nullptr));
+        CHECK(chfsi_rayleigh_ritz(opk, Xv, N, ld, thk.data(), nullptr));
+      }
+      const bool split = rr_mode > 0 && it > 0;
+      const int passes = it == 0 ? 4 : 1;
+      for (int ps = 0; ps < passes; ++ps) {
+        const double a = thk[N - 1], aL = thk[0];
+        if (!(a < b)) return fail(ctx, CHFSI_EDIVERGE, "Ritz values above the spectrum bound");
+        if (!split) {
+          CHECK(chfsi_pass(opk, &prm, Xv, ld, a, b, aL, thk.data(), nullptr));
+          continue;
+        }
+        // Algorithm 1's eigensolver step in the paper's form: the filter, then
+        // Rayleigh-Ritz through the generalised problem with spectrum
+        // splitting (Algorithm 2): X becomes the orthonormal basis Psi_o,
+        // Pfr the nfr highest Ritz vectors
+        CHECK(do_filter(opk, Xv, N, ld, m, a, b, aL, xprec, prm.block));
+        CHECK(rrgep_split(opk, static_cast<double*>(Xv), ld, N, nfr[k], rr_mode == 2, thk.data(), Pfr[k], nfr[k]));
+        CHECK(check_ritz(ctx, thk.data(), nullptr, N, b));
+      }
     }
+    // occupations over all k-points (weights w_k), and the output density
+    for (int k = 0; k < nk; ++k)
+      for (int i = 0; i < nwanted; ++i) {
+        thall[static_cast<size_t>(k) * nwanted + i] = th[k][i];
+        wall[static_cast<size_t>(k) * nwanted + i] = wk[k];
+      }
+    CHECK(chfsi_fermi_level(thall.data(), nk * nwanted, wall.data(), n_electrons, kT, &mu, occ.data()));
     const bool split = rr_mode > 0 && it > 0;
-    const int passes = it == 0 ? 4 : 1;
-    for (int ps = 0; ps < passes; ++ps) {
-      const double a = th[N - 1], aL = th[0];
-      if (!(a < b)) return fail(ctx, CHFSI_EDIVERGE, "Ritz values above the spectrum bound");
+    for (int k = 0; k < nk; ++k) {
+      const double* ok = occ.data() + static_cast<size_t>(k) * nwanted;
       if (!split) {
-        CHECK(chfsi_pass(op, &prm, Xv, ld, a, b, aL, th.data(), nullptr));
-        continue;
+        for (int i = 0; i < nwanted; ++i) f[i] = 2.0 * wk[k] * ok[i];
+        CHECK(chfsi_density(ops[k], Xvs[k], nwanted, lds[k], f.data(), CHFSI_RHO_NODES, k > 0, rout));
+      } else {
+        // Algorithm 3's split form: every basis vector counted fully
+        // occupied, then the nfr highest Ritz vectors corrected by
+        // 2 (f_i - 1) (buffer states: f_i = 0); exact when f_i = 1 below
+        // the split
+        std::vector<double> two(N, 2.0 * wk[k]);
+        CHECK(chfsi_density(ops[k], Xvs[k], N, lds[k], two.data(), CHFSI_RHO_NODES, k > 0, rout));
+        wfr.assign(nfr[k], 0.0);
+        for (int j = 0; j < nfr[k]; ++j) {
+          const int64_t i = N - nfr[k] + j;
+          wfr[j] = 2.0 * wk[k] * ((i < nwanted ? ok[i] : 0.0) - 1.0);
+        }
+        CHECK(chfsi_density(ops[k], Pfr[k], nfr[k], nfr[k], wfr.data(), CHFSI_RHO_NODES, 1, rout));
       }
-      // Algorithm 1's eigensolver step in the paper's form: the filter, then
-      // Rayleigh-Ritz through the generalised problem with spectrum
-      // splitting (Algorithm 2): X becomes the orthonormal basis Psi_o,
-      // Pfr the nfr highest Ritz vectors
-      CHECK(do_filter(op, Xv, N, ld, m, a, b, aL, xprec, prm.block));
-      CHECK(rrgep_split(op, static_cast<double*>(Xv), ld, N, nfr, rr_mode == 2, th.data(), Pfr, nfr));
-      CHECK(check_ritz(ctx, th.data(), nullptr, N, b));
-    }
-    // occupations and the output density
-    CHECK(chfsi_fermi_level(th.data(), nwanted, nullptr, n_electrons, kT, &mu, occ.data()));
-    for (int i = 0; i < nwanted; ++i) f[i] = 2.0 * occ[i];
-    if (!split) {
-      CHECK(chfsi_density(op, Xv, nwanted, ld, f.data(), CHFSI_RHO_NODES, 0, rout));
-    } else {
-      // Algorithm 3's split form: every basis vector counted fully occupied,
-      // then the nfr highest Ritz vectors corrected by 2 (f_i - 1) (buffer
-      // states: f_i = 0); exact when f_i = 1 below the split
-      std::vector<double> two(N, 2.0);
-      CHECK(chfsi_density(op, Xv, N, ld, two.data(), CHFSI_RHO_NODES, 0, rout));
-      wfr.assign(nfr, 0.0);
-      for (int j = 0; j < nfr; ++j) {
-        const int64_t i = N - nfr + j;
-        wfr[j] = 2.0 * ((i < nwanted ? occ[i] : 0.0) - 1.0);
+      if (rr_mode > 0) {
+        // next split: all states whose vacancy 1 - f exceeds 1e-14, plus two
+        int full = 0;
+        while (full < nwanted && 1.0 - ok[full] <= 1e-14) ++full;
+        nfr[k] = static_cast<int>(std::min<int64_t>(N, N - full + 2));
       }
-      CHECK(chfsi_density(op, Pfr, nfr, nfr, wfr.data(), CHFSI_RHO_NODES, 1, rout));
-    }
-    if (rr_mode > 0) {
-      // next split: all states whose vacancy 1 - f exceeds 1e-14, plus two
-      int full = 0;
-      while (full < nwanted && 1.0 - occ[full] <= 1e-14) ++full;
-      nfr = static_cast<int>(std::min<int64_t>(N, N - full + 2));
     }
     // residual F = rho_out - rho_in in the M-weighted norm
     HIP_TRY(ctx, launch_convert(F, 1, CHFSI_F64, rout, 1, CHFSI_F64, M, 1, st));
@@ -2183,10 +2211,41 @@ int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf
   }
   HIP_TRY(ctx, launch_convert(rho, 1, CHFSI_F64, conv ? rout : rin, 1, CHFSI_F64, M, 1, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
-  std::memcpy(theta, th.data(), N * 8);
+  for (int k = 0; k < nk; ++k) std::memcpy(thetas[k], th[k].data(), N * 8);
   if (mu_out) *mu_out = mu;
   if (iters) *iters = it;
   return conv ? 0 : CHFSI_NOTCONV;
+}
+
+int chfsi_scf(chfsi_op* op, void* Xv, int64_t ld, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
+              int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol, int32_t maxit,
+              double* rho, double* theta, double* mu_out, double* res_hist, int32_t* iters) {
+  if (!op) return CHFSI_EINVAL;
+  const double one = 1.0;
+  double* const thetas[1] = {theta};
+  return scf_loop(op->ctx, 1, &op, &Xv, &ld, &one, nwanted, n_buf, m, block, rr_mode, n_electrons, kT, beta, depth,
+                  tol, maxit, rho, thetas, mu_out, res_hist, iters);
+}
+
+int chfsi_scf_kpoints(chfsi_ctx* ctx, int32_t nk, chfsi_op* const* ops, void* const* X, const int64_t* ld,
+                      const double* weights, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
+                      int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol,
+                      int32_t maxit, double* rho, double* const* theta, double* mu_out, double* res_hist,
+                      int32_t* iters) {
+  if (!ctx) return CHFSI_EINVAL;
+  if (nk < 1 || !ops || !X || !ld || !theta) return fail(ctx, CHFSI_EINVAL, "null argument or nk < 1");
+  std::vector<double> w(nk, 1.0 / nk);
+  if (weights) {
+    double sum = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      if (!(weights[k] >= 0.0) || !std::isfinite(weights[k])) return fail(ctx, CHFSI_EINVAL, "bad k-point weight");
+      sum += weights[k];
+    }
+    if (!(sum > 0.0)) return fail(ctx, CHFSI_EINVAL, "k-point weights sum to zero");
+    for (int k = 0; k < nk; ++k) w[k] = weights[k] / sum;
+  }
+  return scf_loop(ctx, nk, ops, X, ld, w.data(), nwanted, n_buf, m, block, rr_mode, n_electrons, kT, beta, depth,
+                  tol, maxit, rho, theta, mu_out, res_hist, iters);
 }
 
 int chfsi_set_timing(chfsi_ctx* ctx, int32_t enable) {

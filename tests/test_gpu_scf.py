@@ -166,3 +166,53 @@ def test_scf_at_k_and_minus_k_agree(ctx, rr_mode):
     assert abs(a["mu"] - b["mu"]) < 1e-7
     # the Bloch phase acts: the upper (delocalised) states move with k
     assert np.max(np.abs(a["theta"] - g["theta"])) > 1e-3
+
+
+def test_scf_kpoints_pairs_and_single_point(ctx):
+    # chfsi_scf_kpoints with k and -k at equal weights reaches the one-k
+    # loop's fixed point (the two densities are equal by time reversal); a
+    # single Gamma point through it is chfsi_scf; four k-points of a 2 x 2 x 1
+    # shifted grid conserve the electron count and converge
+    L, seed = 6.0, 7
+    k = (0.35, -0.2, 0.1)
+
+    def op_at(kk):
+        return lib.Operator(ctx, workloads.small_system(2, 4, 2, seed=seed, L=L, k=kk))
+
+    def block(op, sd):
+        return dev(workloads.start_block(op.M, 12, seed=sd, complex_=op.is_complex))
+
+    m = fe.build_operator(workloads.small_system(2, 4, 2, seed=seed, L=L)).Mdiag
+    rho0 = np.full(m.size, 6.0 / np.sum(m))
+    kw = dict(nwanted=8, n_buf=4, n_electrons=6.0, kT=0.01, m=20, tol=1e-9, maxit=120)
+    # one k-point, the plain call
+    opk = op_at(k)
+    rho1 = dev(rho0)
+    one = opk.scf(block(opk, 8), rho1, **kw)
+    # k and -k
+    ops = [op_at(k), op_at(tuple(-x for x in k))]
+    rho2 = dev(rho0)
+    two = ctx.scf_kpoints(ops, [block(ops[0], 8), block(ops[1], 9)], rho2, weights=[0.5, 0.5], **kw)
+    assert one["converged"] and two["converged"]
+    r1, r2 = rho1.cpu().numpy(), rho2.cpu().numpy()
+    assert np.max(np.abs(r1 - r2)) <= 1e-7 * np.max(r1)
+    assert abs(one["mu"] - two["mu"]) < 1e-7
+    assert np.max(np.abs(two["theta"][0][:8] - two["theta"][1][:8])) < 1e-7
+    # Gamma through the k-point call equals chfsi_scf
+    # (bitwise, in the deterministic mode)
+    op0 = op_at((0.0, 0.0, 0.0))
+    rho3, rho4 = dev(rho0), dev(rho0)
+    ctx.set_deterministic(True)
+    a = op0.scf(block(op0, 8), rho3, **kw)
+    b = ctx.scf_kpoints([op0], [block(op0, 8)], rho4, **kw)
+    ctx.set_deterministic(False)
+    assert a["iters"] == b["iters"] and a["mu"] == b["mu"]
+    assert np.array_equal(rho3.cpu().numpy().view(np.uint64), rho4.cpu().numpy().view(np.uint64))
+    # a shifted 2 x 2 x 1 grid
+    g = 2.0 * np.pi / L
+    ks = [(g * (i + 0.5) / 2 - g / 2, g * (j + 0.5) / 2 - g / 2, 0.0) for i in range(2) for j in range(2)]
+    ops4 = [op_at(kk) for kk in ks]
+    rho5 = dev(rho0)
+    four = ctx.scf_kpoints(ops4, [block(o, 10 + i) for i, o in enumerate(ops4)], rho5, **kw)
+    assert four["converged"]
+    assert abs(float(np.sum(m * rho5.cpu().numpy())) - 6.0) < 1e-9
