@@ -457,8 +457,10 @@ int chfsi_scf(chfsi_op* op, void* X, int64_t ld, int32_t nwanted, int32_t n_buf,
  * potential, the mixing and the stopping rule are those of chfsi_scf, and
  * the eigensolver step (passes, spectrum splitting with its own split per
  * k-point) runs for each k-point in turn.  theta: nk host arrays of
- * nwanted + n_buf values.  chfsi_scf is this call with nk = 1.
- * Synchronous. */
+ * nwanted + n_buf values.  chfsi_scf is this call with nk = 1.  H(-k) is
+ * the complex conjugate of H(k) and has the same density, so a grid closed
+ * under k -> -k may be passed as one k-point of each pair with twice the
+ * weight.  Synchronous. */
 int chfsi_scf_kpoints(chfsi_ctx* ctx, int32_t nk, chfsi_op* const* ops, void* const* X, const int64_t* ld,
                       const double* weights, int32_t nwanted, int32_t n_buf, int32_t m, int32_t block,
                       int32_t rr_mode, double n_electrons, double kT, double beta, int32_t depth, double tol,
